@@ -1,0 +1,208 @@
+"""ORACLE -- test infrastructure, not product code.
+
+The FFT-free MOT-JVIE marched step by step exactly as Sec. 2.4 writes it:
+
+    Z_0 J_n = E_n - P_{n-1},      P_{n-1} = sum_{k=1}^{ell} Z_k J_{n-k}      (eq:MOTInversion, eq:PnMOT)
+
+with the elements of eq:Z, the excitation of eq:E and the FIR regularisation
+Z_k -> Z_k + delta_k I of Sec. 5.1.  Z_0 is assembled as a sparse matrix and factorised
+directly (scipy's sparse LU); the history sum is the direct triple sum of direct.c.
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use it.
+
+Units: h = 1, c dt = 1 (the configurations in workloads/ all use c dt = h).
+Vectors are stored per component: J[a][w][v][u]  (the paper's eq:CurrentVector
+interleaves the three components per voxel; the two orders hold the same numbers).
+"""
+from __future__ import annotations
+
+import ctypes
+from math import floor, sqrt
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import dptr, iptr, lib
+
+# (b, a) -> stored component of the symmetric 3x3 kernel: xx, yy, zz, xy, xz, yz
+COMP = ((0, 3, 4), (3, 1, 5), (4, 5, 2))
+
+
+def ell(U: int, V: int, W: int, h: float = 1.0, c_dt: float = 1.0) -> int:
+    """Number of non-zero lags beyond Z_0 (eq:Ell)."""
+    return int(floor(sqrt((U * h) ** 2 + (V * h) ** 2 + (W * h) ** 2) / c_dt)) + 2
+
+
+def tbasis(t_over_dt: float) -> float:
+    """Temporal basis T(t) = B(t/dt + 1): the causal quadratic B-spline with knots
+    -dt, 0, dt, 2 dt (reading of Sec. 2.3, which defers T to an earlier paper)."""
+    return lib().or_bspline(float(t_over_dt) + 1.0)
+
+
+def kernel_entry(k: int, D, ngl: int = 16, r: float = 1.0) -> np.ndarray:
+    out = np.zeros(6)
+    lib().or_kernel_entry(r, int(k), float(D[0]), float(D[1]), float(D[2]), int(ngl), dptr(out))
+    return out
+
+
+def kernel_table(U: int, V: int, W: int, kmax: int, ngl: int = 16, r: float = 1.0,
+                 skip_outside: bool = True) -> np.ndarray:
+    """K[k][6][2W-1][2V-1][2U-1] for k = 0..kmax (offset D at index D + (U-1, V-1, W-1))."""
+    K = np.zeros((kmax + 1, 6, 2 * W - 1, 2 * V - 1, 2 * U - 1))
+    lib().or_kernel_table(r, U, V, W, kmax, ngl, 1 if skip_outside else 0, dptr(K))
+    return K
+
+
+def chi_of(eps: np.ndarray) -> np.ndarray:
+    """chi_m = (eps_m - 1) / eps_m  (the contrast factor of eq:TDJVIE)."""
+    return (eps - 1.0) / eps
+
+
+def local_coefficients(eps: np.ndarray, fir: np.ndarray, kmax: int) -> np.ndarray:
+    """c_k(m) = T(k dt)/eps_m + delta_k for k = 0..kmax: the identity part of Z_k
+    (eq:Z tested at its own voxel, with 1 - chi = 1/eps) plus the FIR tap (Sec. 5.1)."""
+    c = np.zeros((kmax + 1,) + eps.shape)
+    for k in range(kmax + 1):
+        d = fir[k] if k < len(fir) else 0.0
+        c[k] = tbasis(k) / eps + d
+    return c
+
+
+def excitation(U, V, W, eps, wave, n: int, nquad: int = 8) -> np.ndarray:
+    """E_n(m) = chi_m (1/h^3) Int_{V_m} E^i(r, n dt) dV  (eq:E, test voxel m and step n),
+    the voxel average taken with an nquad^3 Gauss-Legendre rule."""
+    x, w = np.polynomial.legendre.leggauss(nquad)
+    x = 0.5 * x
+    w = 0.5 * w
+    wz, wy, wx = np.meshgrid(np.arange(W), np.arange(V), np.arange(U), indexing="ij")
+    k = np.asarray(wave.khat, float)
+    p = np.asarray(wave.pol, float)
+    rr = np.asarray(wave.r_ref, float)
+    # tau at the voxel centre, and the projections of the quadrature offsets on khat
+    tc = float(n) - wave.t0 - ((wx + 0.5 - rr[0]) * k[0] + (wy + 0.5 - rr[1]) * k[1] + (wz + 0.5 - rr[2]) * k[2])
+    avg = np.zeros(tc.shape)
+    for i in range(nquad):
+        for j in range(nquad):
+            for l in range(nquad):
+                s = x[i] * k[0] + x[j] * k[1] + x[l] * k[2]
+                avg += w[i] * w[j] * w[l] * np.exp(-((tc - s) / wave.width) ** 2)
+    avg *= wave.amp
+    chi = chi_of(eps)
+    return np.stack([chi * avg * p[0], chi * avg * p[1], chi * avg * p[2]])
+
+
+def conv(K: np.ndarray, Jh: np.ndarray, targets=None) -> np.ndarray:
+    """sum_{k=1}^{nlag} K_k (*) J_{n-k}: K[1..nlag] from a table K[0..], Jh[k-1] = J_{n-k}.
+    Returns [3][W][V][U], or [3][len(targets)] for a list of voxel indices."""
+    nlag = Jh.shape[0]
+    _, _, W, V, U = Jh.shape
+    Kl = np.ascontiguousarray(K[1:nlag + 1])
+    assert Kl.shape[0] == nlag
+    Jc = np.ascontiguousarray(Jh, dtype=np.float64)
+    if targets is None:
+        out = np.zeros((3, W, V, U))
+        lib().or_conv(U, V, W, nlag, dptr(Kl), dptr(Jc), None, 0, dptr(out))
+        return out
+    t = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    out = np.zeros((3, len(t)))
+    lib().or_conv(U, V, W, nlag, dptr(Kl), dptr(Jc), t.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                  len(t), dptr(out))
+    return out
+
+
+def conv_pairs(targets, sources, Js: np.ndarray, ngl: int = 16, r: float = 1.0) -> np.ndarray:
+    """sum_{k=1}^{nlag} sum_s K_k(r_t - r_s) J_{n-k}(s) for integer voxel coordinates
+    targets [nt][3], sources [ns][3] and source currents Js[k-1][3][ns] = J_{n-k};
+    every kernel value is computed on the spot.  Returns [3][nt]."""
+    t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    s = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+    J = np.ascontiguousarray(Js, dtype=np.float64)
+    out = np.zeros((3, len(t)))
+    lib().or_conv_pairs(r, J.shape[0], iptr(t), len(t), iptr(s), len(s), dptr(J), ngl, dptr(out))
+    return out
+
+
+def history_sum(K: np.ndarray, Jh: np.ndarray, eps: np.ndarray, fir: np.ndarray, ell_: int) -> np.ndarray:
+    """P_{n-1} = sum_{k>=1} Z^delta_k J_{n-k} (eq:PnMOT with Sec. 5.1's taps) for a history
+    Jh[k-1] = J_{n-k}, k = 1..depth (missing lags count as zero currents):
+      P = sum_k c_k J_{n-k} - chi * sum_{k=1}^{ell} K_k (*) J_{n-k}."""
+    depth = Jh.shape[0]
+    chi = chi_of(eps)
+    nl = min(ell_, depth)
+    P = -chi[None] * conv(K, Jh[:nl])
+    c = local_coefficients(eps, fir, depth)
+    for k in range(1, depth + 1):
+        P += c[k][None] * Jh[k - 1]
+    return P
+
+
+def z0_matrix(K0: np.ndarray, eps: np.ndarray, fir: np.ndarray) -> sp.csr_matrix:
+    """Z^delta_0 as a sparse 3M x 3M matrix in the per-component order (b*M + m):
+    rows  c_0(m) J^b(m) - chi_m sum_{m',a} K^{ba}_0(m - m') J^a(m')."""
+    W, V, U = eps.shape
+    M = U * V * W
+    chi = chi_of(eps).ravel()
+    c0 = local_coefficients(eps, fir, 0)[0].ravel()
+    rows, cols, vals = [], [], []
+    idx = np.arange(M).reshape(W, V, U)
+    nz, ny, nx = K0.shape[1:]
+    for dz in range(-(W - 1), W):
+        for dy in range(-(V - 1), V):
+            for dx in range(-(U - 1), U):
+                kv = K0[:, dz + W - 1, dy + V - 1, dx + U - 1]
+                if not np.any(kv):
+                    continue
+                # target m = source m' + D
+                zs = slice(max(0, -dz), W - max(0, dz)); zt = slice(max(0, dz), W - max(0, -dz))
+                ys = slice(max(0, -dy), V - max(0, dy)); yt = slice(max(0, dy), V - max(0, -dy))
+                xs = slice(max(0, -dx), U - max(0, dx)); xt = slice(max(0, dx), U - max(0, -dx))
+                src = idx[zs, ys, xs].ravel()
+                tgt = idx[zt, yt, xt].ravel()
+                for b in range(3):
+                    for a in range(3):
+                        v = kv[COMP[b][a]]
+                        if v == 0.0:
+                            continue
+                        rows.append(b * M + tgt)
+                        cols.append(a * M + src)
+                        vals.append(-chi[tgt] * v)
+    for b in range(3):
+        rows.append(b * M + np.arange(M))
+        cols.append(b * M + np.arange(M))
+        vals.append(c0)
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(3 * M, 3 * M))
+    A.sum_duplicates()
+    return A
+
+
+class Oracle:
+    """Direct MOT-JVIE march for one Problem (workloads.Problem) and one right-hand side."""
+
+    def __init__(self, prob, K=None, ngl: int = 16):
+        assert abs(prob.c_dt - prob.h) < 1e-14 * prob.h, "oracle assumes c dt = h"
+        self.p = prob
+        self.ell = ell(prob.U, prob.V, prob.W)
+        self.K = kernel_table(prob.U, prob.V, prob.W, self.ell, ngl) if K is None else K
+        self.fir = np.asarray(prob.fir, float)
+        self.depth = max(self.ell, len(self.fir) - 1, 1)
+        self.Z0 = z0_matrix(self.K[0], prob.eps, self.fir).tocsc()
+        self.lu = spla.splu(self.Z0)
+
+    def run(self, n_steps: int, rhs: int = 0, return_P: bool = False, excite=None):
+        """J_1..J_n for the Problem's plane wave `rhs`, or for excite(n) -> E_n [3][W][V][U]."""
+        p = self.p
+        W, V, U = p.W, p.V, p.U
+        J = np.zeros((n_steps + 1, 3, W, V, U))      # J[0] = 0 (J_{n'} = 0 for n' <= 0)
+        Ps = []
+        for n in range(1, n_steps + 1):
+            lo = max(0, n - self.depth)
+            Jh = J[lo:n][::-1]                       # Jh[k-1] = J_{n-k}
+            P = history_sum(self.K, np.ascontiguousarray(Jh), p.eps, self.fir, self.ell)
+            E = excite(n) if excite is not None else excitation(U, V, W, p.eps, p.waves[rhs], n)
+            b = (E - P).ravel()
+            J[n] = self.lu.solve(b).reshape(3, W, V, U)
+            if return_P:
+                Ps.append(P)
+        if return_P:
+            return J[1:], np.array(Ps)
+        return J[1:]

@@ -1,0 +1,183 @@
+"""Seeded synthetic inputs for the MOT-JVIE hot path.
+
+This module only builds inputs: voxel grids, relative-permittivity maps, plane-wave
+parameters, FIR taps, probe positions and random current histories.  It holds none of
+the method's arithmetic, and both the HIP library's tests and the CPU oracle take their
+inputs from here.
+
+Units: lengths in voxel edges (h = 1), times as c*t in the same unit, so c*dt = 1 in
+every configuration below.  Voxel (u, v, w) (0-based) has its centre at
+(u + 1/2, v + 1/2, w + 1/2) (Sec. 2.2) and index m = (w V + v) U + u.
+
+The configurations stand in for the paper's cube (eps_r = 12, Sec. 3.3 / 6.1) and
+sphere (Sec. 6.2) workloads; no public dataset is involved.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from math import comb, sqrt, pi
+
+import numpy as np
+
+
+@dataclass
+class PlaneWave:
+    """Gaussian plane wave  E^i(r,t) = amp * pol * exp(-((c t - c t0 - (r - r_ref).khat) / width)^2).
+
+    The paper's pulse (eq:GaussPlaneWave) is amp = 4 E0 / (sigma sqrt(pi)), width = sigma / 4;
+    a pulse with standard deviation s has width = sqrt(2) s.  r_ref is the corner of the
+    grid box that the wave front reaches first, so the pulse centre arrives there at t0.
+    """
+    khat: tuple
+    pol: tuple
+    width: float
+    t0: float
+    amp: float = 1.0
+    r_ref: tuple = (0.0, 0.0, 0.0)
+
+
+@dataclass
+class Problem:
+    name: str
+    U: int
+    V: int
+    W: int
+    eps: np.ndarray                 # [W][V][U] relative permittivity, >= 1
+    waves: list                     # list[PlaneWave], one per right-hand side
+    n_steps: int
+    fir: np.ndarray = field(default_factory=lambda: np.zeros(0))   # taps delta_0..delta_{L-1}
+    probes: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    h: float = 1.0
+    c_dt: float = 1.0
+
+    @property
+    def M(self) -> int:
+        return self.U * self.V * self.W
+
+
+def binomial_highpass(n_taps: int, delta: float) -> np.ndarray:
+    """Taps delta_k = delta (-1)^k C(n-1, k) / 2^(n-1): linear phase, sum (-1)^k delta_k = delta,
+    zero DC gain.  n_taps = 2, 3 give the paper's FIR2 and FIR3 (eq:FIR2, eq:FIR3)."""
+    n = n_taps - 1
+    return np.array([delta * (-1) ** k * comb(n, k) / 2.0 ** n for k in range(n_taps)])
+
+
+def _ref_corner(U, V, W, khat):
+    ext = (U, V, W)
+    return tuple(0.0 if khat[i] >= 0 else float(ext[i]) for i in range(3))
+
+
+def gaussian_wave(U, V, W, khat, pol, sigma_std, delay_in_sigmas=6.0, amp=1.0) -> PlaneWave:
+    khat = tuple(float(x) for x in khat)
+    pol = tuple(float(x) for x in pol)
+    return PlaneWave(khat=khat, pol=pol, width=sqrt(2.0) * sigma_std, t0=delay_in_sigmas * sigma_std,
+                     amp=amp, r_ref=_ref_corner(U, V, W, khat))
+
+
+def voxel_centres(U, V, W):
+    w, v, u = np.meshgrid(np.arange(W), np.arange(V), np.arange(U), indexing="ij")
+    return u + 0.5, v + 0.5, w + 0.5
+
+
+def fibonacci_sphere(n, radius, centre):
+    i = np.arange(n) + 0.5
+    phi = np.arccos(1.0 - 2.0 * i / n)
+    theta = pi * (1.0 + 5.0 ** 0.5) * i
+    pts = np.stack([np.cos(theta) * np.sin(phi), np.sin(theta) * np.sin(phi), np.cos(phi)], axis=1)
+    return radius * pts + np.asarray(centre, dtype=float)[None, :]
+
+
+def _box_mean3(a):
+    """3x3x3 box mean over in-grid neighbours (window truncated at the boundary)."""
+    s = np.zeros_like(a)
+    n = np.zeros_like(a)
+    W, V, U = a.shape
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                zs = slice(max(0, dz), W + min(0, dz)); zd = slice(max(0, -dz), W + min(0, -dz))
+                ys = slice(max(0, dy), V + min(0, dy)); yd = slice(max(0, -dy), V + min(0, -dy))
+                xs = slice(max(0, dx), U + min(0, dx)); xd = slice(max(0, -dx), U + min(0, -dx))
+                s[zd, yd, xd] += a[zs, ys, xs]
+                n[zd, yd, xd] += 1.0
+    return s / n
+
+
+def random_directions(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        g = rng.standard_normal(3)
+        k = g / np.linalg.norm(g)
+        g2 = rng.standard_normal(3)
+        p = g2 - np.dot(g2, k) * k
+        p = p / np.linalg.norm(p)
+        out.append((tuple(k), tuple(p)))
+    return out
+
+
+XPOL_PLUS_Z = ((0.0, 0.0, 1.0), (1.0, 0.0, 0.0))
+
+
+def homogeneous_cube(U=8, eps=4.0, n_steps=200, sigma=4.0, fir=None, name="cube") -> Problem:
+    k, p = XPOL_PLUS_Z
+    return Problem(name=name, U=U, V=U, W=U, eps=np.full((U, U, U), float(eps)),
+                   waves=[gaussian_wave(U, U, U, k, p, sigma)], n_steps=n_steps,
+                   fir=np.zeros(0) if fir is None else np.asarray(fir, float))
+
+
+def config(name: str) -> Problem:
+    """Named workloads (c dt = h = 1, FP64)."""
+    if name == "C1":
+        # 8^3 homogeneous cube eps_r = 4, x-pol +z Gaussian sigma = 4 dt, delay 6 sigma, 200 steps, no FIR
+        return homogeneous_cube(8, 4.0, 200, 4.0, None, "C1")
+    if name == "C2":
+        U = 32
+        x, y, z = voxel_centres(U, U, U)
+        c = U / 2.0
+        inside = (x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2 <= 15.0 ** 2
+        eps = np.where(inside, 12.0, 1.0)
+        k, p = XPOL_PLUS_Z
+        return Problem("C2", U, U, U, eps, [gaussian_wave(U, U, U, k, p, 4.0)], 1000,
+                       fir=binomial_highpass(17, 0.1),
+                       probes=fibonacci_sphere(32, 24.0, (c, c, c)))
+    if name == "C3":
+        U = 64
+        rng = np.random.default_rng(3)
+        raw = rng.uniform(2.0, 20.0, size=(U, U, U))
+        eps = _box_mean3(raw)
+        waves = [gaussian_wave(U, U, U, k, p, 6.0) for k, p in random_directions(16, 33)]
+        return Problem("C3", U, U, U, eps, waves, 1500, fir=binomial_highpass(17, 0.1))
+    if name == "C4":
+        U = 48
+        eps = np.full((U, U, U), 10.0)
+        rng = np.random.default_rng(4)
+        eps[16:32, 16:32, 16:32] = rng.uniform(1.0, 12.0, size=(16, 16, 16))
+        k, p = XPOL_PLUS_Z
+        c = U / 2.0
+        return Problem("C4", U, U, U, eps, [gaussian_wave(U, U, U, k, p, 4.0)], 800,
+                       fir=binomial_highpass(17, 0.1),
+                       probes=fibonacci_sphere(32, 48.0, (c, c, c)))
+    if name == "C5":
+        U = 104
+        eps = np.ones((U, U, U))
+        eps[2:102, 2:102, 2:102] = 12.0
+        k, p = XPOL_PLUS_Z
+        return Problem("C5", U, U, U, eps, [gaussian_wave(U, U, U, k, p, 8.0)], 2000,
+                       fir=binomial_highpass(17, max(0.1, 1e-7 * U ** 3)))
+    raise KeyError(name)
+
+
+def random_history(U, V, W, nlag, seed, mask=None):
+    """Seeded random current history [nlag][3][W][V][U] (standard normal), optionally
+    zeroed outside a voxel mask [W][V][U]."""
+    rng = np.random.default_rng(seed)
+    J = rng.standard_normal((nlag, 3, W, V, U))
+    if mask is not None:
+        J *= mask[None, None].astype(float)
+    return J
+
+
+def random_eps(U, V, W, seed, lo=1.0, hi=12.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(W, V, U))
