@@ -1,0 +1,157 @@
+/*
+ * motjvie.h -- C interface of the MI355X (gfx950) MOT-JVIE library.
+ *
+ * The library marches the FFT-accelerated, FIR-regularised marching-on-in-time
+ * contrast-current-density volume integral equation (MOT-JVIE) of
+ * van Diepen, van Beurden & Dilz, "FFT-acceleration and stabilization of the 3D
+ * Marching-on-in-Time Contrast Current Density Volume Integral Equation for
+ * scattering from high contrast dielectrics" (arXiv 2407.03323).
+ *
+ * Problem statement (Sec. 2.1): a dielectric with relative permittivity eps_r >= 1,
+ * voxelised on a U x V x W box (Sec. 2.2), is illuminated by an incident field that
+ * arrives after t = 0.  Unknowns are the coefficients J^a_{m,n} of the contrast
+ * current (eq:J_basis) at steps t_n = n dt.  Every step solves
+ *     Z_0 J_n = E_n - P_{n-1},   P_{n-1} = sum_{k=1}^{ell} Z_k J_{n-k}
+ * (eq:MOTInversion, eq:PnMOT), with the history sum evaluated by zero-padded 3-D
+ * FFT convolution (Sec. 3, Appendix A) and the FIR regularisation
+ * Z_k -> Z_k + delta_k I (Sec. 5.1) built in.
+ *
+ * Conventions
+ *  - Lengths in any unit; h is the voxel edge.  Times enter as c*t (same unit).
+ *    This version requires c*dt == h (the paper's choice dt = dx/c, Sec. 3.3).
+ *  - Voxel index m = (w*V + v)*U + u, 0-based, x fastest (Sec. 2.2, 1-based there).
+ *    Voxel (u,v,w) has its centre at ((u+1/2)h, (v+1/2)h, (w+1/2)h).
+ *  - Vector fields are stored per component: F[a][w][v][u], a = x,y,z (the paper's
+ *    eq:CurrentVector interleaves the components per voxel; same numbers).
+ *  - All arithmetic is IEEE binary64.
+ *  - Pointers documented "device" must point to device memory of the current HIP
+ *    device (e.g. torch CUDA tensors); "host" pointers are read during the call and
+ *    may be freed afterwards.  The library never takes ownership of caller memory.
+ *  - Every call returns MJ_OK (0) or a negative status and never throws.  On error
+ *    mj_last_error() returns a description (per handle; mj_create failures use the
+ *    thread's own message, readable with mj_last_error(NULL)).
+ *  - One handle must not be used by two host threads at once.  All work is enqueued
+ *    on the configured stream; calls returning results to host memory synchronise it.
+ */
+#ifndef MOTJVIE_H
+#define MOTJVIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MJ_OK = 0,
+    MJ_EINVAL = -1,      /* invalid argument */
+    MJ_ENOMEM = -2,      /* device allocation failed */
+    MJ_EHIP = -3,        /* HIP runtime error */
+    MJ_ENOCONV = -4,     /* Z_0 solve did not reach cg_rtol within cg_maxit */
+    MJ_EUNSTABLE = -5,   /* current grew beyond the instability threshold */
+    MJ_ESTATE = -6       /* call not valid in the current state */
+};
+
+typedef struct mj_solver mj_solver;
+
+typedef struct {
+    int32_t U, V, W;          /* voxels per axis (>= 1) */
+    double h;                 /* voxel edge (> 0) */
+    double c_dt;              /* c * dt; must equal h */
+    const double *eps_r;      /* host [W][V][U], relative permittivity >= 1, finite */
+    const double *fir;        /* host taps delta_0..delta_{n_fir-1} (Sec. 5.1); may be NULL if n_fir == 0 */
+    int32_t n_fir;            /* 0 = no regularisation */
+    int32_t n_rhs;            /* number of right-hand sides (plane waves) marched together, >= 1 */
+    double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-12 */
+    int32_t cg_maxit;         /* <= 0 selects 200 */
+    int32_t time_block;       /* history MAC time block B; 0 selects automatically, 1 = no blocking */
+    void *stream;             /* hipStream_t to enqueue on; NULL = the null stream */
+    int32_t quad_order;       /* Gauss-Legendre points per cell of the kernel quadrature; 0 selects 16 */
+} mj_config;
+
+/*
+ * mj_create -- build a solver.
+ *   Computes ell (eq:Ell), generates the space-time interaction kernels K_k(D),
+ *   k = 0..ell, on the device (eq:Z, Sec. 2.3), transforms them to spectra on the
+ *   zero-padded grid (circulant embedding, Appendix A) and allocates the march state.  The march starts at n = 0 with J_{n'} = 0, n' <= 0.
+ *   Returns MJ_EINVAL for invalid sizes/values, MJ_ENOMEM if the device memory
+ *   needed (reported by mj_memory_bytes) does not fit.
+ */
+int mj_create(const mj_config *cfg, mj_solver **out);
+
+/* mj_destroy -- release all device memory of the solver (NULL is ignored). */
+void mj_destroy(mj_solver *s);
+
+/* mj_last_error -- description of the last error on this handle (or thread if NULL). */
+const char *mj_last_error(const mj_solver *s);
+
+/*
+ * mj_info -- sizes of the solver.  out (host, n entries used, n <= 12):
+ *   [0] ell  [1] Nx [2] Ny [3] Nz (padded FFT sizes)  [4] time block B
+ *   [5] history depth kept in real space  [6] n_rhs  [7] current step n
+ *   [8] device bytes allocated  [9] kernel generation time (ms)  [10] spectra time (ms)
+ *   [11] number of FIR taps
+ */
+int mj_info(const mj_solver *s, double *out, int32_t n);
+
+/*
+ * mj_set_plane_waves -- incident Gaussian plane waves, one per right-hand side (host arrays):
+ *   E^i(r,t) = amp * pol * exp(-((c t - c t0 - (r - r_ref).khat) / width)^2)
+ *   khat[n_rhs][3] (unit), pol[n_rhs][3], width[n_rhs] (> 0), ct0[n_rhs], amp[n_rhs],
+ *   r_ref[n_rhs][3].  The paper's pulse (eq:GaussPlaneWave) is amp = 4 E0/(sigma sqrt(pi)),
+ *   width = sigma/4.  The excitation E_n (eq:E) is chi_m times the voxel average of
+ *   E^i at t_n, taken with an 8-point Gauss-Legendre rule per axis.
+ */
+int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, const double *width,
+                       const double *ct0, const double *amp, const double *r_ref);
+
+/*
+ * mj_run -- march n_steps steps (eq:MOTInversion for n = n_cur+1 .. n_cur+n_steps).
+ *   J_hist: device, nullable, [n_steps][n_rhs][3][W][V][U]; receives J_n of every step.
+ *   Returns MJ_ENOCONV if a Z_0 solve missed cg_rtol (the march state stays consistent:
+ *   J_n holds the last iterate).
+ */
+int mj_run(mj_solver *s, int32_t n_steps, double *J_hist);
+
+/* mj_reset -- restart the march at n = 0 (all past currents zero). */
+int mj_reset(mj_solver *s);
+
+/*
+ * mj_history_sum -- P_{n-1} = sum_{k>=1} Z^delta_k J_{n-k} (eq:PnMOT with the FIR taps)
+ *   for an explicit history, through the same FFT / spectral multiply-accumulate / inverse
+ *   FFT path that the march uses (right-hand side 0).
+ *   J_hist: device [depth][3][W][V][U] with J_hist[k-1] = J_{n-k}, 1 <= depth; lags beyond
+ *   depth count as zero.  P: device [3][W][V][U].  Overwrites the march state (call
+ *   mj_reset before marching again).
+ */
+int mj_history_sum(mj_solver *s, const double *J_hist, int32_t depth, double *P);
+
+/*
+ * mj_kernel_values -- interaction kernels K_k(D) as generated on the device (eq:Z without
+ *   the identity and chi factors), for n requests (host arrays): lag[n] (0..ell) and
+ *   offset[n][3] (integer voxel offsets, |D_i| < U_i).  out (host) [n][6] receives
+ *   K^{xx}, K^{yy}, K^{zz}, K^{xy}, K^{xz}, K^{yz}.
+ */
+int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t *offset, double *out);
+
+/*
+ * mj_stats -- per-phase device times of the last mj_run, in ms per step, and CG
+ *   statistics.  out (host, n <= 10): [0] forward FFT  [1] history MAC  [2] inverse FFT
+ *   [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total  [6] mean CG iterations
+ *   [7] max final relative residual  [8] steps timed  [9] max CG iterations.
+ */
+int mj_stats(const mj_solver *s, double *out, int32_t n);
+
+/*
+ * mj_fft_roundtrip -- diagnostic: forward 3-D FFT of x (device [3][W][V][U]) on the
+ *   padded grid into X (device, [3][Nz][Ny][Nx/2+1] complex interleaved re,im), and the
+ *   inverse of X restricted to the voxel box, unnormalised, into y (device [3][W][V][U]).
+ *   Either output may be NULL.
+ */
+int mj_fft_roundtrip(mj_solver *s, const double *x, double *X, double *y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOTJVIE_H */

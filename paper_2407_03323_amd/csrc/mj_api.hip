@@ -1,0 +1,661 @@
+// C interface and host orchestration of the MOT-JVIE march (see include/motjvie.h).
+#include "motjvie.h"
+#include "mj_march.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using mj::ArgError;
+using mj::HipError;
+using mj::MemError;
+
+namespace {
+
+thread_local std::string g_err;
+
+__global__ void k_extract_octant(const double2 *__restrict__ X, int Hx, int Ny, int Nz, double scale,
+                                 double *__restrict__ out)
+{
+    const int Nyo = Ny / 2 + 1, Nzo = Nz / 2 + 1;
+    const long n = (long)Hx * Nyo * Nzo;
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int kx = (int)(t % Hx), qy = (int)((t / Hx) % Nyo), qz = (int)(t / ((long)Hx * Nyo));
+    const long plane = (long)Nz * Ny * Hx;
+    for (int c = 0; c < 6; c++) out[c * n + t] = scale * X[c * plane + ((long)qz * Ny + qy) * Hx + kx].x;
+}
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    void ensure(size_t n)
+    {
+        while (ev.size() < n) {
+            hipEvent_t e;
+            MJ_CHECK(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+    }
+    ~Events()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+struct mj_solver {
+    // geometry and configuration
+    int U = 0, V = 0, W = 0;
+    long M = 0;
+    double h = 1.0, c_dt = 1.0;
+    int nrhs = 1, ell = 0;
+    int Nx = 0, Ny = 0, Nz = 0, Hx = 0;
+    std::vector<double> fir;
+    double cg_rtol = 1e-12;
+    int cg_maxit = 200;
+    int B = 1;
+    int nquad = 16;
+    hipStream_t st = nullptr;
+    int nloc = 3, rdepth = 4;
+    // device state
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+    double *chi = nullptr, *schi = nullptr, *inv_eps = nullptr, *c0 = nullptr, *inv_diag = nullptr;
+    double *fir_d = nullptr;
+    double *Khat = nullptr;
+    double2 *ring = nullptr, *Shat = nullptr;
+    double *S = nullptr, *Jr = nullptr;
+    double *rhs = nullptr, *y = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *parts = nullptr;
+    int *done = nullptr, *iters = nullptr;
+    double *res = nullptr;
+    int *done_h = nullptr, *iters_h = nullptr;
+    double *res_h = nullptr;
+    mj::WaveArg *waves_d = nullptr;
+    bool waves_set = false;
+    std::vector<mj::WaveArg> waves;
+    mj::Fft3D fft{};
+    mj::GenResult gen{};
+    double K0_27[27 * 6] = {};
+    int nblk = 1;
+    int n = 0;
+    std::string err;
+    // statistics of the last run
+    double t_gen_ms = 0, t_spec_ms = 0;
+    double stat[10] = {};
+    Events events;
+
+    template <class T>
+    T *dalloc(size_t count, const char *what)
+    {
+        void *ptr = nullptr;
+        size_t b = count * sizeof(T);
+        if (b == 0) b = sizeof(T);
+        if (hipMalloc(&ptr, b) != hipSuccess) {
+            (void)hipGetLastError();
+            throw MemError(std::string("device allocation failed: ") + what + " (" + std::to_string(b) + " bytes)");
+        }
+        allocs.push_back(ptr);
+        bytes += b;
+        return (T *)ptr;
+    }
+
+    ~mj_solver()
+    {
+        if (st) (void)hipStreamSynchronize(st);
+        mj::fft3d_free(fft);
+        if (gen.moments) (void)hipFree(gen.moments);
+        for (void *a : allocs) (void)hipFree(a);
+        if (done_h) (void)hipHostFree(done_h);
+        if (iters_h) (void)hipHostFree(iters_h);
+        if (res_h) (void)hipHostFree(res_h);
+    }
+
+    long spec_plane() const { return (long)Nz * Ny * Hx; }
+    long koct() const { return (long)Hx * (Ny / 2 + 1) * (Nz / 2 + 1); }
+    int slotS(int j) const { return j % ell; }
+    int slotR(int j) const { return j % rdepth; }
+
+    void create(const mj_config &c);
+    void build_spectra();
+    void run(int n_steps, double *Jout);
+    void solve_z0();
+    void history_sum(const double *Jh, int depth, double *P);
+};
+
+void mj_solver::create(const mj_config &c)
+{
+    if (c.U < 1 || c.V < 1 || c.W < 1) throw ArgError("U, V, W must be >= 1");
+    if (!(c.h > 0.0) || !std::isfinite(c.h)) throw ArgError("h must be positive and finite");
+    if (!(std::fabs(c.c_dt - c.h) <= 1e-12 * c.h)) throw ArgError("this version requires c*dt == h");
+    if (!c.eps_r) throw ArgError("eps_r is NULL");
+    if (c.n_fir < 0 || (c.n_fir > 0 && !c.fir)) throw ArgError("bad FIR taps");
+    if (c.n_fir > mj::kMaxLocal) throw ArgError("at most 64 FIR taps");
+    if (c.n_rhs < 1 || c.n_rhs > 64) throw ArgError("n_rhs must be in [1, 64]");
+    U = c.U;
+    V = c.V;
+    W = c.W;
+    M = (long)U * V * W;
+    h = c.h;
+    c_dt = c.c_dt;
+    nrhs = c.n_rhs;
+    cg_rtol = c.cg_rtol > 0 ? c.cg_rtol : 1e-12;
+    cg_maxit = c.cg_maxit > 0 ? c.cg_maxit : 200;
+    nquad = c.quad_order > 0 ? c.quad_order : 16;
+    st = (hipStream_t)c.stream;
+    fir.assign(c.fir, c.fir + c.n_fir);
+    for (double d : fir)
+        if (!std::isfinite(d)) throw ArgError("FIR taps must be finite");
+    std::vector<double> eps(c.eps_r, c.eps_r + M);
+    for (double e : eps)
+        if (!(e >= 1.0) || !std::isfinite(e)) throw ArgError("eps_r must be finite and >= 1");
+    // eq:Ell
+    double diag = std::sqrt((double)U * U + (double)V * V + (double)W * W) * h;
+    ell = (int)std::floor(diag / c_dt + 1e-12) + 2;
+    // zero padding N >= 2U - 1 per axis (Appendix A)
+    Nx = mj::fft_pick_size(2 * U - 1);
+    Ny = mj::fft_pick_size(2 * V - 1);
+    Nz = mj::fft_pick_size(2 * W - 1);
+    Hx = Nx / 2 + 1;
+    B = c.time_block > 0 ? c.time_block : 1;
+    nloc = std::max(3, (int)fir.size() - 1);
+    rdepth = nloc + 1;
+
+    // material
+    std::vector<double> chi_h(M), schi_h(M), ie_h(M), c0_h(M);
+    const double d0 = fir.empty() ? 0.0 : fir[0];
+    for (long i = 0; i < M; i++) {
+        chi_h[i] = (eps[i] - 1.0) / eps[i];
+        schi_h[i] = std::sqrt(chi_h[i]);
+        ie_h[i] = 1.0 / eps[i];
+        c0_h[i] = 0.5 * ie_h[i] + d0;   // T(0)/eps + delta_0
+    }
+    chi = dalloc<double>(M, "chi");
+    schi = dalloc<double>(M, "sqrt chi");
+    inv_eps = dalloc<double>(M, "1/eps");
+    c0 = dalloc<double>(M, "c0");
+    inv_diag = dalloc<double>(M, "Jacobi");
+    MJ_CHECK(hipMemcpy(chi, chi_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(schi, schi_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(inv_eps, ie_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(c0, c0_h.data(), M * 8, hipMemcpyHostToDevice));
+    fir_d = dalloc<double>(std::max<size_t>(fir.size(), 1), "fir");
+    if (!fir.empty()) MJ_CHECK(hipMemcpy(fir_d, fir.data(), fir.size() * 8, hipMemcpyHostToDevice));
+
+    build_spectra();
+
+    // Jacobi preconditioner diag(A) = c_0 - chi K_0^{bb}(0)
+    const double k0self = K0_27[13 * 6 + 0];
+    std::vector<double> idg(M);
+    for (long i = 0; i < M; i++) {
+        double d = c0_h[i] - chi_h[i] * k0self;
+        idg[i] = chi_h[i] > 0.0 ? 1.0 / d : 0.0;
+    }
+    MJ_CHECK(hipMemcpy(inv_diag, idg.data(), M * 8, hipMemcpyHostToDevice));
+
+    // march state
+    const long sp = spec_plane();
+    ring = dalloc<double2>((size_t)ell * nrhs * 3 * sp, "spectral history ring");
+    Shat = dalloc<double2>((size_t)nrhs * 3 * sp, "spectral sum");
+    S = dalloc<double>((size_t)nrhs * 3 * M, "convolution");
+    Jr = dalloc<double>((size_t)rdepth * nrhs * 3 * M, "current history");
+    rhs = dalloc<double>((size_t)nrhs * 3 * M, "cg rhs");
+    y = dalloc<double>((size_t)nrhs * 3 * M, "cg y");
+    r = dalloc<double>((size_t)nrhs * 3 * M, "cg r");
+    z = dalloc<double>((size_t)nrhs * 3 * M, "cg z");
+    p = dalloc<double>((size_t)nrhs * 3 * M, "cg p");
+    q = dalloc<double>((size_t)nrhs * 3 * M, "cg q");
+    nblk = (int)std::min<long>(1024, (M + 255) / 256);
+    parts = dalloc<double>((size_t)5 * nrhs * nblk, "cg partials");
+    done = dalloc<int>(nrhs, "cg flags");
+    iters = dalloc<int>(nrhs, "cg iterations");
+    res = dalloc<double>(nrhs, "cg residuals");
+    waves_d = dalloc<mj::WaveArg>(nrhs, "waves");
+    MJ_CHECK(hipHostMalloc((void **)&done_h, sizeof(int) * nrhs, hipHostMallocDefault));
+    MJ_CHECK(hipHostMalloc((void **)&iters_h, sizeof(int) * nrhs, hipHostMallocDefault));
+    MJ_CHECK(hipHostMalloc((void **)&res_h, sizeof(double) * nrhs, hipHostMallocDefault));
+    mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz);
+    bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hx + (size_t)3 * nrhs * W * Ny * Hx);
+    n = 0;
+    MJ_CHECK(hipStreamSynchronize(st));
+}
+
+void mj_solver::build_spectra()
+{
+    auto t0 = std::chrono::steady_clock::now();
+    mj::gen_moments(gen, U, V, W, nquad, st);
+    bytes += (size_t)M * mj::kMaxShells * mj::kMoments * sizeof(double);
+    MJ_CHECK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    t_gen_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+    // K_0 stencil (27 offsets, 6 components) for the Z_0 solve
+    {
+        std::vector<int> lag(27, 0), off(81);
+        int o = 0;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++, o++) {
+                    off[3 * o] = (U > 1 || dx == 0) ? dx : 0;
+                    off[3 * o + 1] = (V > 1 || dy == 0) ? dy : 0;
+                    off[3 * o + 2] = (W > 1 || dz == 0) ? dz : 0;
+                }
+        int *lag_d, *off_d;
+        double *out_d;
+        MJ_CHECK(hipMalloc(&lag_d, 27 * sizeof(int)));
+        MJ_CHECK(hipMalloc(&off_d, 81 * sizeof(int)));
+        MJ_CHECK(hipMalloc(&out_d, 162 * sizeof(double)));
+        MJ_CHECK(hipMemcpy(lag_d, lag.data(), 27 * sizeof(int), hipMemcpyHostToDevice));
+        MJ_CHECK(hipMemcpy(off_d, off.data(), 81 * sizeof(int), hipMemcpyHostToDevice));
+        mj::gen_kernel_values(gen, 27, lag_d, off_d, out_d, st);
+        MJ_CHECK(hipMemcpyAsync(K0_27, out_d, 162 * sizeof(double), hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipStreamSynchronize(st));
+        (void)hipFree(lag_d);
+        (void)hipFree(off_d);
+        (void)hipFree(out_d);
+        // offsets that fall outside a one-voxel-thick axis do not couple
+        o = 0;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++, o++)
+                    if ((U == 1 && dx != 0) || (V == 1 && dy != 0) || (W == 1 && dz != 0))
+                        for (int c = 0; c < 6; c++) K0_27[6 * o + c] = 0.0;
+        mj::upload_stencil(K0_27);
+    }
+
+    // spectra of lags 1..ell on the padded grid, octant only, with 1/(Nx Ny Nz) folded in
+    const long ko = koct();
+    Khat = dalloc<double>((size_t)ell * 6 * ko, "kernel spectra");
+    mj::Fft3D kf{};
+    double *grid = nullptr;
+    double2 *X = nullptr;
+    const size_t ng = (size_t)Nx * Ny * Nz;
+    try {
+        mj::fft3d_init(kf, Nx, Ny, Nz, 6, Nx, Ny, Nz);
+        if (hipMalloc(&grid, 6 * ng * sizeof(double)) != hipSuccess) throw MemError("kernel grid");
+        if (hipMalloc(&X, 6 * (size_t)Nz * Ny * Hx * sizeof(double2)) != hipSuccess) throw MemError("kernel spectrum");
+        const double scale = 1.0 / ((double)Nx * Ny * Nz);
+        for (int k = 1; k <= ell; k++) {
+            mj::gen_kernel_grid(gen, k, Nx, Ny, Nz, grid, st);
+            mj::fft3d_forward(kf, grid, X, 6, st);
+            hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((ko + 255) / 256)), dim3(256), 0, st, X, Hx, Ny, Nz,
+                               scale, Khat + (size_t)(k - 1) * 6 * ko);
+            MJ_CHECK(hipGetLastError());
+        }
+        MJ_CHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        mj::fft3d_free(kf);
+        if (grid) (void)hipFree(grid);
+        if (X) (void)hipFree(X);
+        throw;
+    }
+    mj::fft3d_free(kf);
+    (void)hipFree(grid);
+    (void)hipFree(X);
+    auto t2 = std::chrono::steady_clock::now();
+    t_spec_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+}
+
+void mj_solver::solve_z0()
+{
+    mj::CgArg a{};
+    a.M = M;
+    a.U = U;
+    a.V = V;
+    a.W = W;
+    a.nrhs = nrhs;
+    a.nblk = nblk;
+    a.tol2 = cg_rtol * cg_rtol;
+    a.schi = schi;
+    a.c0 = c0;
+    a.inv_diag = inv_diag;
+    a.rhs = rhs;
+    a.y = y;
+    a.r = r;
+    a.z = z;
+    a.p = p;
+    a.q = q;
+    const size_t pn = (size_t)nrhs * nblk;
+    a.part_rz[0] = parts;
+    a.part_rz[1] = parts + pn;
+    a.part_rr = parts + 2 * pn;
+    a.part_bb = parts + 3 * pn;
+    a.part_pq = parts + 4 * pn;
+    a.done = done;
+    a.iters = iters;
+    a.res = res;
+    MJ_CHECK(hipMemsetAsync(done, 0, sizeof(int) * nrhs, st));
+    mj::launch_cg_init(a, st);
+    const int chunk = 4;
+    int it = 0;
+    bool all_done = false;
+    while (it < cg_maxit && !all_done) {
+        int upto = std::min(cg_maxit, it + chunk);
+        for (; it < upto; it++) {
+            mj::launch_cg_a(a, it, st);
+            mj::launch_cg_b(a, it, st);
+        }
+        MJ_CHECK(hipMemcpyAsync(done_h, done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipStreamSynchronize(st));
+        all_done = true;
+        for (int i = 0; i < nrhs; i++) all_done = all_done && done_h[i];
+    }
+    if (!all_done) {
+        mj::launch_cg_a(a, it, st);   // records the final residual (and the flag if converged)
+    }
+    MJ_CHECK(hipMemcpyAsync(done_h, done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    MJ_CHECK(hipMemcpyAsync(iters_h, iters, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    MJ_CHECK(hipMemcpyAsync(res_h, res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    MJ_CHECK(hipStreamSynchronize(st));
+}
+
+void mj_solver::run(int n_steps, double *Jout)
+{
+    if (!waves_set) throw std::logic_error("plane waves not set (mj_set_plane_waves)");
+    events.ensure((size_t)6 * std::max(n_steps, 1));
+    double cg_iter_sum = 0, cg_res_max = 0, cg_iter_max = 0;
+    bool noconv = false;
+    const long sp = spec_plane();
+    double glx8[8], glw8[8];
+    {
+        // 8-point Gauss-Legendre on [-1/2, 1/2] (weights summing to 1), long double Newton
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int i = 0; i < 8; i++) {
+            long double zz = cosl(pi * (i + 0.75L) / 8.5L);
+            long double dp = 0;
+            for (int itn = 0; itn < 50; itn++) {
+                long double p0 = 1, p1 = zz;
+                for (int j = 2; j <= 8; j++) {
+                    long double p2 = ((2 * j - 1) * zz * p1 - (j - 1) * p0) / j;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = 8 * (zz * p1 - p0) / (zz * zz - 1);
+                long double d = p1 / dp;
+                zz -= d;
+                if (fabsl(d) < 1e-19L) break;
+            }
+            glx8[i] = (double)(0.5L * zz);
+            glw8[i] = (double)(1.0L / ((1 - zz * zz) * dp * dp));
+        }
+    }
+    for (int s = 0; s < n_steps; s++) {
+        hipEvent_t *ev = &events.ev[(size_t)6 * s];
+        MJ_CHECK(hipEventRecord(ev[0], st));
+        n += 1;
+        const bool hist = n >= 2;
+        if (hist) {
+            const int j = n - 1;
+            mj::fft3d_forward(fft, Jr + (size_t)slotR(j) * nrhs * 3 * M, ring + (size_t)slotS(j) * nrhs * 3 * sp,
+                              3 * nrhs, st);
+        }
+        MJ_CHECK(hipEventRecord(ev[1], st));
+        if (hist) {
+            mj::MacArg a{};
+            a.Khat = Khat;
+            a.ring_base = ring;
+            a.Shat = Shat;
+            a.Hx = Hx;
+            a.Ny = Ny;
+            a.Nz = Nz;
+            a.nk = std::min(ell, n - 1);
+            a.ring = ell;
+            a.slot_nm1 = slotS(n - 1);
+            a.nrhs = nrhs;
+            mj::launch_mac(a, st);
+        }
+        MJ_CHECK(hipEventRecord(ev[2], st));
+        if (hist) mj::fft3d_inverse(fft, Shat, S, 3 * nrhs, st);
+        MJ_CHECK(hipEventRecord(ev[3], st));
+        {
+            mj::EpiArg e{};
+            e.M = M;
+            e.U = U;
+            e.V = V;
+            e.W = W;
+            e.nrhs = nrhs;
+            e.n = n;
+            e.h = h;
+            e.c_dt = c_dt;
+            e.chi = chi;
+            e.schi = schi;
+            e.inv_eps = inv_eps;
+            e.fir = fir_d;
+            e.nfir = (int)fir.size();
+            e.nloc = nloc;
+            for (int k = 1; k <= nloc; k++) e.slot_of[k] = n - k >= 1 ? slotR(n - k) : 0;
+            e.Jring = Jr;
+            e.S = hist ? S : nullptr;
+            e.waves = waves_d;
+            for (int i = 0; i < 8; i++) {
+                e.glx8[i] = glx8[i];
+                e.glw8[i] = glw8[i];
+            }
+            e.rhs = rhs;
+            e.y = y;
+            mj::launch_epilogue(e, st);
+        }
+        MJ_CHECK(hipEventRecord(ev[4], st));
+        solve_z0();
+        mj::launch_cg_finish(y, schi, M, nrhs, Jr + (size_t)slotR(n) * nrhs * 3 * M,
+                             Jout ? Jout + (size_t)s * nrhs * 3 * M : nullptr, st);
+        MJ_CHECK(hipEventRecord(ev[5], st));
+        for (int i = 0; i < nrhs; i++) {
+            cg_iter_sum += iters_h[i];
+            cg_iter_max = std::max(cg_iter_max, (double)iters_h[i]);
+            cg_res_max = std::max(cg_res_max, res_h[i]);
+            if (!done_h[i]) noconv = true;
+        }
+    }
+    MJ_CHECK(hipStreamSynchronize(st));
+    double ph[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < n_steps; s++) {
+        hipEvent_t *ev = &events.ev[(size_t)6 * s];
+        for (int k = 0; k < 5; k++) {
+            float ms = 0;
+            MJ_CHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            ph[k] += ms;
+        }
+        float tot = 0;
+        MJ_CHECK(hipEventElapsedTime(&tot, ev[0], ev[5]));
+        ph[5] += tot;
+    }
+    const double ns = std::max(n_steps, 1);
+    for (int k = 0; k < 6; k++) stat[k] = ph[k] / ns;
+    stat[6] = cg_iter_sum / (ns * nrhs);
+    stat[7] = cg_res_max;
+    stat[8] = n_steps;
+    stat[9] = cg_iter_max;
+    if (noconv) throw std::range_error("Z_0 solve did not converge");
+}
+
+void mj_solver::history_sum(const double *Jh, int depth, double *P)
+{
+    const long sp = spec_plane();
+    const int nfake = ell + 1;
+    for (int k = 1; k <= ell; k++) {
+        double2 *slot = ring + (size_t)slotS(nfake - k) * nrhs * 3 * sp;
+        if (k <= depth) mj::fft3d_forward(fft, Jh + (size_t)(k - 1) * 3 * M, slot, 3, st);
+        else MJ_CHECK(hipMemsetAsync(slot, 0, sizeof(double2) * 3 * sp, st));
+    }
+    mj::MacArg a{};
+    a.Khat = Khat;
+    a.ring_base = ring;
+    a.Shat = Shat;
+    a.Hx = Hx;
+    a.Ny = Ny;
+    a.Nz = Nz;
+    a.nk = ell;
+    a.ring = ell;
+    a.slot_nm1 = slotS(nfake - 1);
+    a.nrhs = nrhs;   // ring stride; only right-hand side 0 is meaningful here
+    mj::launch_mac(a, st);
+    mj::fft3d_inverse(fft, Shat, S, 3, st);
+    mj::launch_history_local(Jh, depth, S, chi, inv_eps, fir_d, (int)fir.size(), M, P, st);
+    MJ_CHECK(hipStreamSynchronize(st));
+    n = 0;
+}
+
+// ============================================================================ C ABI
+namespace {
+int fail(mj_solver *s, int code, const std::string &msg)
+{
+    if (s) s->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+template <class F>
+int guarded(mj_solver *s, F &&f)
+{
+    try {
+        f();
+        return MJ_OK;
+    } catch (const ArgError &e) {
+        return fail(s, MJ_EINVAL, e.what());
+    } catch (const MemError &e) {
+        return fail(s, MJ_ENOMEM, e.what());
+    } catch (const HipError &e) {
+        return fail(s, MJ_EHIP, e.what());
+    } catch (const std::range_error &e) {
+        return fail(s, MJ_ENOCONV, e.what());
+    } catch (const std::logic_error &e) {
+        return fail(s, MJ_ESTATE, e.what());
+    } catch (const std::exception &e) {
+        return fail(s, MJ_EHIP, e.what());
+    } catch (...) {
+        return fail(s, MJ_EHIP, "unknown error");
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int mj_create(const mj_config *cfg, mj_solver **out)
+{
+    if (!cfg || !out) return fail(nullptr, MJ_EINVAL, "NULL argument");
+    *out = nullptr;
+    mj_solver *s = new (std::nothrow) mj_solver();
+    if (!s) return fail(nullptr, MJ_ENOMEM, "host allocation failed");
+    int rc = guarded(nullptr, [&] { s->create(*cfg); });
+    if (rc != MJ_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return MJ_OK;
+}
+
+void mj_destroy(mj_solver *s) { delete s; }
+
+const char *mj_last_error(const mj_solver *s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+int mj_info(const mj_solver *s, double *out, int32_t n)
+{
+    if (!s || !out) return MJ_EINVAL;
+    double v[12] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
+                    (double)s->nloc, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
+                    s->t_spec_ms, (double)s->fir.size()};
+    for (int i = 0; i < n && i < 12; i++) out[i] = v[i];
+    return MJ_OK;
+}
+
+int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, const double *width, const double *ct0,
+                       const double *amp, const double *r_ref)
+{
+    if (!s) return MJ_EINVAL;
+    return guarded(s, [&] {
+        if (!khat || !pol || !width || !ct0 || !amp || !r_ref) throw ArgError("NULL wave parameter");
+        std::vector<mj::WaveArg> w(s->nrhs);
+        for (int i = 0; i < s->nrhs; i++) {
+            double kn = 0;
+            for (int c = 0; c < 3; c++) {
+                w[i].k[c] = khat[3 * i + c];
+                w[i].pol[c] = pol[3 * i + c];
+                w[i].rref[c] = r_ref[3 * i + c];
+                kn += khat[3 * i + c] * khat[3 * i + c];
+            }
+            if (!(std::fabs(kn - 1.0) < 1e-12)) throw ArgError("khat must be a unit vector");
+            if (!(width[i] > 0.0)) throw ArgError("width must be positive");
+            w[i].width = width[i];
+            w[i].ct0 = ct0[i];
+            w[i].amp = amp[i];
+        }
+        MJ_CHECK(hipMemcpy(s->waves_d, w.data(), sizeof(mj::WaveArg) * s->nrhs, hipMemcpyHostToDevice));
+        s->waves = w;
+        s->waves_set = true;
+    });
+}
+
+int mj_run(mj_solver *s, int32_t n_steps, double *J_hist)
+{
+    if (!s) return MJ_EINVAL;
+    if (n_steps < 0) return fail(s, MJ_EINVAL, "n_steps < 0");
+    return guarded(s, [&] { s->run(n_steps, J_hist); });
+}
+
+int mj_reset(mj_solver *s)
+{
+    if (!s) return MJ_EINVAL;
+    s->n = 0;
+    return MJ_OK;
+}
+
+int mj_history_sum(mj_solver *s, const double *J_hist, int32_t depth, double *P)
+{
+    if (!s) return MJ_EINVAL;
+    if (!J_hist || !P || depth < 1) return fail(s, MJ_EINVAL, "bad history arguments");
+    return guarded(s, [&] { s->history_sum(J_hist, depth, P); });
+}
+
+int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t *offset, double *out)
+{
+    if (!s) return MJ_EINVAL;
+    if (n < 0 || (n > 0 && (!lag || !offset || !out))) return fail(s, MJ_EINVAL, "bad kernel value request");
+    return guarded(s, [&] {
+        for (int i = 0; i < n; i++) {
+            if (lag[i] < 0 || lag[i] > s->ell) throw ArgError("lag out of range");
+            if (std::abs(offset[3 * i]) >= s->U || std::abs(offset[3 * i + 1]) >= s->V ||
+                std::abs(offset[3 * i + 2]) >= s->W)
+                throw ArgError("offset out of range");
+        }
+        if (n == 0) return;
+        int *lag_d = nullptr, *off_d = nullptr;
+        double *out_d = nullptr;
+        MJ_CHECK(hipMalloc(&lag_d, sizeof(int) * n));
+        MJ_CHECK(hipMalloc(&off_d, sizeof(int) * 3 * n));
+        MJ_CHECK(hipMalloc(&out_d, sizeof(double) * 6 * n));
+        MJ_CHECK(hipMemcpy(lag_d, lag, sizeof(int) * n, hipMemcpyHostToDevice));
+        MJ_CHECK(hipMemcpy(off_d, offset, sizeof(int) * 3 * n, hipMemcpyHostToDevice));
+        mj::gen_kernel_values(s->gen, n, lag_d, off_d, out_d, s->st);
+        MJ_CHECK(hipMemcpyAsync(out, out_d, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, s->st));
+        MJ_CHECK(hipStreamSynchronize(s->st));
+        (void)hipFree(lag_d);
+        (void)hipFree(off_d);
+        (void)hipFree(out_d);
+    });
+}
+
+int mj_stats(const mj_solver *s, double *out, int32_t n)
+{
+    if (!s || !out) return MJ_EINVAL;
+    for (int i = 0; i < n && i < 10; i++) out[i] = s->stat[i];
+    return MJ_OK;
+}
+
+int mj_fft_roundtrip(mj_solver *s, const double *x, double *X, double *yout)
+{
+    if (!s || !x) return MJ_EINVAL;
+    return guarded(s, [&] {
+        double2 *Xd = X ? (double2 *)X : s->Shat;
+        mj::fft3d_forward(s->fft, x, Xd, 3, s->st);
+        if (yout) mj::fft3d_inverse(s->fft, Xd, yout, 3, s->st);
+        MJ_CHECK(hipStreamSynchronize(s->st));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations of the MOT-JVIE HIP library (gfx950, FP64 throughout).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#define MJ_CHECK(expr)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw mj::HipError(std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+namespace mj {
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+struct MemError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+// ---------------------------------------------------------------------------- complex
+__host__ __device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// ---------------------------------------------------------------------------- FFT plan
+constexpr int kMaxStages = 12;
+constexpr int kMaxFftN = 512;
+
+struct FftPlan1D {
+    int N = 0;
+    int nst = 0;
+    int radix[kMaxStages] = {};
+    double2 *tw = nullptr;  // device table W_N^m = exp(-2 pi i m / N), m = 0..N-1
+};
+
+// Builds the radix plan and uploads the correctly rounded twiddle table.
+void fft_plan_init(FftPlan1D &p, int N);
+void fft_plan_free(FftPlan1D &p);
+bool fft_size_ok(int N);
+int fft_pick_size(int nmin);  // smallest even N >= nmin whose factors are all supported radices
+
+// Geometry of one padded 3-D transform of `ncomp` real fields on a U x V x W box.
+struct Fft3D {
+    int U, V, W;
+    int Nx, Ny, Nz, Hx;  // Hx = Nx/2 + 1
+    FftPlan1D px, py, pz;
+    // scratch: after the x pass [ncomp][W][V][Hx], after the y pass [ncomp][W][Ny][Hx]
+    double2 *bufA = nullptr, *bufB = nullptr;
+    int ncomp = 0;
+};
+
+void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz);
+void fft3d_free(Fft3D &f);
+// x: [ncomp][W][V][U] real; X: [ncomp][Nz][Ny][Hx] complex (unnormalised forward DFT of the zero-padded field)
+void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t st);
+// X: [ncomp][Nz][Ny][Hx]; y: [ncomp][W][V][U] = unnormalised inverse DFT restricted to the box
+void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t st);
+
+// ---------------------------------------------------------------------------- generator
+// Shell moments per octant offset (see mj_gen.hip).  kMoments values per (offset, shell).
+constexpr int kMoments = 19;
+constexpr int kMaxShells = 6;
+
+struct GenResult {
+    double *moments = nullptr;  // [Woct][Voct][Uoct][kMaxShells][kMoments]
+    int Uo = 0, Vo = 0, Wo = 0;
+};
+
+void gen_moments(GenResult &g, int U, int V, int W, int nquad, hipStream_t st);
+// K_k on the full periodic grid [6][Nz][Ny][Nx] (real), from the octant moments
+void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *grid, hipStream_t st);
+// K_k(D) for a list of (k, D): out[n][6]
+void gen_kernel_values(const GenResult &g, int n, const int *lag_dev, const int *off_dev, double *out_dev,
+                       hipStream_t st);
+
+}  // namespace mj

@@ -1,0 +1,68 @@
+// Argument blocks of the per-step march kernels.
+#pragma once
+
+#include "mj_internal.h"
+
+namespace mj {
+
+constexpr int kMaxLocal = 64;   // largest history depth kept in real space
+
+struct MacArg {
+    const double *Khat;      // [nk][6][Nz/2+1][Ny/2+1][Hx] real, lags 1..nk
+    const double2 *ring_base;// [ring][nrhs][3][Nz][Ny][Hx]
+    double2 *Shat;           // [nrhs][3][Nz][Ny][Hx]
+    int Hx, Ny, Nz;
+    int nk;                  // number of lags summed (1..nk)
+    int ring;                // ring slots
+    int slot_nm1;            // slot of Jhat_{n-1}
+    int nrhs;
+};
+
+struct WaveArg {
+    double k[3], pol[3], rref[3];
+    double width, ct0, amp;
+};
+
+struct EpiArg {
+    long M;
+    int U, V, W;
+    int nrhs;
+    int n;                   // current step
+    double h, c_dt;
+    const double *chi, *schi, *inv_eps;
+    const double *fir;       // device taps (nfir)
+    int nfir;
+    int nloc;                // local history depth used (>= 3)
+    int slot_of[kMaxLocal + 1];  // real-ring slot of J_{n-k}, k = 1..nloc
+    const double *Jring;     // [depth][nrhs][3][M]
+    const double *S;         // [nrhs][3][M] convolution (normalised) or NULL at n = 1
+    const WaveArg *waves;    // [nrhs]
+    double glx8[8], glw8[8]; // 8-point rule on [-1/2, 1/2], weights summing to 1
+    double *rhs, *y;         // [nrhs][3][M]
+};
+
+struct CgArg {
+    long M;
+    int U, V, W;
+    int nrhs, nblk;
+    double tol2;
+    const double *schi, *c0, *inv_diag;
+    const double *rhs;
+    double *y, *r, *z, *p, *q;
+    double *part_rz[2], *part_rr, *part_bb, *part_pq;   // [nrhs][nblk]
+    int *done, *iters;
+    double *res;
+};
+
+void launch_mac(const MacArg &a, hipStream_t st);
+void launch_epilogue(const EpiArg &e, hipStream_t st);
+void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,
+                          const double *fir, int nfir, long M, double *P, hipStream_t st);
+void upload_stencil(const double *K0_27x6);
+void launch_cg_init(const CgArg &a, hipStream_t st);
+void launch_cg_a(const CgArg &a, int it, hipStream_t st);
+void launch_cg_b(const CgArg &a, int it, hipStream_t st);
+void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, double *J, double *Jout,
+                      hipStream_t st);
+
+}  // namespace mj

@@ -1,0 +1,204 @@
+"""Python binding of libmotjvie.so (C interface in include/motjvie.h).
+
+Argument marshalling only: every step of the march runs in the HIP library.  Device
+buffers are torch CUDA tensors (float64, contiguous); PyTorch provides device memory
+and the stream, nothing else.  The library must have been built (paper_2407_03323_amd/
+build.py); importing this module on a machine without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmotjvie.so")
+
+MJ_OK, MJ_EINVAL, MJ_ENOMEM, MJ_EHIP, MJ_ENOCONV, MJ_EUNSTABLE, MJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {MJ_EINVAL: "MJ_EINVAL", MJ_ENOMEM: "MJ_ENOMEM", MJ_EHIP: "MJ_EHIP", MJ_ENOCONV: "MJ_ENOCONV",
+          MJ_EUNSTABLE: "MJ_EUNSTABLE", MJ_ESTATE: "MJ_ESTATE"}
+
+
+class MotJvieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class mj_config(ctypes.Structure):
+    _fields_ = [
+        ("U", ctypes.c_int32), ("V", ctypes.c_int32), ("W", ctypes.c_int32),
+        ("h", ctypes.c_double), ("c_dt", ctypes.c_double),
+        ("eps_r", ctypes.POINTER(ctypes.c_double)),
+        ("fir", ctypes.POINTER(ctypes.c_double)), ("n_fir", ctypes.c_int32),
+        ("n_rhs", ctypes.c_int32),
+        ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
+        ("time_block", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("quad_order", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmotjvie.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libmotjvie.so not built (run paper_2407_03323_amd/build.py): %s" % path)
+    L = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    L.mj_create.argtypes = [ctypes.POINTER(mj_config), ctypes.POINTER(vp)]
+    L.mj_destroy.argtypes = [vp]
+    L.mj_destroy.restype = None
+    L.mj_last_error.argtypes = [vp]
+    L.mj_last_error.restype = ctypes.c_char_p
+    L.mj_info.argtypes = [vp, dp, ctypes.c_int32]
+    L.mj_set_plane_waves.argtypes = [vp, dp, dp, dp, dp, dp, dp]
+    L.mj_run.argtypes = [vp, ctypes.c_int32, vp]
+    L.mj_reset.argtypes = [vp]
+    L.mj_history_sum.argtypes = [vp, vp, ctypes.c_int32, vp]
+    L.mj_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, dp]
+    L.mj_stats.argtypes = [vp, dp, ctypes.c_int32]
+    L.mj_fft_roundtrip.argtypes = [vp, vp, vp, vp]
+    for f in ("mj_create", "mj_info", "mj_set_plane_waves", "mj_run", "mj_reset", "mj_history_sum",
+              "mj_kernel_values", "mj_stats", "mj_fft_roundtrip"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _tptr(t, what):
+    """Device pointer of a float64 contiguous CUDA tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float64 CUDA tensor" % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One MOT-JVIE march on the device (see include/motjvie.h for the exact semantics)."""
+
+    def __init__(self, U, V, W, eps, fir=None, h=1.0, c_dt=None, n_rhs=1, cg_rtol=0.0, cg_maxit=0,
+                 time_block=0, quad_order=0, stream=None):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(W, V, U))
+        fir = np.ascontiguousarray(np.zeros(0) if fir is None else np.asarray(fir, dtype=np.float64))
+        self.U, self.V, self.W, self.n_rhs = int(U), int(V), int(W), int(n_rhs)
+        self.M = self.U * self.V * self.W
+        cfg = mj_config()
+        cfg.U, cfg.V, cfg.W = self.U, self.V, self.W
+        cfg.h = float(h)
+        cfg.c_dt = float(h if c_dt is None else c_dt)
+        cfg.eps_r = _dptr(eps)
+        cfg.fir = _dptr(fir) if len(fir) else None
+        cfg.n_fir = len(fir)
+        cfg.n_rhs = self.n_rhs
+        cfg.cg_rtol = float(cg_rtol)
+        cfg.cg_maxit = int(cg_maxit)
+        cfg.time_block = int(time_block)
+        cfg.stream = stream if stream is not None else _current_stream()
+        cfg.quad_order = int(quad_order)
+        self._keep = (eps, fir)
+        rc = self._lib.mj_create(ctypes.byref(cfg), ctypes.byref(self._h))
+        if rc != MJ_OK:
+            raise MotJvieError(rc, self._lib.mj_last_error(None).decode())
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, rc):
+        if rc != MJ_OK:
+            raise MotJvieError(rc, self._lib.mj_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            self._lib.mj_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        out = np.zeros(12)
+        self._check(self._lib.mj_info(self._h, _dptr(out), 12))
+        keys = ["ell", "Nx", "Ny", "Nz", "time_block", "local_depth", "n_rhs", "n", "device_bytes",
+                "gen_ms", "spectra_ms", "n_fir"]
+        return {k: (int(v) if k not in ("gen_ms", "spectra_ms") else float(v)) for k, v in zip(keys, out)}
+
+    @property
+    def ell(self) -> int:
+        return self.info()["ell"]
+
+    # ------------------------------------------------------------------ march
+    def set_plane_waves(self, waves):
+        """waves: sequence (one per right-hand side) of objects with khat, pol, width, t0, amp, r_ref."""
+        assert len(waves) == self.n_rhs
+        k = np.ascontiguousarray([w.khat for w in waves], dtype=np.float64)
+        p = np.ascontiguousarray([w.pol for w in waves], dtype=np.float64)
+        wd = np.ascontiguousarray([w.width for w in waves], dtype=np.float64)
+        t0 = np.ascontiguousarray([w.t0 for w in waves], dtype=np.float64)
+        a = np.ascontiguousarray([w.amp for w in waves], dtype=np.float64)
+        rr = np.ascontiguousarray([w.r_ref for w in waves], dtype=np.float64)
+        self._check(self._lib.mj_set_plane_waves(self._h, _dptr(k), _dptr(p), _dptr(wd), _dptr(t0), _dptr(a),
+                                                 _dptr(rr)))
+
+    def run(self, n_steps: int, J_out=None):
+        """March n_steps; J_out (optional) is a CUDA tensor [n_steps][n_rhs][3][W][V][U]."""
+        if J_out is not None:
+            assert J_out.numel() == n_steps * self.n_rhs * 3 * self.M
+        self._check(self._lib.mj_run(self._h, int(n_steps), _tptr(J_out, "J_out")))
+
+    def reset(self):
+        self._check(self._lib.mj_reset(self._h))
+
+    def history_sum(self, J_hist, P):
+        """P_{n-1} for the explicit history J_hist[k-1] = J_{n-k} (CUDA tensors)."""
+        depth = J_hist.shape[0]
+        assert J_hist.numel() == depth * 3 * self.M and P.numel() == 3 * self.M
+        self._check(self._lib.mj_history_sum(self._h, _tptr(J_hist, "J_hist"), int(depth), _tptr(P, "P")))
+
+    def kernel_values(self, lags, offsets) -> np.ndarray:
+        lags = np.ascontiguousarray(np.asarray(lags, dtype=np.int32))
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+        out = np.zeros((len(lags), 6))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        self._check(self._lib.mj_kernel_values(self._h, len(lags), lags.ctypes.data_as(ip),
+                                               offs.ctypes.data_as(ip), _dptr(out)))
+        return out
+
+    def stats(self) -> dict:
+        out = np.zeros(10)
+        self._check(self._lib.mj_stats(self._h, _dptr(out), 10))
+        keys = ["fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms", "z0_ms", "step_ms", "cg_iters",
+                "cg_res_max", "steps", "cg_iters_max"]
+        return dict(zip(keys, out.tolist()))
+
+    def fft_roundtrip(self, x, X=None, y=None):
+        self._check(self._lib.mj_fft_roundtrip(self._h, _tptr(x, "x"), _tptr(X, "X"), _tptr(y, "y")))
+
+
+def solver_for(problem, **kw) -> Solver:
+    """Solver for a workloads.Problem, with its plane waves set."""
+    s = Solver(problem.U, problem.V, problem.W, problem.eps, fir=problem.fir, h=problem.h, c_dt=problem.c_dt,
+               n_rhs=kw.pop("n_rhs", len(problem.waves) or 1), **kw)
+    if problem.waves:
+        s.set_plane_waves(problem.waves)
+    return s

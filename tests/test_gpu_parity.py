@@ -1,0 +1,166 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle and with library FFTs."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from conftest import oracle_kernel_table
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_solver(prob, **kw):
+    from paper_2407_03323_amd import solver_for
+    return solver_for(prob, **kw)
+
+
+# ----------------------------------------------------------------------------- FFT
+@pytest.mark.parametrize("UVW", [(8, 8, 8), (5, 6, 7), (11, 3, 12), (4, 13, 2)])
+def test_fft_matches_numpy(torch_cuda, UVW):
+    """Forward 3-D FFT of the zero-padded box against numpy.fft.rfftn; the inverse restricted
+    to the box returns N x (unnormalised)."""
+    torch = torch_cuda
+    U, V, W = UVW
+    say("fft case", UVW)
+    prob = wl.Problem("fft", U, V, W, np.full((W, V, U), 2.0), [], 1)
+    s = make_solver(prob, n_rhs=1, quad_order=8)
+    info = s.info()
+    Nx, Ny, Nz = info["Nx"], info["Ny"], info["Nz"]
+    assert Nx >= 2 * U - 1 and Ny >= 2 * V - 1 and Nz >= 2 * W - 1
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((3, W, V, U))
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    Hx = Nx // 2 + 1
+    Xt = torch.zeros((3, Nz, Ny, Hx, 2), dtype=torch.float64, device="cuda")
+    yt = torch.zeros_like(xt)
+    s.fft_roundtrip(xt, Xt, yt)
+    torch.cuda.synchronize()
+    X = Xt.cpu().numpy()
+    X = X[..., 0] + 1j * X[..., 1]
+    pad = np.zeros((3, Nz, Ny, Nx))
+    pad[:, :W, :V, :U] = x
+    ref = np.fft.rfftn(pad, axes=(1, 2, 3))
+    assert np.abs(X - ref).max() < 1e-12 * np.abs(ref).max()
+    y = yt.cpu().numpy() / (Nx * Ny * Nz)
+    assert np.abs(y - x).max() < 1e-13 * np.abs(x).max()
+    s.close()
+
+
+# ----------------------------------------------------------------------------- generator
+def _all_offsets(U):
+    r = np.arange(-(U - 1), U)
+    dz, dy, dx = np.meshgrid(r, r, r, indexing="ij")
+    return np.stack([dx.ravel(), dy.ravel(), dz.ravel()], axis=1)
+
+
+def test_generator_matches_oracle_8cube(torch_cuda):
+    """Every K_k(D) of the 8^3 grid (k = 0..ell, all offsets) against the oracle's
+    independent per-lag quadrature."""
+    say("generator 8^3")
+    prob = wl.config("C1")
+    s = make_solver(prob)
+    ell = s.ell
+    assert ell == 15
+    Ko = oracle_kernel_table(8, 8, 8, ell)
+    offs = _all_offsets(8)
+    for k in range(ell + 1):
+        got = s.kernel_values(np.full(len(offs), k), offs)
+        ref = np.stack([Ko[k, c][offs[:, 2] + 7, offs[:, 1] + 7, offs[:, 0] + 7] for c in range(6)], axis=1)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-12 * scale + 1e-16, (k, np.abs(got - ref).max(), scale)
+    s.close()
+
+
+def test_generator_matches_oracle_sampled_large(torch_cuda):
+    """Sampled K_k(D) on a 48^3 grid (offsets up to 47, lags up to 85) against the oracle."""
+    from oracle import mot
+    say("generator sampled 48^3")
+    U = 48
+    prob = wl.Problem("g48", U, U, U, np.full((U, U, U), 3.0), [], 1)
+    s = make_solver(prob, n_rhs=1)
+    ell = s.ell
+    rng = np.random.default_rng(11)
+    offs, lags = [], []
+    for _ in range(60):
+        D = rng.integers(-(U - 1), U, 3)
+        R = np.sqrt(((np.maximum(np.abs(D) - 1, 0)) ** 2).sum())
+        k = int(min(ell, max(0, int(R) + rng.integers(0, 4))))
+        offs.append(D)
+        lags.append(k)
+    offs += [np.array([47, 47, 47]), np.array([-47, 0, 1]), np.array([0, 0, 0]), np.array([1, -1, 1])]
+    lags += [ell, 48, 1, 2]
+    got = s.kernel_values(lags, np.array(offs))
+    for i, (k, D) in enumerate(zip(lags, offs)):
+        ref = mot.kernel_entry(k, D)
+        # entries at the edge of their lag window can be far below the kernel's size at
+        # that distance (about 0.03 / R); compare against that size
+        R = np.sqrt(((np.maximum(np.abs(D) - 1, 0)) ** 2).sum())
+        scale = max(np.abs(ref).max(), 0.03 / (1.0 + R))
+        assert np.abs(got[i] - ref).max() <= 3e-12 * scale, (k, D, got[i], ref)
+    s.close()
+
+
+# ----------------------------------------------------------------------------- history sum
+def _rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+@pytest.mark.parametrize("with_fir", [False, True])
+def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir):
+    """P_{n-1} through FFT -> spectral MAC -> inverse FFT (+ local and FIR terms) against the
+    direct sum, random history over all ell lags, heterogeneous eps."""
+    from oracle import mot
+    torch = torch_cuda
+    say("history sum 8^3 fir=%s" % with_fir)
+    U = 8
+    eps = wl.random_eps(U, U, U, 21, 1.0, 12.0)
+    fir = wl.binomial_highpass(17, 0.1) if with_fir else np.zeros(0)
+    prob = wl.Problem("hs", U, U, U, eps, [], 1, fir=fir)
+    s = make_solver(prob, n_rhs=1)
+    ell = s.ell
+    depth = max(ell, len(fir) - 1)
+    Jh = wl.random_history(U, U, U, depth, 99)
+    K = oracle_kernel_table(U, U, U, ell)
+    ref = mot.history_sum(K, Jh, eps, fir, ell)
+    Jt = torch.tensor(Jh, dtype=torch.float64, device="cuda")
+    Pt = torch.zeros((3, U, U, U), dtype=torch.float64, device="cuda")
+    s.history_sum(Jt, Pt)
+    torch.cuda.synchronize()
+    P = Pt.cpu().numpy()
+    err = _rel(P, ref)
+    say("  rel err", err)
+    assert err <= 1e-11
+    s.close()
+
+
+# ----------------------------------------------------------------------------- march
+def test_march_matches_oracle_C1(torch_cuda, c1_oracle):
+    """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8."""
+    torch = torch_cuda
+    say("march C1")
+    prob, o, Jref = c1_oracle
+    s = make_solver(prob)
+    Jt = torch.zeros((prob.n_steps, 1, 3, 8, 8, 8), dtype=torch.float64, device="cuda")
+    s.run(prob.n_steps, Jt)
+    torch.cuda.synchronize()
+    J = Jt.cpu().numpy()[:, 0]
+    err = _rel(J, Jref)
+    st = s.stats()
+    say("  rel L2", err, "cg iters", st["cg_iters"], "res", st["cg_res_max"])
+    assert err <= 1e-8
+    s.close()
