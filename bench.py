@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the MOT-JVIE march on one MI355X.
+
+A step is one pass of the whole hot path for one time step: forward FFT of the newest
+current, spectral multiply-accumulate over all ell history lags, inverse FFT, right-hand
+side assembly (excitation, FIR, local terms) and the Z_0 solve.  The timed steps start
+after `warmup` steps; warmup defaults to more than ell so every timed step sums the full
+history.  Kernel generation and spectra are one-time setup and are reported separately.
+
+Prints one JSON line (metric voxel*steps/s, FP64).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "voxel·steps/s FP64 at 1.1M voxels; % HBM roofline; batched/adjoint vs plain"
+
+WORKLOADS = {
+    "C5": "104^3 cube of side 100h eps_r=12 in a 2-voxel eps_r=1 margin, c dt = h, x-pol +z Gaussian "
+          "plane wave sigma=8 dt delay 6 sigma, 17-tap binomial FIR delta=0.1125",
+    "C2": "32^3 sphere r=15h eps_r=12, c dt = h, x-pol +z Gaussian sigma=4 dt, 17-tap binomial FIR delta=0.1",
+    "C1": "8^3 cube eps_r=4, c dt = h, x-pol +z Gaussian sigma=4 dt, no FIR",
+}
+
+
+def mac_source_digest() -> str:
+    with open(os.path.join(ROOT, "paper_2407_03323_amd", "csrc", "mj_march.hip"), "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()[:12]
+
+
+def mac_traffic(workload: str):
+    """HBM bytes per MAC launch from the committed rocprofv3 counter summary, if it was taken
+    on the current MAC source; else None."""
+    path = os.path.join(ROOT, "profiles", "mac_traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("mac_source_sha1_12") != mac_source_digest():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, ell: int, target_seconds: float = 20.0):
+    """The oracle's direct history sum (oracle/direct.c, unchanged) timed on the host on a
+    bounded sample of the same grid: a few target voxels, every source voxel and 4 of the
+    ell lags, scaled linearly to all voxels and all lags (the triple loop's cost is exactly
+    linear in both).  The kernel table holds zeros: the loop's cost does not depend on the
+    values.  Z_0 solve and excitation are not included (they are O(M) per step against
+    O(M^2 ell) for the history sum)."""
+    from oracle import mot
+    U, V, W, M = prob.U, prob.V, prob.W, prob.M
+    nlag = 4
+    K = np.zeros((nlag + 1, 6, 2 * W - 1, 2 * V - 1, 2 * U - 1))
+    Jh = np.zeros((nlag, 3, W, V, U))
+    rng = np.random.default_rng(0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    nt = max(threads, 8)
+    t0 = time.perf_counter()
+    mot.conv(K, Jh, rng.integers(0, M, nt))
+    dt = time.perf_counter() - t0
+    # grow the sample to about target_seconds
+    nt2 = int(min(M, max(nt, nt * target_seconds / max(dt, 1e-3))))
+    nt2 = max(threads, (nt2 // threads) * threads)
+    t0 = time.perf_counter()
+    mot.conv(K, Jh, rng.integers(0, M, nt2))
+    dt2 = time.perf_counter() - t0
+    per_step = dt2 * (M / nt2) * (ell / nlag)
+    return {"value": M / per_step, "unit": "voxel·steps/s", "cores": threads, "kind": "oracle",
+            "sample": "direct history sum of the oracle for %d target voxels x all %d sources x %d of %d lags "
+                      "(%.1f s), scaled to %d targets and %d lags" % (nt2, M, nlag, ell, dt2, M, ell)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=-1, help="default: ell + 8")
+    ap.add_argument("--workload", default="C5", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(how the march would shard is a design note, not code); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2407_03323_amd import motjvie
+    if not os.path.exists(motjvie.LIB_PATH):
+        from paper_2407_03323_amd import build
+        build.build()
+    import workloads as wl
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    prob = wl.config(args.workload)
+    t_setup = time.perf_counter()
+    solver = motjvie.solver_for(prob)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    info = solver.info()
+    ell = info["ell"]
+    warmup = args.warmup if args.warmup >= 0 else ell + 8
+    print("setup %.2f s (kernels %.0f ms, spectra %.0f ms), ell=%d, pads %dx%dx%d, %.1f GB" % (
+        t_setup, info["gen_ms"], info["spectra_ms"], ell, info["Nx"], info["Ny"], info["Nz"],
+        info["device_bytes"] / 1e9), file=sys.stderr, flush=True)
+
+    if warmup:
+        solver.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.run(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = solver.stats()
+    M = prob.M
+    value = M * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    print("phases ms/step: fft %.3f mac %.3f ifft %.3f epi %.3f z0 %.3f (cg %.1f it)" % (
+        st["fft_fwd_ms"], st["mac_ms"], st["fft_inv_ms"], st["epilogue_ms"], st["z0_ms"], st["cg_iters"]),
+        file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (spectral MAC): algorithmic bytes per launch
+    Nx, Ny, Nz = info["Nx"], info["Ny"], info["Nz"]
+    Hx = Nx // 2 + 1
+    half = Hx * Ny * Nz                       # half-spectrum points
+    octant = Hx * (Ny // 2 + 1) * (Nz // 2 + 1)
+    nk = ell                                  # every timed step sums all ell lags
+    bytes_launch = nk * (48.0 * half + 48.0 * octant) + 48.0 * half
+    mac_s = st["mac_ms"] / 1e3
+    achieved = bytes_launch / mac_s / 1e9
+    traffic = mac_traffic(args.workload)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel·steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "grid": [prob.U, prob.V, prob.W], "voxels": M, "ell": ell, "pad": [Nx, Ny, Nz],
+                   "fir_taps": len(prob.fir), "setup_s": round(t_setup, 3),
+                   "phase_ms": {k: round(st[k], 4) for k in ("fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms",
+                                                              "z0_ms")},
+                   "cg_iters": round(st["cg_iters"], 2)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "spectral MAC (k_mac)", "bytes_per_launch": bytes_launch,
+                     "avg_launch_ms": st["mac_ms"]},
+    }
+    solver.close()
+    del solver
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, ell)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
