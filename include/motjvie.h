@@ -65,7 +65,7 @@ typedef struct {
     int32_t n_rhs;            /* number of right-hand sides (plane waves) marched together, >= 1 */
     double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-12 */
     int32_t cg_maxit;         /* <= 0 selects 200 */
-    int32_t time_block;       /* history MAC time block B; 0 selects automatically, 1 = no blocking */
+    int32_t time_block;       /* steps per time block of the history MAC: 1 (none), 4 or 8; 0 selects 8 */
     void *stream;             /* hipStream_t to enqueue on; NULL = the null stream */
     int32_t quad_order;       /* Gauss-Legendre points per cell of the kernel quadrature; 0 selects 16 */
 } mj_config;
@@ -136,10 +136,12 @@ int mj_history_sum(mj_solver *s, const double *J_hist, int32_t depth, double *P)
 int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t *offset, double *out);
 
 /*
- * mj_stats -- per-phase device times of the last mj_run, in ms per step, and CG
- *   statistics.  out (host, n <= 10): [0] forward FFT  [1] history MAC  [2] inverse FFT
- *   [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total  [6] mean CG iterations
- *   [7] max final relative residual  [8] steps timed  [9] max CG iterations.
+ * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
+ *   in ms per step, and CG statistics.  out (host, n <= 13): [0] forward FFT  [1] history
+ *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total
+ *   [6] mean CG iterations  [7] max final relative residual  [8] steps timed
+ *   [9] max CG iterations  [10] mean duration of one far-part MAC launch (time-blocked,
+ *   once per block)  [11] far-part launches  [12] mean duration of one near-part launch.
  */
 int mj_stats(const mj_solver *s, double *out, int32_t n);
 

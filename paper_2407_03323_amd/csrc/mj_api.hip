@@ -67,10 +67,14 @@ struct mj_solver {
     double *chi = nullptr, *schi = nullptr, *inv_eps = nullptr, *c0 = nullptr, *inv_diag = nullptr;
     double *fir_d = nullptr;
     double *Khat = nullptr;
-    double2 *ring = nullptr, *Shat = nullptr;
+    double2 *ring = nullptr, *Shat = nullptr, *farbuf = nullptr;
     double *S = nullptr, *Jr = nullptr;
     double *rhs = nullptr, *y = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *u = nullptr, *uy = nullptr;
     double *parts = nullptr;
+    unsigned *counters = nullptr;
+    mj::CgScalars *scal = nullptr;
+    int cg_guess = 8;
     int *done = nullptr, *iters = nullptr;
     double *res = nullptr;
     int *done_h = nullptr, *iters_h = nullptr;
@@ -86,7 +90,7 @@ struct mj_solver {
     std::string err;
     // statistics of the last run
     double t_gen_ms = 0, t_spec_ms = 0;
-    double stat[10] = {};
+    double stat[13] = {};
     Events events;
 
     template <class T>
@@ -161,7 +165,8 @@ void mj_solver::create(const mj_config &c)
     Ny = mj::fft_pick_size(2 * V - 1);
     Nz = mj::fft_pick_size(2 * W - 1);
     Hx = Nx / 2 + 1;
-    B = c.time_block > 0 ? c.time_block : 1;
+    B = c.time_block > 0 ? c.time_block : 8;
+    if (B != 1 && B != 4 && B != 8) throw ArgError("time_block must be 0 (auto), 1, 4 or 8");
     nloc = std::max(3, (int)fir.size() - 1);
     rdepth = nloc + 1;
 
@@ -201,6 +206,7 @@ void mj_solver::create(const mj_config &c)
     const long sp = spec_plane();
     ring = dalloc<double2>((size_t)ell * nrhs * 3 * sp, "spectral history ring");
     Shat = dalloc<double2>((size_t)nrhs * 3 * sp, "spectral sum");
+    if (B > 1) farbuf = dalloc<double2>((size_t)B * nrhs * 3 * sp, "time-block partial sums");
     S = dalloc<double>((size_t)nrhs * 3 * M, "convolution");
     Jr = dalloc<double>((size_t)rdepth * nrhs * 3 * M, "current history");
     rhs = dalloc<double>((size_t)nrhs * 3 * M, "cg rhs");
@@ -209,8 +215,13 @@ void mj_solver::create(const mj_config &c)
     z = dalloc<double>((size_t)nrhs * 3 * M, "cg z");
     p = dalloc<double>((size_t)nrhs * 3 * M, "cg p");
     q = dalloc<double>((size_t)nrhs * 3 * M, "cg q");
-    nblk = (int)std::min<long>(1024, (M + 255) / 256);
-    parts = dalloc<double>((size_t)5 * nrhs * nblk, "cg partials");
+    u = dalloc<double>((size_t)nrhs * 3 * M, "cg u");
+    uy = dalloc<double>((size_t)nrhs * 3 * M, "cg uy");
+    nblk = (int)((M + 255) / 256);
+    parts = dalloc<double>((size_t)3 * nrhs * nblk, "cg partials");
+    counters = dalloc<unsigned>(nrhs, "cg counters");
+    MJ_CHECK(hipMemset(counters, 0, sizeof(unsigned) * nrhs));
+    scal = dalloc<mj::CgScalars>(nrhs, "cg scalars");
     done = dalloc<int>(nrhs, "cg flags");
     iters = dalloc<int>(nrhs, "cg iterations");
     res = dalloc<double>(nrhs, "cg residuals");
@@ -314,27 +325,27 @@ void mj_solver::solve_z0()
     a.c0 = c0;
     a.inv_diag = inv_diag;
     a.rhs = rhs;
+    a.uy = uy;
     a.y = y;
     a.r = r;
     a.z = z;
     a.p = p;
     a.q = q;
-    const size_t pn = (size_t)nrhs * nblk;
-    a.part_rz[0] = parts;
-    a.part_rz[1] = parts + pn;
-    a.part_rr = parts + 2 * pn;
-    a.part_bb = parts + 3 * pn;
-    a.part_pq = parts + 4 * pn;
+    a.u = u;
+    a.part = parts;
+    a.scal = scal;
     a.done = done;
     a.iters = iters;
     a.res = res;
     MJ_CHECK(hipMemsetAsync(done, 0, sizeof(int) * nrhs, st));
     mj::launch_cg_init(a, st);
-    const int chunk = 4;
+    // enqueue as many iterations as the last solve needed before the first look at the
+    // convergence flags; kernels after convergence return at once
     int it = 0;
+    int batch = std::max(2, std::min(cg_maxit, cg_guess));
     bool all_done = false;
     while (it < cg_maxit && !all_done) {
-        int upto = std::min(cg_maxit, it + chunk);
+        int upto = std::min(cg_maxit, it + batch);
         for (; it < upto; it++) {
             mj::launch_cg_a(a, it, st);
             mj::launch_cg_b(a, it, st);
@@ -343,14 +354,17 @@ void mj_solver::solve_z0()
         MJ_CHECK(hipStreamSynchronize(st));
         all_done = true;
         for (int i = 0; i < nrhs; i++) all_done = all_done && done_h[i];
+        batch = 2;
     }
-    if (!all_done) {
-        mj::launch_cg_a(a, it, st);   // records the final residual (and the flag if converged)
-    }
+    // one more test records the final residual (and the flag, if the last update converged)
+    if (!all_done) mj::launch_cg_a(a, it, st);
     MJ_CHECK(hipMemcpyAsync(done_h, done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
     MJ_CHECK(hipMemcpyAsync(iters_h, iters, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
     MJ_CHECK(hipMemcpyAsync(res_h, res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     MJ_CHECK(hipStreamSynchronize(st));
+    int mx = 0;
+    for (int i = 0; i < nrhs; i++) mx = std::max(mx, iters_h[i]);
+    cg_guess = mx + 1;
 }
 
 void mj_solver::run(int n_steps, double *Jout)
@@ -383,6 +397,7 @@ void mj_solver::run(int n_steps, double *Jout)
             glw8[i] = (double)(1.0L / ((1 - zz * zz) * dp * dp));
         }
     }
+    std::vector<char> step_far(n_steps, 0);
     for (int s = 0; s < n_steps; s++) {
         hipEvent_t *ev = &events.ev[(size_t)6 * s];
         MJ_CHECK(hipEventRecord(ev[0], st));
@@ -394,7 +409,8 @@ void mj_solver::run(int n_steps, double *Jout)
                               3 * nrhs, st);
         }
         MJ_CHECK(hipEventRecord(ev[1], st));
-        if (hist) {
+        const double2 *spec = Shat;
+        if (hist && B == 1) {
             mj::MacArg a{};
             a.Khat = Khat;
             a.ring_base = ring;
@@ -407,9 +423,30 @@ void mj_solver::run(int n_steps, double *Jout)
             a.slot_nm1 = slotS(n - 1);
             a.nrhs = nrhs;
             mj::launch_mac(a, st);
+        } else if (hist) {
+            // blocks of B steps starting at n_b = 2, 2 + B, ...: the far part of every step of the
+            // block is formed at n_b, when all of its sources are in the ring
+            const int t = (n - 2) % B;
+            mj::BlockMacArg a{};
+            a.Khat = Khat;
+            a.ring_base = ring;
+            a.far = farbuf;
+            a.Hx = Hx;
+            a.Ny = Ny;
+            a.Nz = Nz;
+            a.nk = ell;
+            a.ring = ell;
+            a.nb = n - t;
+            a.ntarget = B;
+            a.t = t;
+            a.nrhs = nrhs;
+            if (t == 0) mj::launch_mac_far(a, B, st);
+            else mj::launch_mac_near(a, st);
+            step_far[s] = t == 0 ? 1 : 2;
+            spec = farbuf + (size_t)t * nrhs * 3 * sp;
         }
         MJ_CHECK(hipEventRecord(ev[2], st));
-        if (hist) mj::fft3d_inverse(fft, Shat, S, 3 * nrhs, st);
+        if (hist) mj::fft3d_inverse(fft, spec, S, 3 * nrhs, st);
         MJ_CHECK(hipEventRecord(ev[3], st));
         {
             mj::EpiArg e{};
@@ -437,6 +474,7 @@ void mj_solver::run(int n_steps, double *Jout)
             }
             e.rhs = rhs;
             e.y = y;
+            e.uy = uy;
             mj::launch_epilogue(e, st);
         }
         MJ_CHECK(hipEventRecord(ev[4], st));
@@ -453,12 +491,16 @@ void mj_solver::run(int n_steps, double *Jout)
     }
     MJ_CHECK(hipStreamSynchronize(st));
     double ph[6] = {0, 0, 0, 0, 0, 0};
+    double far_ms = 0, near_ms = 0;
+    int nfar = 0, nnear = 0;
     for (int s = 0; s < n_steps; s++) {
         hipEvent_t *ev = &events.ev[(size_t)6 * s];
         for (int k = 0; k < 5; k++) {
             float ms = 0;
             MJ_CHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
             ph[k] += ms;
+            if (k == 1 && step_far[s] == 1) { far_ms += ms; nfar++; }
+            if (k == 1 && step_far[s] == 2) { near_ms += ms; nnear++; }
         }
         float tot = 0;
         MJ_CHECK(hipEventElapsedTime(&tot, ev[0], ev[5]));
@@ -470,6 +512,9 @@ void mj_solver::run(int n_steps, double *Jout)
     stat[7] = cg_res_max;
     stat[8] = n_steps;
     stat[9] = cg_iter_max;
+    stat[10] = nfar ? far_ms / nfar : 0.0;
+    stat[11] = nfar;
+    stat[12] = nnear ? near_ms / nnear : 0.0;
     if (noconv) throw std::range_error("Z_0 solve did not converge");
 }
 
@@ -482,19 +527,39 @@ void mj_solver::history_sum(const double *Jh, int depth, double *P)
         if (k <= depth) mj::fft3d_forward(fft, Jh + (size_t)(k - 1) * 3 * M, slot, 3, st);
         else MJ_CHECK(hipMemsetAsync(slot, 0, sizeof(double2) * 3 * sp, st));
     }
-    mj::MacArg a{};
-    a.Khat = Khat;
-    a.ring_base = ring;
-    a.Shat = Shat;
-    a.Hx = Hx;
-    a.Ny = Ny;
-    a.Nz = Nz;
-    a.nk = ell;
-    a.ring = ell;
-    a.slot_nm1 = slotS(nfake - 1);
-    a.nrhs = nrhs;   // ring stride; only right-hand side 0 is meaningful here
-    mj::launch_mac(a, st);
-    mj::fft3d_inverse(fft, Shat, S, 3, st);
+    const double2 *spec = Shat;
+    if (B == 1) {
+        mj::MacArg a{};
+        a.Khat = Khat;
+        a.ring_base = ring;
+        a.Shat = Shat;
+        a.Hx = Hx;
+        a.Ny = Ny;
+        a.Nz = Nz;
+        a.nk = ell;
+        a.ring = ell;
+        a.slot_nm1 = slotS(nfake - 1);
+        a.nrhs = nrhs;   // ring stride; only right-hand side 0 is meaningful here
+        mj::launch_mac(a, st);
+    } else {
+        // the far part of the first step of a block starting at n = ell + 1 is the whole sum
+        mj::BlockMacArg a{};
+        a.Khat = Khat;
+        a.ring_base = ring;
+        a.far = farbuf;
+        a.Hx = Hx;
+        a.Ny = Ny;
+        a.Nz = Nz;
+        a.nk = ell;
+        a.ring = ell;
+        a.nb = nfake;
+        a.ntarget = 1;
+        a.t = 0;
+        a.nrhs = nrhs;
+        mj::launch_mac_far(a, B, st);
+        spec = farbuf;
+    }
+    mj::fft3d_inverse(fft, spec, S, 3, st);
     mj::launch_history_local(Jh, depth, S, chi, inv_eps, fir_d, (int)fir.size(), M, P, st);
     MJ_CHECK(hipStreamSynchronize(st));
     n = 0;
@@ -643,7 +708,7 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
 int mj_stats(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    for (int i = 0; i < n && i < 10; i++) out[i] = s->stat[i];
+    for (int i = 0; i < n && i < 13; i++) out[i] = s->stat[i];
     return MJ_OK;
 }
 

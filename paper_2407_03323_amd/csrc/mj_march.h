@@ -18,6 +18,19 @@ struct MacArg {
     int nrhs;
 };
 
+struct BlockMacArg {
+    const double *Khat;        // [ell][6][Nz/2+1][Ny/2+1][Hx]
+    const double2 *ring_base;  // [ring][nrhs][3][Nz][Ny][Hx]
+    double2 *far;              // [TB][nrhs][3][Nz][Ny][Hx]
+    int Hx, Ny, Nz;
+    int nk;                    // ell (far: lags 1..nk)
+    int ring;
+    int nb;                    // first step of the block
+    int ntarget;               // targets written by the far kernel (<= TB)
+    int t;                     // near: position of the step in the block
+    int nrhs;
+};
+
 struct WaveArg {
     double k[3], pol[3], rref[3];
     double width, ct0, amp;
@@ -38,23 +51,31 @@ struct EpiArg {
     const double *S;         // [nrhs][3][M] convolution (normalised) or NULL at n = 1
     const WaveArg *waves;    // [nrhs]
     double glx8[8], glw8[8]; // 8-point rule on [-1/2, 1/2], weights summing to 1
-    double *rhs, *y;         // [nrhs][3][M]
+    double *rhs, *y, *uy;    // [nrhs][3][M]; uy = sqrt(chi) y
+};
+
+struct CgScalars {
+    double rz[2];            // r.z of the current and the previous iteration (alternating slots)
+    double pq, rr, bb;
 };
 
 struct CgArg {
     long M;
     int U, V, W;
-    int nrhs, nblk;
+    int nrhs, nblk;          // nblk = ceil(M / 256): one voxel per thread
     double tol2;
     const double *schi, *c0, *inv_diag;
-    const double *rhs;
-    double *y, *r, *z, *p, *q;
-    double *part_rz[2], *part_rr, *part_bb, *part_pq;   // [nrhs][nblk]
+    const double *rhs, *uy;
+    double *y, *r, *z, *p, *q, *u;
+    double *part;            // [nrhs][3][nblk]
+    CgScalars *scal;         // [nrhs]
     int *done, *iters;
     double *res;
 };
 
 void launch_mac(const MacArg &a, hipStream_t st);
+void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st);
+void launch_mac_near(const BlockMacArg &a, hipStream_t st);
 void launch_epilogue(const EpiArg &e, hipStream_t st);
 void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,
                           const double *fir, int nfir, long M, double *P, hipStream_t st);

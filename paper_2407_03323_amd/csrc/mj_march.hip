@@ -104,6 +104,208 @@ void launch_mac(const MacArg &a, hipStream_t st)
     MJ_CHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------- time-blocked MAC
+// Toeplitz time division (Sec. 4.1) in two levels.  For the block of target steps
+// n_b .. n_b + TB - 1 (t = n - n_b):
+//   far:  F[t] = sum_{k=t+1}^{ell} Khat_k Jhat_{n_b+t-k}   (sources before the block, all known at n_b)
+//   near: S_n  = F[t] + sum_{k=1}^{t} Khat_k Jhat_{n-k}      (sources inside the block)
+// The far kernel streams every lag once per block: at lag k the TB targets need the TB
+// consecutive sources n_b - k .. n_b - k + TB - 1, a window that slides by one source per lag,
+// so each spectrum is loaded once and reused TB times from registers.
+//
+// Mapping: one workgroup = 64 consecutive octant points x the 4 mirror points
+// (ky, Ny-ky) x (kz, Nz-kz), one wave per mirror; the 4 waves load the same Khat values, so 3
+// of the 4 loads hit in cache.  Duplicate mirrors (ky = 0 or Ny/2, kz = 0 or Nz/2) idle.
+struct MirrorPoint {
+    bool valid;
+    long off;      // offset in one spectrum component [Nz][Ny][Hx]
+    long koff;     // offset in one Khat octant component
+    double sy, sz; // parity signs of the odd components
+};
+
+__device__ inline MirrorPoint mirror_point(int Hx, int Ny, int Nz)
+{
+    MirrorPoint mp;
+    const int Nyo = Ny / 2 + 1, Nzo = Nz / 2 + 1;
+    const long nocts = (long)Hx * Nyo * Nzo;
+    const long o = blockIdx.x * 64L + (threadIdx.x & 63);
+    const int m = (threadIdx.x >> 6) & 3;
+    mp.valid = o < nocts;
+    if (!mp.valid) return mp;
+    const int kx = (int)(o % Hx), qy = (int)((o / Hx) % Nyo), qz = (int)(o / ((long)Hx * Nyo));
+    const int fy = m & 1, fz = m >> 1;
+    if (fy && (qy == 0 || 2 * qy == Ny)) mp.valid = false;
+    if (fz && (qz == 0 || 2 * qz == Nz)) mp.valid = false;
+    const int ky = fy ? Ny - qy : qy, kz = fz ? Nz - qz : qz;
+    mp.off = ((long)kz * Ny + ky) * Hx + kx;
+    mp.koff = o;
+    mp.sy = fy ? -1.0 : 1.0;
+    mp.sz = fz ? -1.0 : 1.0;
+    return mp;
+}
+
+struct KVal {
+    double xx, yy, zz, xy, xz, yz;
+};
+
+__device__ inline KVal load_k(const double *__restrict__ Kk, long koct, const MirrorPoint &mp)
+{
+    KVal k;
+    k.xx = Kk[0];
+    k.yy = Kk[koct];
+    k.zz = Kk[2 * koct];
+    k.xy = Kk[3 * koct] * mp.sy;
+    k.xz = Kk[4 * koct] * mp.sz;
+    k.yz = Kk[5 * koct] * mp.sy * mp.sz;
+    return k;
+}
+
+__device__ inline void kmul_acc(const KVal &k, const double2 *j, double2 *a)
+{
+    a[0].x += k.xx * j[0].x + k.xy * j[1].x + k.xz * j[2].x;
+    a[0].y += k.xx * j[0].y + k.xy * j[1].y + k.xz * j[2].y;
+    a[1].x += k.xy * j[0].x + k.yy * j[1].x + k.yz * j[2].x;
+    a[1].y += k.xy * j[0].y + k.yy * j[1].y + k.yz * j[2].y;
+    a[2].x += k.xz * j[0].x + k.yz * j[1].x + k.zz * j[2].x;
+    a[2].y += k.xz * j[0].y + k.yz * j[1].y + k.zz * j[2].y;
+}
+
+__device__ inline int ring_slot(int j, int ring)
+{
+    int s = j % ring;
+    return s < 0 ? s + ring : s;
+}
+
+// Far part.  Khat is real, so the real and imaginary parts of Jhat never mix: each lane
+// takes one part of one mirror point (lanes 2i, 2i+1 = real, imaginary of point i), which
+// halves the registers per lane.  The lag loop is unrolled by TB so that the sliding source
+// window lives in registers with compile-time slot indices: the source of lag k goes to slot
+// (k - 1) mod TB, and target t at lag k reads the slot written at lag k - t.
+template <int TB>
+__global__ void __launch_bounds__(256) k_mac_far(BlockMacArg a)
+{
+    const int Nyo = a.Ny / 2 + 1, Nzo = a.Nz / 2 + 1;
+    const long nocts = (long)a.Hx * Nyo * Nzo;
+    const int lane = threadIdx.x & 63;
+    const long o = blockIdx.x * 32L + (lane >> 1);
+    const int part = lane & 1;
+    const int m = threadIdx.x >> 6;
+    if (o >= nocts) return;
+    const int kx = (int)(o % a.Hx), qy = (int)((o / a.Hx) % Nyo), qz = (int)(o / ((long)a.Hx * Nyo));
+    const int fy = m & 1, fz = m >> 1;
+    if ((fy && (qy == 0 || 2 * qy == a.Ny)) || (fz && (qz == 0 || 2 * qz == a.Nz))) return;
+    const int ky = fy ? a.Ny - qy : qy, kz = fz ? a.Nz - qz : qz;
+    const double sy = fy ? -1.0 : 1.0, sz = fz ? -1.0 : 1.0;
+    const long off2 = 2 * (((long)kz * a.Ny + ky) * a.Hx + kx) + part;   // in doubles
+    const int r = blockIdx.y;
+    const long plane2 = 2L * a.Nz * a.Ny * a.Hx;                           // one component, in doubles
+    const long koct = nocts;
+    const double *ringd = (const double *)a.ring_base;
+    double acc[TB][3], jw[TB][3];
+#pragma unroll
+    for (int t = 0; t < TB; t++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[t][c] = jw[t][c] = 0.0;
+    const double *Kp = a.Khat + o;
+    const double *Jbase = ringd + (long)r * 3 * plane2 + off2;
+    const long slot_stride = (long)a.nrhs * 3 * plane2;
+    // one lag: source j = n_b - k into slot i (zero if j < 1, i.e. before the march started),
+    // then every target t takes slot (i - t) mod TB, the source of lag k - t
+    auto lag = [&](int k, int i, bool guard) {
+        const int j = a.nb - k;
+        if (!guard || j >= 1) {
+            const double *J = Jbase + (long)ring_slot(j, a.ring) * slot_stride;
+            jw[i][0] = J[0];
+            jw[i][1] = J[plane2];
+            jw[i][2] = J[2 * plane2];
+        } else {
+            jw[i][0] = jw[i][1] = jw[i][2] = 0.0;
+        }
+        const double *Kk = Kp + (long)(k - 1) * 6 * koct;
+        const double kxx = Kk[0], kyy = Kk[koct], kzz = Kk[2 * koct];
+        const double kxy = Kk[3 * koct] * sy, kxz = Kk[4 * koct] * sz, kyz = Kk[5 * koct] * sy * sz;
+#pragma unroll
+        for (int t = 0; t < TB; t++) {
+            const int sl = (i - t + TB) % TB;
+            const double j0 = jw[sl][0], j1 = jw[sl][1], j2 = jw[sl][2];
+            acc[t][0] += kxx * j0 + kxy * j1 + kxz * j2;
+            acc[t][1] += kxy * j0 + kyy * j1 + kyz * j2;
+            acc[t][2] += kxz * j0 + kyz * j1 + kzz * j2;
+        }
+    };
+    // lags up to n_b - 1 have a source for every slot; later lags (at most TB - 1 of them, only
+    // early in the march) still feed targets t >= 1 through older slots
+    const int kfull = min(a.nk, a.nb - 1);
+    const int kend = min(a.nk, a.nb - 2 + TB);
+    int k0 = 1;
+    // full groups of TB lags with valid sources: no branch in the unrolled body, so loads of
+    // later lags can be issued while earlier lags are being accumulated
+    for (; k0 + TB - 1 <= kfull; k0 += TB) {
+#pragma unroll
+        for (int i = 0; i < TB; i++) lag(k0 + i, i, false);
+    }
+    for (; k0 <= kend; k0 += TB) {
+#pragma unroll
+        for (int i = 0; i < TB; i++)
+            if (k0 + i <= kend) lag(k0 + i, i, true);
+    }
+    double *Fd = (double *)a.far;
+#pragma unroll
+    for (int t = 0; t < TB; t++) {
+        if (t >= a.ntarget) break;
+        double *F = Fd + ((long)t * a.nrhs + r) * 3 * plane2 + off2;
+        F[0] = acc[t][0];
+        F[plane2] = acc[t][1];
+        F[2 * plane2] = acc[t][2];
+    }
+}
+
+// near part of step n = n_b + t, accumulated in place into F[t]
+__global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
+{
+    const MirrorPoint mp = mirror_point(a.Hx, a.Ny, a.Nz);
+    if (!mp.valid) return;
+    const int r = blockIdx.y;
+    const long plane = (long)a.Nz * a.Ny * a.Hx;
+    const long koct = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    const int t = a.t;
+    double2 *F = a.far + ((long)t * a.nrhs + r) * 3 * plane + mp.off;
+    double2 acc[3] = {F[0], F[plane], F[2 * plane]};
+    const double *Kp = a.Khat + mp.koff;
+    const int n = a.nb + t;
+    for (int k = 1; k <= t; k++) {
+        const int j = n - k;
+        if (j < 1) continue;
+        const double2 *J = a.ring_base + ((long)ring_slot(j, a.ring) * a.nrhs + r) * 3 * plane + mp.off;
+        const double2 jv[3] = {J[0], J[plane], J[2 * plane]};
+        const KVal kv = load_k(Kp + (long)(k - 1) * 6 * koct, koct, mp);
+        kmul_acc(kv, jv, acc);
+    }
+    F[0] = acc[0];
+    F[plane] = acc[1];
+    F[2 * plane] = acc[2];
+}
+
+void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
+{
+    const long nocts = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    dim3 grd((unsigned)((nocts + 31) / 32), a.nrhs), blk(256);
+    switch (tb) {
+    case 4: hipLaunchKernelGGL(k_mac_far<4>, grd, blk, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_mac_far<8>, grd, blk, 0, st, a); break;
+    default: throw ArgError("unsupported time block (4 or 8)");
+    }
+    MJ_CHECK(hipGetLastError());
+}
+
+void launch_mac_near(const BlockMacArg &a, hipStream_t st)
+{
+    const long nocts = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    dim3 grd((unsigned)((nocts + 63) / 64), a.nrhs), blk(256);
+    hipLaunchKernelGGL(k_mac_near, grd, blk, 0, st, a);
+    MJ_CHECK(hipGetLastError());
+}
+
 // ---------------------------------------------------------------------------- excitation
 // chi_m times the voxel average of a Gaussian plane wave at c t = n c dt (eq:E), with an
 // 8-point Gauss-Legendre rule along every axis on which the wave varies (the average over an
@@ -169,6 +371,7 @@ __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
         const long o = ((long)r * 3 + c) * M + i;
         e.rhs[o] = rhs;
         e.y[o] = y0;
+        e.uy[o] = sc * y0;
     }
 }
 
@@ -206,8 +409,12 @@ void launch_history_local(const double *Jh, int depth, const double *S, const do
 
 // ---------------------------------------------------------------------------- CG
 // Symmetrised Z_0:  J = D y with D = diag(sqrt(chi)),  A = C_0 - D K_0 D,
-// (A y)_b(m) = c_0(m) y_b(m) - s(m) sum_{D in 27} sum_a K_0^{ba}(D) s(m-D) y_a(m-D).
+// (A z)_b(m) = c_0(m) z_b(m) - s(m) sum_{D in 27} sum_a K_0^{ba}(D) u_a(m-D),   u = s z.
+// K_0(D) = K_0(-D) for every component, so the 26 neighbours are summed in 13 pairs.
 // A is symmetric positive definite; Jacobi preconditioning with diag(A).
+//
+// Reductions: every block writes its partial sums; a one-block kernel per right-hand side adds
+// them in block order and stores the scalars, so the results do not depend on scheduling.
 __constant__ double c_K0[27 * 6];
 
 void upload_stencil(const double *K0_27x6)
@@ -215,37 +422,50 @@ void upload_stencil(const double *K0_27x6)
     MJ_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_K0), K0_27x6, sizeof(double) * 27 * 6));
 }
 
-__device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ x, long i, int u, int v, int z,
+// sum_{D} K_0(D) u(m - D) at voxel i = (x, y, z)
+__device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ u, long i, int x, int y, int z,
                                      double out[3])
 {
     const long M = a.M;
-    const double s = a.schi[i];
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    if (s != 0.0) {
-        int o = 0;
-        for (int dz = -1; dz <= 1; dz++) {
-            const int zz = z - dz;
-            for (int dy = -1; dy <= 1; dy++) {
-                const int yy = v - dy;
-                for (int dx = -1; dx <= 1; dx++, o++) {
-                    const int xx = u - dx;
-                    if (xx < 0 || xx >= a.U || yy < 0 || yy >= a.V || zz < 0 || zz >= a.W) continue;
-                    const long j = ((long)zz * a.V + yy) * a.U + xx;
-                    const double sj = a.schi[j];
-                    if (sj == 0.0) continue;
-                    const double *k = &c_K0[o * 6];
-                    const double x0 = sj * x[j], x1 = sj * x[M + j], x2 = sj * x[2 * M + j];
-                    acc0 += k[0] * x0 + k[3] * x1 + k[4] * x2;
-                    acc1 += k[3] * x0 + k[1] * x1 + k[5] * x2;
-                    acc2 += k[4] * x0 + k[5] * x1 + k[2] * x2;
-                }
-            }
-        }
+    const long sy = a.U, sz = (long)a.U * a.V;
+    double acc0, acc1, acc2;
+    {
+        const double *k = &c_K0[13 * 6];
+        const double u0 = u[i], u1 = u[M + i], u2 = u[2 * M + i];
+        acc0 = k[0] * u0 + k[3] * u1 + k[4] * u2;
+        acc1 = k[3] * u0 + k[1] * u1 + k[5] * u2;
+        acc2 = k[4] * u0 + k[5] * u1 + k[2] * u2;
     }
-    const double c0 = a.c0[i];
-    out[0] = c0 * x[i] - s * acc0;
-    out[1] = c0 * x[M + i] - s * acc1;
-    out[2] = c0 * x[2 * M + i] - s * acc2;
+#pragma unroll
+    for (int o = 14; o < 27; o++) {
+        // entry o = 13 + dx + 3 dy + 9 dz holds K_0(D); its pair is -D
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool m_ok = (x - dx >= 0 && x - dx < a.U) && (y - dy >= 0 && y - dy < a.V) &&
+                          (z - dz >= 0 && z - dz < a.W);
+        const bool p_ok = (x + dx >= 0 && x + dx < a.U) && (y + dy >= 0 && y + dy < a.V) &&
+                          (z + dz >= 0 && z + dz < a.W);
+        const long off = dx + dy * sy + dz * sz;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (m_ok) {
+            const long j = i - off;
+            s0 += u[j];
+            s1 += u[M + j];
+            s2 += u[2 * M + j];
+        }
+        if (p_ok) {
+            const long j = i + off;
+            s0 += u[j];
+            s1 += u[M + j];
+            s2 += u[2 * M + j];
+        }
+        const double *k = &c_K0[o * 6];
+        acc0 += k[0] * s0 + k[3] * s1 + k[4] * s2;
+        acc1 += k[3] * s0 + k[1] * s1 + k[5] * s2;
+        acc2 += k[4] * s0 + k[5] * s1 + k[2] * s2;
+    }
+    out[0] = acc0;
+    out[1] = acc1;
+    out[2] = acc2;
 }
 
 __device__ inline double block_sum(double v, double *sm)
@@ -261,138 +481,146 @@ __device__ inline double block_sum(double v, double *sm)
     return t;   // valid in thread 0
 }
 
-// every block reduces the nblk partials of one right-hand side in a fixed order
-__device__ inline double reduce_partials(const double *__restrict__ part, int nblk, double *sm)
+// Stores this block's NV partial sums (every thread calls it).
+template <int NV>
+__device__ inline void block_partials(const double (&v)[NV], double *part, int nb)
 {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += part[b];
-    v = block_sum(v, sm);
-    if (threadIdx.x == 0) sm[32] = v;
-    __syncthreads();
-    double out = sm[32];
-    __syncthreads();
-    return out;
+    __shared__ double sm[8];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        const double t = block_sum(v[q], sm);
+        if (threadIdx.x == 0) part[(size_t)q * nb + blockIdx.x] = t;
+    }
 }
 
-// r = rhs - A y0, z = M^-1 r, p = q = 0; partials of r.z, r.r, rhs.rhs
+// One block per right-hand side: dst[q] = sum_b part[q][b] in block order.
+__global__ void __launch_bounds__(1024) k_cg_reduce(const double *__restrict__ part, int nb, int nv,
+                                                    CgScalars *scal, int slot0, int slot1, int slot2)
+{
+    __shared__ double sm[16];
+    const int r = blockIdx.x;
+    const double *pr = part + (size_t)r * 3 * nb;
+    double *base = (double *)(scal + r);
+    const int slots[3] = {slot0, slot1, slot2};
+    for (int q = 0; q < nv; q++) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += pr[(size_t)q * nb + b];
+        acc = block_sum(acc, sm);
+        if (threadIdx.x == 0) base[slots[q]] = acc;
+    }
+}
+
+// r = rhs - A y0 (uy = s y0), z = M^-1 r, u = s z, p = q = 0; scalars rz[0], rr, bb
 __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
 {
-    __shared__ double sm[40];
     const int r = blockIdx.y;
     const long M = a.M, base = (long)r * 3 * M;
-    double rz = 0, rr = 0, bb = 0;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x) {
-        const int u = (int)(i % a.U), v = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
-        double Ay[3];
-        stencil_apply(a, a.y + base, i, u, v, z, Ay);
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};   // rz, rr, bb
+    if (i < M) {
+        const double s = a.schi[i];
         const double md = a.inv_diag[i];
+        double Ay[3] = {0.0, 0.0, 0.0};
+        if (s != 0.0) {
+            const int x = (int)(i % a.U), y = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
+            double Ku[3];
+            stencil_apply(a, a.uy + base, i, x, y, z, Ku);
+            const double c0 = a.c0[i];
+            for (int c = 0; c < 3; c++) Ay[c] = c0 * a.y[base + c * M + i] - s * Ku[c];
+        }
         for (int c = 0; c < 3; c++) {
             const long o = base + c * M + i;
             const double b = a.rhs[o];
-            const double rv = a.schi[i] != 0.0 ? b - Ay[c] : 0.0;
+            const double rv = s != 0.0 ? b - Ay[c] : 0.0;
             const double zv = md * rv;
             a.r[o] = rv;
             a.z[o] = zv;
+            a.u[o] = s * zv;
             a.p[o] = 0.0;
             a.q[o] = 0.0;
-            rz += rv * zv;
-            rr += rv * rv;
-            bb += b * b;
+            v[0] += rv * zv;
+            v[1] += rv * rv;
+            v[2] += b * b;
         }
     }
-    const int nb = gridDim.x;
-    double t = block_sum(rz, sm);
-    if (threadIdx.x == 0) a.part_rz[0][r * nb + blockIdx.x] = t;
-    t = block_sum(rr, sm);
-    if (threadIdx.x == 0) a.part_rr[r * nb + blockIdx.x] = t;
-    t = block_sum(bb, sm);
-    if (threadIdx.x == 0) a.part_bb[r * nb + blockIdx.x] = t;
+    block_partials<3>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
 }
 
-// iteration it (first half): beta = rz_it / rz_{it-1} (0 at it = 0); convergence test on
-// r.r; w = A z;  p = z + beta p;  q = w + beta q;  partials of p.q
+// iteration it, first half: convergence test on r.r; beta = rz_it / rz_{it-1} (0 at it = 0);
+// w = A z;  p = z + beta p;  q = w + beta q;  scalar p.q
 __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
 {
-    __shared__ double sm[40];
-    __shared__ int skip;
     const int r = blockIdx.y;
-    const int nb = gridDim.x;
-    // one read of the flag per block, so the whole block takes the same branch
-    if (threadIdx.x == 0) skip = a.done[r];
-    __syncthreads();
-    if (skip) return;
-    const double rz = reduce_partials(a.part_rz[it & 1] + r * nb, nb, sm);
-    const double rr = reduce_partials(a.part_rr + r * nb, nb, sm);
-    const double bb = reduce_partials(a.part_bb + r * nb, nb, sm);
-    const bool conv = rr <= a.tol2 * bb || bb == 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.res[r] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        a.iters[r] = it;
-    }
-    if (conv) {
-        // every block takes the same decision; block 0 records it for the host and later kernels
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.done[r] = 1;
+    CgScalars *sc = a.scal + r;
+    if (a.done[r]) return;
+    const double rr = sc->rr, bb = sc->bb;
+    if (rr <= a.tol2 * bb || bb == 0.0) {
+        // every block takes the same decision; block 0 records it
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.done[r] = 1;
+            a.iters[r] = it;
+            a.res[r] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        }
         return;
     }
-    double beta = 0.0;
-    if (it > 0) {
-        const double rz_old = reduce_partials(a.part_rz[(it + 1) & 1] + r * nb, nb, sm);
-        beta = rz / rz_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.iters[r] = it;
+        a.res[r] = sqrt(rr / bb);
     }
+    const double beta = it > 0 ? sc->rz[it & 1] / sc->rz[(it + 1) & 1] : 0.0;
     const long M = a.M, base = (long)r * 3 * M;
-    double pq = 0.0;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x) {
-        if (a.schi[i] == 0.0) continue;
-        const int u = (int)(i % a.U), v = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
-        double Az[3];
-        stencil_apply(a, a.z + base, i, u, v, z, Az);
-        for (int c = 0; c < 3; c++) {
-            const long o = base + c * M + i;
-            const double pv = a.z[o] + beta * a.p[o];
-            const double qv = Az[c] + beta * a.q[o];
-            a.p[o] = pv;
-            a.q[o] = qv;
-            pq += pv * qv;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < M) {
+        const double s = a.schi[i];
+        if (s != 0.0) {
+            const int x = (int)(i % a.U), y = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
+            double Ku[3];
+            stencil_apply(a, a.u + base, i, x, y, z, Ku);
+            const double c0 = a.c0[i];
+            for (int c = 0; c < 3; c++) {
+                const long o = base + c * M + i;
+                const double zv = a.z[o];
+                const double pv = zv + beta * a.p[o];
+                const double qv = (c0 * zv - s * Ku[c]) + beta * a.q[o];
+                a.p[o] = pv;
+                a.q[o] = qv;
+                v[0] += pv * qv;
+            }
         }
     }
-    const double t = block_sum(pq, sm);
-    if (threadIdx.x == 0) a.part_pq[r * nb + blockIdx.x] = t;
+    block_partials<1>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
 }
 
-// second half: alpha = rz_it / p.q;  y += alpha p;  r -= alpha q;  z = M^-1 r;
-// partials of r.z (into the other buffer) and r.r
+// second half: alpha = rz_it / p.q;  y += alpha p;  r -= alpha q;  z = M^-1 r;  u = s z;
+// scalars rz_{it+1} (other slot) and r.r
 __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
 {
-    __shared__ double sm[40];
-    __shared__ int skip;
     const int r = blockIdx.y;
-    const int nb = gridDim.x;
-    if (threadIdx.x == 0) skip = a.done[r];
-    __syncthreads();
-    if (skip) return;
-    const double rz = reduce_partials(a.part_rz[it & 1] + r * nb, nb, sm);
-    const double pq = reduce_partials(a.part_pq + r * nb, nb, sm);
-    const double alpha = rz / pq;
+    CgScalars *sc = a.scal + r;
+    if (a.done[r]) return;
+    const double alpha = sc->rz[it & 1] / sc->pq;
     const long M = a.M, base = (long)r * 3 * M;
-    double rz2 = 0.0, rr = 0.0;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x) {
-        if (a.schi[i] == 0.0) continue;
-        const double md = a.inv_diag[i];
-        for (int c = 0; c < 3; c++) {
-            const long o = base + c * M + i;
-            a.y[o] += alpha * a.p[o];
-            const double rv = a.r[o] - alpha * a.q[o];
-            const double zv = md * rv;
-            a.r[o] = rv;
-            a.z[o] = zv;
-            rz2 += rv * zv;
-            rr += rv * rv;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < M) {
+        const double s = a.schi[i];
+        if (s != 0.0) {
+            const double md = a.inv_diag[i];
+            for (int c = 0; c < 3; c++) {
+                const long o = base + c * M + i;
+                a.y[o] += alpha * a.p[o];
+                const double rv = a.r[o] - alpha * a.q[o];
+                const double zv = md * rv;
+                a.r[o] = rv;
+                a.z[o] = zv;
+                a.u[o] = s * zv;
+                v[0] += rv * zv;
+                v[1] += rv * rv;
+            }
         }
     }
-    double t = block_sum(rz2, sm);
-    if (threadIdx.x == 0) a.part_rz[(it + 1) & 1][r * nb + blockIdx.x] = t;
-    t = block_sum(rr, sm);
-    if (threadIdx.x == 0) a.part_rr[r * nb + blockIdx.x] = t;
+    block_partials<2>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
 }
 
 // J_n = sqrt(chi) y into the real-space ring (and optionally the caller's output)
@@ -411,20 +639,29 @@ __global__ void k_cg_finish(const double *__restrict__ y, const double *__restri
         }
 }
 
+// slot indices of CgScalars viewed as double[5]: rz[0], rz[1], pq, rr, bb
+static void launch_reduce(const CgArg &a, int nv, int s0, int s1, int s2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_reduce, dim3(a.nrhs), dim3(1024), 0, st, a.part, a.nblk, nv, a.scal, s0, s1, s2);
+    MJ_CHECK(hipGetLastError());
+}
 void launch_cg_init(const CgArg &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_init, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a);
     MJ_CHECK(hipGetLastError());
+    launch_reduce(a, 3, 0, 3, 4, st);            // rz[0], rr, bb
 }
 void launch_cg_a(const CgArg &a, int it, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_a, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a, it);
     MJ_CHECK(hipGetLastError());
+    launch_reduce(a, 1, 2, 2, 2, st);            // pq
 }
 void launch_cg_b(const CgArg &a, int it, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_b, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a, it);
     MJ_CHECK(hipGetLastError());
+    launch_reduce(a, 2, (it + 1) & 1, 3, 3, st); // rz[(it+1)&1], rr
 }
 void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, double *J, double *Jout,
                       hipStream_t st)

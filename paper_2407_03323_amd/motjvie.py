@@ -185,10 +185,10 @@ class Solver:
         return out
 
     def stats(self) -> dict:
-        out = np.zeros(10)
-        self._check(self._lib.mj_stats(self._h, _dptr(out), 10))
+        out = np.zeros(13)
+        self._check(self._lib.mj_stats(self._h, _dptr(out), 13))
         keys = ["fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms", "z0_ms", "step_ms", "cg_iters",
-                "cg_res_max", "steps", "cg_iters_max"]
+                "cg_res_max", "steps", "cg_iters_max", "far_launch_ms", "far_launches", "near_launch_ms"]
         return dict(zip(keys, out.tolist()))
 
     def fft_roundtrip(self, x, X=None, y=None):

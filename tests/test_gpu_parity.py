@@ -120,18 +120,18 @@ def _rel(a, b):
     return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
 
 
-@pytest.mark.parametrize("with_fir", [False, True])
-def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir):
+@pytest.mark.parametrize("with_fir,tb", [(False, 1), (True, 1), (False, 8), (True, 4)])
+def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir, tb):
     """P_{n-1} through FFT -> spectral MAC -> inverse FFT (+ local and FIR terms) against the
     direct sum, random history over all ell lags, heterogeneous eps."""
     from oracle import mot
     torch = torch_cuda
-    say("history sum 8^3 fir=%s" % with_fir)
+    say("history sum 8^3 fir=%s time_block=%d" % (with_fir, tb))
     U = 8
     eps = wl.random_eps(U, U, U, 21, 1.0, 12.0)
     fir = wl.binomial_highpass(17, 0.1) if with_fir else np.zeros(0)
     prob = wl.Problem("hs", U, U, U, eps, [], 1, fir=fir)
-    s = make_solver(prob, n_rhs=1)
+    s = make_solver(prob, n_rhs=1, time_block=tb)
     ell = s.ell
     depth = max(ell, len(fir) - 1)
     Jh = wl.random_history(U, U, U, depth, 99)
@@ -149,12 +149,14 @@ def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir):
 
 
 # ----------------------------------------------------------------------------- march
-def test_march_matches_oracle_C1(torch_cuda, c1_oracle):
-    """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8."""
+@pytest.mark.parametrize("tb", [1, 4, 8])
+def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb):
+    """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8, with and without
+    time blocking of the history sum."""
     torch = torch_cuda
-    say("march C1")
+    say("march C1 time_block=%d" % tb)
     prob, o, Jref = c1_oracle
-    s = make_solver(prob)
+    s = make_solver(prob, time_block=tb)
     Jt = torch.zeros((prob.n_steps, 1, 3, 8, 8, 8), dtype=torch.float64, device="cuda")
     s.run(prob.n_steps, Jt)
     torch.cuda.synchronize()
