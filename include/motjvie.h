@@ -65,7 +65,7 @@ typedef struct {
     int32_t n_rhs;            /* number of right-hand sides (plane waves) marched together, >= 1 */
     double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-12 */
     int32_t cg_maxit;         /* <= 0 selects 200 */
-    int32_t time_block;       /* steps per time block of the history MAC: 1 (none), 4 or 8; 0 selects 8 */
+    int32_t time_block;       /* steps per time block of the history MAC: 1 (none), 4, 8, 16 or 32; 0 selects the default */
     void *stream;             /* hipStream_t to enqueue on; NULL = the null stream */
     int32_t quad_order;       /* Gauss-Legendre points per cell of the kernel quadrature; 0 selects 16 */
 } mj_config;

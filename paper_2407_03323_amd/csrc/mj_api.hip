@@ -26,7 +26,7 @@ __global__ void k_extract_octant(const double2 *__restrict__ X, int Hx, int Ny, 
     if (t >= n) return;
     const int kx = (int)(t % Hx), qy = (int)((t / Hx) % Nyo), qz = (int)(t / ((long)Hx * Nyo));
     const long plane = (long)Nz * Ny * Hx;
-    for (int c = 0; c < 6; c++) out[c * n + t] = scale * X[c * plane + ((long)qz * Ny + qy) * Hx + kx].x;
+    for (int c = 0; c < 6; c++) out[6 * t + c] = scale * X[c * plane + ((long)qz * Ny + qy) * Hx + kx].x;
 }
 
 struct Events {
@@ -60,7 +60,7 @@ struct mj_solver {
     int B = 1;
     int nquad = 16;
     hipStream_t st = nullptr;
-    int nloc = 3, rdepth = 4;
+    int nloc = 5, rdepth = 6;
     // device state
     size_t bytes = 0;
     std::vector<void *> allocs;
@@ -69,16 +69,13 @@ struct mj_solver {
     double *Khat = nullptr;
     double2 *ring = nullptr, *Shat = nullptr, *farbuf = nullptr;
     double *S = nullptr, *Jr = nullptr;
-    double *rhs = nullptr, *y = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *rhs = nullptr, *y = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     double *u = nullptr, *uy = nullptr;
     double *parts = nullptr;
     unsigned *counters = nullptr;
     mj::CgScalars *scal = nullptr;
     int cg_guess = 8;
-    int *done = nullptr, *iters = nullptr;
-    double *res = nullptr;
-    int *done_h = nullptr, *iters_h = nullptr;
-    double *res_h = nullptr;
+    mj::CgStatus *cgstat = nullptr, *cgstat_h = nullptr;
     mj::WaveArg *waves_d = nullptr;
     bool waves_set = false;
     std::vector<mj::WaveArg> waves;
@@ -114,9 +111,7 @@ struct mj_solver {
         mj::fft3d_free(fft);
         if (gen.moments) (void)hipFree(gen.moments);
         for (void *a : allocs) (void)hipFree(a);
-        if (done_h) (void)hipHostFree(done_h);
-        if (iters_h) (void)hipHostFree(iters_h);
-        if (res_h) (void)hipHostFree(res_h);
+        if (cgstat_h) (void)hipHostFree(cgstat_h);
     }
 
     long spec_plane() const { return (long)Nz * Ny * Hx; }
@@ -166,8 +161,9 @@ void mj_solver::create(const mj_config &c)
     Nz = mj::fft_pick_size(2 * W - 1);
     Hx = Nx / 2 + 1;
     B = c.time_block > 0 ? c.time_block : 8;
-    if (B != 1 && B != 4 && B != 8) throw ArgError("time_block must be 0 (auto), 1, 4 or 8");
-    nloc = std::max(3, (int)fir.size() - 1);
+    if (B != 1 && B != 4 && B != 8 && B != 16 && B != 32)
+        throw ArgError("time_block must be 0 (auto), 1, 4, 8, 16 or 32");
+    nloc = std::max(5, (int)fir.size() - 1);   // >= 5: the solve's initial guess uses five steps
     rdepth = nloc + 1;
 
     // material
@@ -212,23 +208,25 @@ void mj_solver::create(const mj_config &c)
     rhs = dalloc<double>((size_t)nrhs * 3 * M, "cg rhs");
     y = dalloc<double>((size_t)nrhs * 3 * M, "cg y");
     r = dalloc<double>((size_t)nrhs * 3 * M, "cg r");
-    z = dalloc<double>((size_t)nrhs * 3 * M, "cg z");
     p = dalloc<double>((size_t)nrhs * 3 * M, "cg p");
     q = dalloc<double>((size_t)nrhs * 3 * M, "cg q");
-    u = dalloc<double>((size_t)nrhs * 3 * M, "cg u");
-    uy = dalloc<double>((size_t)nrhs * 3 * M, "cg uy");
+    // the first iteration of every solve scales p and q by beta = 0: they must be finite
+    MJ_CHECK(hipMemset(p, 0, sizeof(double) * nrhs * 3 * M));
+    MJ_CHECK(hipMemset(q, 0, sizeof(double) * nrhs * 3 * M));
+    const size_t Mp = (size_t)(U + 2) * (V + 2) * (W + 2);
+    u = dalloc<double>((size_t)nrhs * 3 * Mp, "cg u");
+    uy = dalloc<double>((size_t)nrhs * 3 * Mp, "cg uy");
+    // the one-voxel halo of u and uy is never written and stays zero
+    MJ_CHECK(hipMemset(u, 0, sizeof(double) * nrhs * 3 * Mp));
+    MJ_CHECK(hipMemset(uy, 0, sizeof(double) * nrhs * 3 * Mp));
     nblk = (int)((M + 255) / 256);
     parts = dalloc<double>((size_t)3 * nrhs * nblk, "cg partials");
     counters = dalloc<unsigned>(nrhs, "cg counters");
     MJ_CHECK(hipMemset(counters, 0, sizeof(unsigned) * nrhs));
     scal = dalloc<mj::CgScalars>(nrhs, "cg scalars");
-    done = dalloc<int>(nrhs, "cg flags");
-    iters = dalloc<int>(nrhs, "cg iterations");
-    res = dalloc<double>(nrhs, "cg residuals");
+    cgstat = dalloc<mj::CgStatus>(nrhs, "cg status");
     waves_d = dalloc<mj::WaveArg>(nrhs, "waves");
-    MJ_CHECK(hipHostMalloc((void **)&done_h, sizeof(int) * nrhs, hipHostMallocDefault));
-    MJ_CHECK(hipHostMalloc((void **)&iters_h, sizeof(int) * nrhs, hipHostMallocDefault));
-    MJ_CHECK(hipHostMalloc((void **)&res_h, sizeof(double) * nrhs, hipHostMallocDefault));
+    MJ_CHECK(hipHostMalloc((void **)&cgstat_h, sizeof(mj::CgStatus) * nrhs, hipHostMallocDefault));
     mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz);
     bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hx + (size_t)3 * nrhs * W * Ny * Hx);
     n = 0;
@@ -318,6 +316,7 @@ void mj_solver::solve_z0()
     a.U = U;
     a.V = V;
     a.W = W;
+    a.Mp = (long)(U + 2) * (V + 2) * (W + 2);
     a.nrhs = nrhs;
     a.nblk = nblk;
     a.tol2 = cg_rtol * cg_rtol;
@@ -328,17 +327,13 @@ void mj_solver::solve_z0()
     a.uy = uy;
     a.y = y;
     a.r = r;
-    a.z = z;
     a.p = p;
     a.q = q;
     a.u = u;
     a.part = parts;
     a.scal = scal;
-    a.done = done;
-    a.iters = iters;
-    a.res = res;
-    MJ_CHECK(hipMemsetAsync(done, 0, sizeof(int) * nrhs, st));
-    mj::launch_cg_init(a, st);
+    a.stat = cgstat;
+    mj::launch_cg_init(a, st);   // also clears the status records
     // enqueue as many iterations as the last solve needed before the first look at the
     // convergence flags; kernels after convergence return at once
     int it = 0;
@@ -350,20 +345,21 @@ void mj_solver::solve_z0()
             mj::launch_cg_a(a, it, st);
             mj::launch_cg_b(a, it, st);
         }
-        MJ_CHECK(hipMemcpyAsync(done_h, done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipMemcpyAsync(cgstat_h, cgstat, sizeof(mj::CgStatus) * nrhs, hipMemcpyDeviceToHost, st));
         MJ_CHECK(hipStreamSynchronize(st));
         all_done = true;
-        for (int i = 0; i < nrhs; i++) all_done = all_done && done_h[i];
+        for (int i = 0; i < nrhs; i++) all_done = all_done && cgstat_h[i].done;
         batch = 2;
     }
-    // one more test records the final residual (and the flag, if the last update converged)
-    if (!all_done) mj::launch_cg_a(a, it, st);
-    MJ_CHECK(hipMemcpyAsync(done_h, done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-    MJ_CHECK(hipMemcpyAsync(iters_h, iters, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-    MJ_CHECK(hipMemcpyAsync(res_h, res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    MJ_CHECK(hipStreamSynchronize(st));
+    if (!all_done) {
+        // out of iterations: one more test records the final residual (and the flag, if the
+        // last update converged)
+        mj::launch_cg_a(a, it, st);
+        MJ_CHECK(hipMemcpyAsync(cgstat_h, cgstat, sizeof(mj::CgStatus) * nrhs, hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipStreamSynchronize(st));
+    }
     int mx = 0;
-    for (int i = 0; i < nrhs; i++) mx = std::max(mx, iters_h[i]);
+    for (int i = 0; i < nrhs; i++) mx = std::max(mx, cgstat_h[i].iters);
     cg_guess = mx + 1;
 }
 
@@ -483,10 +479,10 @@ void mj_solver::run(int n_steps, double *Jout)
                              Jout ? Jout + (size_t)s * nrhs * 3 * M : nullptr, st);
         MJ_CHECK(hipEventRecord(ev[5], st));
         for (int i = 0; i < nrhs; i++) {
-            cg_iter_sum += iters_h[i];
-            cg_iter_max = std::max(cg_iter_max, (double)iters_h[i]);
-            cg_res_max = std::max(cg_res_max, res_h[i]);
-            if (!done_h[i]) noconv = true;
+            cg_iter_sum += cgstat_h[i].iters;
+            cg_iter_max = std::max(cg_iter_max, (double)cgstat_h[i].iters);
+            cg_res_max = std::max(cg_res_max, cgstat_h[i].res);
+            if (!cgstat_h[i].done) noconv = true;
         }
     }
     MJ_CHECK(hipStreamSynchronize(st));

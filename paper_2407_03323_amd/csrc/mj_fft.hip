@@ -7,8 +7,9 @@
 // box part of the inverse is kept.
 //
 // Each 1-D pass loads a tile of pencils into LDS, runs a Stockham autosort FFT
-// (decimation in time, natural-order output) stage by stage between two LDS
-// buffers, and writes the tile back.  Pencils along y and z are strided in
+// (decimation in time, natural-order output) stage by stage in place (each stage
+// reads its butterflies into registers, synchronises, writes them back), and
+// writes the tile back.  Pencils along y and z are strided in
 // memory; a tile covers consecutive x-frequencies so every global access is a
 // run of consecutive complex values.  The x pass packs two real rows into one
 // complex pencil (real and imaginary part) and separates the two half-spectra
@@ -21,6 +22,7 @@
 
 #include "mj_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace mj {
@@ -28,7 +30,6 @@ namespace mj {
 namespace {
 
 constexpr int kThreads = 256;
-static const int kRadices[] = {8, 4, 2, 3, 5, 7, 11, 13};
 
 __device__ inline double2 tw_at(const double2 *tw, int m, bool inv)
 {
@@ -55,45 +56,93 @@ __device__ inline void dft_small(double2 *v, const double2 *tw, int N, bool inv)
         v[1] = cadd(d02, r);
         v[3] = csub(d02, r);
     } else {
+        // odd R: pair inputs t and R - t.  With a_t = v_t + v_{R-t}, b_t = v_t - v_{R-t},
+        // c_m = cos(2 pi m / R), s_m = sin(2 pi m / R) and sg = -1 (forward) or +1 (inverse):
+        //   out_q     = v_0 + sum_t a_t c_{qt} + i sg sum_t b_t s_{qt}
+        //   out_{R-q} = v_0 + sum_t a_t c_{qt} - i sg sum_t b_t s_{qt}     (q, t = 1 .. (R-1)/2)
+        static_assert(R % 2 == 1, "even radices other than 2 and 4 are not used");
+        constexpr int H = (R - 1) / 2;
         const int st = N / R;
-        double2 o[R];
+        double cm[H + 1], sm[H + 1];
 #pragma unroll
-        for (int q = 0; q < R; q++) {
-            double2 acc = v[0];
-#pragma unroll
-            for (int t = 1; t < R; t++) {
-                double2 w = tw_at(tw, ((q * t) % R) * st, inv);
-                acc.x += v[t].x * w.x - v[t].y * w.y;
-                acc.y += v[t].x * w.y + v[t].y * w.x;
-            }
-            o[q] = acc;
+        for (int m = 1; m <= H; m++) {
+            const double2 w = tw[m * st];   // exp(-2 pi i m / R)
+            cm[m] = w.x;
+            sm[m] = -w.y;
         }
+        double2 a[H + 1], b[H + 1];
+        double2 sum = v[0];
 #pragma unroll
-        for (int q = 0; q < R; q++) v[q] = o[q];
+        for (int t = 1; t <= H; t++) {
+            a[t] = cadd(v[t], v[R - t]);
+            b[t] = csub(v[t], v[R - t]);
+            sum = cadd(sum, a[t]);
+        }
+        const double sg = inv ? 1.0 : -1.0;
+        const double2 v0 = v[0];
+        v[0] = sum;
+#pragma unroll
+        for (int q = 1; q <= H; q++) {
+            double2 A = v0, B = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int t = 1; t <= H; t++) {
+                const int m = (q * t) % R;
+                // cos is even and sin odd about R/2: fold m into 1 .. H
+                const double c = m <= H ? cm[m] : cm[R - m];
+                const double sn = m <= H ? sm[m] : -sm[R - m];
+                A.x += a[t].x * c;
+                A.y += a[t].y * c;
+                B.x += b[t].x * sn;
+                B.y += b[t].y * sn;
+            }
+            // i sg B = (-sg B.y, sg B.x)
+            const double2 iB = make_double2(-sg * B.y, sg * B.x);
+            v[q] = cadd(A, iB);
+            v[R - q] = csub(A, iB);
+        }
     }
 }
 
-// One Stockham stage on P pencils of length N stored with leading dimension ld.
+// A tile holds at most kTileElems complex values (P pencils of length N, P * N <= kTileElems).
+constexpr int kTileElems = 2048;
+static_assert(kMaxFftN <= kTileElems, "one pencil must fit a tile");
+
+// One Stockham stage, in place, on P pencils of length N stored with leading dimension ld.
+// Every thread first reads and transforms all of its butterflies (at most BF of them), the
+// block synchronises, and only then are the results written back over the inputs; the caller
+// synchronises again before the next stage.
 template <int R>
-__device__ void stage(const double2 *src, double2 *dst, int N, int Ns, int P, int ld, const double2 *tw,
-                      bool inv)
+__device__ void stage(double2 *buf, int N, int Ns, int P, int ld, const double2 *tw, bool inv)
 {
+    constexpr int BF = (kTileElems / R + kThreads - 1) / kThreads;
     const int nb = N / R;
     const int step = N / (Ns * R);
-    for (int b = threadIdx.x; b < P * nb; b += blockDim.x) {
-        int p = b / nb, j = b - p * nb;
-        const double2 *s = src + p * ld;
-        double2 v[R];
-        int jm = j % Ns;
+    const int total = P * nb;
+    double2 v[BF][R];
 #pragma unroll
-        for (int r = 0; r < R; r++) v[r] = s[j + r * nb];
+    for (int f = 0; f < BF; f++) {
+        const int b = (int)threadIdx.x + f * kThreads;
+        if (b < total) {
+            const int p = b / nb, j = b - p * nb, jm = j % Ns;
+            const double2 *s = buf + p * ld;
 #pragma unroll
-        for (int r = 1; r < R; r++) v[r] = cmul(v[r], tw_at(tw, jm * r * step, inv));
-        dft_small<R>(v, tw, N, inv);
-        int base = (j / Ns) * Ns * R + jm;
-        double2 *d = dst + p * ld;
+            for (int r = 0; r < R; r++) v[f][r] = s[j + r * nb];
 #pragma unroll
-        for (int r = 0; r < R; r++) d[base + r * Ns] = v[r];
+            for (int r = 1; r < R; r++) v[f][r] = cmul(v[f][r], tw_at(tw, jm * r * step, inv));
+            dft_small<R>(v[f], tw, N, inv);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < BF; f++) {
+        const int b = (int)threadIdx.x + f * kThreads;
+        if (b < total) {
+            const int p = b / nb, j = b - p * nb, jm = j % Ns;
+            const int base = (j / Ns) * Ns * R + jm;
+            double2 *d = buf + p * ld;
+#pragma unroll
+            for (int r = 0; r < R; r++) d[base + r * Ns] = v[f][r];
+        }
     }
 }
 
@@ -102,35 +151,51 @@ struct PlanArg {
     int radix[kMaxStages];
 };
 
-// Runs all stages; returns the LDS buffer holding the result (a or b).
-__device__ double2 *lds_fft(double2 *a, double2 *b, int P, int ld, const PlanArg &pl, const double2 *tw, bool inv)
+// Runs all stages in place on the tile in buf.
+__device__ void lds_fft(double2 *buf, int P, int ld, const PlanArg &pl, const double2 *tw, bool inv)
 {
     int Ns = 1;
-    double2 *src = a, *dst = b;
     for (int s = 0; s < pl.nst; s++) {
         int R = pl.radix[s];
         switch (R) {
-        case 2: stage<2>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        case 3: stage<3>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        case 4: stage<4>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        case 5: stage<5>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        case 7: stage<7>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        case 8: stage<8>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        case 11: stage<11>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
-        default: stage<13>(src, dst, pl.N, Ns, P, ld, tw, inv); break;
+        case 2: stage<2>(buf, pl.N, Ns, P, ld, tw, inv); break;
+        case 3: stage<3>(buf, pl.N, Ns, P, ld, tw, inv); break;
+        case 4: stage<4>(buf, pl.N, Ns, P, ld, tw, inv); break;
+        case 5: stage<5>(buf, pl.N, Ns, P, ld, tw, inv); break;
+        case 7: stage<7>(buf, pl.N, Ns, P, ld, tw, inv); break;
+        case 11: stage<11>(buf, pl.N, Ns, P, ld, tw, inv); break;
+        default: stage<13>(buf, pl.N, Ns, P, ld, tw, inv); break;   // the plan holds only 2, 3, 4, 5, 7, 11, 13
         }
         __syncthreads();
         Ns *= R;
-        double2 *t = src;
-        src = dst;
-        dst = t;
     }
-    return src;
 }
 
 __device__ inline void load_twiddles(double2 *tw_s, const double2 *tw, int N)
 {
     for (int i = threadIdx.x; i < N; i += blockDim.x) tw_s[i] = tw[i];
+}
+
+// Moves a tile from global memory into LDS: every thread first issues kBatch independent
+// loads (get(i) for items i = i0 + u * kThreads + tid), then stores them (put(i, v)), so
+// that the loads of a thread overlap instead of each waiting out the memory latency.
+constexpr int kBatch = 8;
+template <typename T, class Get, class Put>
+__device__ inline void gather_tile(int total, Get get, Put put)
+{
+    for (int i0 = 0; i0 < total; i0 += kThreads * kBatch) {
+        T v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+            const int i = i0 + u * kThreads + (int)threadIdx.x;
+            v[u] = i < total ? get(i) : T{};
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+            const int i = i0 + u * kThreads + (int)threadIdx.x;
+            if (i < total) put(i, v[u]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------- x pass
@@ -143,7 +208,6 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
     const int N = pl.N, ld = N + 1;
     double2 *tw_s = sm;
     double2 *a = sm + N;
-    double2 *b = a + P * ld;
     load_twiddles(tw_s, tw, N);
     const int row0 = blockIdx.x * (2 * P);
     // load: pencil p takes rows row0 + 2p (real part) and row0 + 2p + 1 (imaginary part)
@@ -152,17 +216,20 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
         a[p * ld + n] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * P * U; i += blockDim.x) {
-        int rr = i / U, u = i - rr * U;
-        int row = row0 + rr;
-        if (row < nrows) {
-            double v = x[(size_t)row * U + u];
+    gather_tile<double>(
+        2 * P * U,
+        [&](int i) {
+            const int rr = i / U, u = i - rr * U, row = row0 + rr;
+            return row < nrows ? x[(size_t)row * U + u] : 0.0;
+        },
+        [&](int i, double v) {
+            const int rr = i / U, u = i - rr * U;
             double2 *slot = &a[(rr >> 1) * ld + u];
             if (rr & 1) slot->y = v; else slot->x = v;
-        }
-    }
+        });
     __syncthreads();
-    double2 *res = lds_fft(a, b, P, ld, pl, tw_s, false);
+    lds_fft(a, P, ld, pl, tw_s, false);
+    const double2 *res = a;
     // separate: Xa[k] = (Z[k] + conj Z[N-k]) / 2, Xb[k] = (Z[k] - conj Z[N-k]) / (2i)
     for (int i = threadIdx.x; i < 2 * P * Hx; i += blockDim.x) {
         int rr = i / Hx, k = i - rr * Hx;
@@ -185,26 +252,32 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
     const int N = pl.N, ld = N + 1;
     double2 *tw_s = sm;
     double2 *a = sm + N;
-    double2 *b = a + P * ld;
     load_twiddles(tw_s, tw, N);
     const int row0 = blockIdx.x * (2 * P);
     // Z[k] = Xa[k] + i Xb[k] for k <= N/2, Z[N-k] = conj(Xa[k]) + i conj(Xb[k]) for 0 < k < N/2
-    for (int i = threadIdx.x; i < P * N; i += blockDim.x) {
-        int p = i / N, n = i - p * N;
-        int ra = row0 + 2 * p, rb = ra + 1;
-        double2 xa = make_double2(0, 0), xb = make_double2(0, 0);
-        int k = n <= N / 2 ? n : N - n;
-        bool conj = n > N / 2;
-        if (ra < nrows) xa = X[(size_t)ra * Hx + k];
-        if (rb < nrows) xb = X[(size_t)rb * Hx + k];
-        if (conj) {
-            xa.y = -xa.y;
-            xb.y = -xb.y;
-        }
-        a[p * ld + n] = make_double2(xa.x - xb.y, xa.y + xb.x);
-    }
+    gather_tile<double4>(
+        P * N,
+        [&](int i) {
+            const int p = i / N, n = i - p * N;
+            const int ra = row0 + 2 * p, rb = ra + 1;
+            const int k = n <= N / 2 ? n : N - n;
+            double2 xa = make_double2(0, 0), xb = make_double2(0, 0);
+            if (ra < nrows) xa = X[(size_t)ra * Hx + k];
+            if (rb < nrows) xb = X[(size_t)rb * Hx + k];
+            return make_double4(xa.x, xa.y, xb.x, xb.y);
+        },
+        [&](int i, double4 v) {
+            const int p = i / N, n = i - p * N;
+            double2 xa = make_double2(v.x, v.y), xb = make_double2(v.z, v.w);
+            if (n > N / 2) {
+                xa.y = -xa.y;
+                xb.y = -xb.y;
+            }
+            a[p * ld + n] = make_double2(xa.x - xb.y, xa.y + xb.x);
+        });
     __syncthreads();
-    double2 *res = lds_fft(a, b, P, ld, pl, tw_s, true);
+    lds_fft(a, P, ld, pl, tw_s, true);
+    const double2 *res = a;
     for (int i = threadIdx.x; i < 2 * P * U; i += blockDim.x) {
         int rr = i / U, u = i - rr * U;
         int row = row0 + rr;
@@ -232,7 +305,6 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restr
     const int N = pl.N, ld = N + 1;
     double2 *tw_s = sm;
     double2 *a = sm + N;
-    double2 *b = a + P * ld;
     load_twiddles(tw_s, tw, N);
     const int ntile = (g.Hx + P - 1) / P;
     const int tile = blockIdx.x % ntile;
@@ -241,14 +313,19 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restr
     const int kx0 = tile * P;
     const int np = min(P, g.Hx - kx0);
     const double2 *src = in + c * g.cs_in + q * g.qs_in + kx0;
-    for (int i = threadIdx.x; i < P * N; i += blockDim.x) {
-        int n = i / P, p = i - n * P;
-        double2 v = make_double2(0.0, 0.0);
-        if (n < g.n_in && p < np) v = src[(long)n * g.es_in + p];
-        a[p * ld + n] = v;
-    }
+    gather_tile<double2>(
+        P * N,
+        [&](int i) {
+            const int n = i / P, p = i - n * P;
+            return (n < g.n_in && p < np) ? src[(long)n * g.es_in + p] : make_double2(0.0, 0.0);
+        },
+        [&](int i, double2 v) {
+            const int n = i / P, p = i - n * P;
+            a[p * ld + n] = v;
+        });
     __syncthreads();
-    double2 *res = lds_fft(a, b, P, ld, pl, tw_s, inv != 0);
+    lds_fft(a, P, ld, pl, tw_s, inv != 0);
+    const double2 *res = a;
     double2 *dst = out + c * g.cs_out + q * g.qs_out + kx0;
     for (int i = threadIdx.x; i < P * g.n_out; i += blockDim.x) {
         int n = i / P, p = i - n * P;
@@ -265,9 +342,9 @@ PlanArg plan_arg(const FftPlan1D &p)
     return a;
 }
 
-int pencils_per_block(int N) { return N <= 64 ? 16 : (N <= 128 ? 12 : 8); }
+int pencils_per_block(int N) { return std::max(1, std::min(16, kTileElems / N)); }
 
-size_t lds_bytes(int N, int P) { return sizeof(double2) * (size_t)(N + 2 * P * (N + 1)); }
+size_t lds_bytes(int N, int P) { return sizeof(double2) * (size_t)(N + P * (N + 1)); }
 
 bool factor(int N, std::vector<int> &out)
 {

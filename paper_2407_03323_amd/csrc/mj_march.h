@@ -8,7 +8,7 @@ namespace mj {
 constexpr int kMaxLocal = 64;   // largest history depth kept in real space
 
 struct MacArg {
-    const double *Khat;      // [nk][6][Nz/2+1][Ny/2+1][Hx] real, lags 1..nk
+    const double *Khat;      // [nk][Nz/2+1][Ny/2+1][Hx][6] real, lags 1..nk
     const double2 *ring_base;// [ring][nrhs][3][Nz][Ny][Hx]
     double2 *Shat;           // [nrhs][3][Nz][Ny][Hx]
     int Hx, Ny, Nz;
@@ -19,7 +19,7 @@ struct MacArg {
 };
 
 struct BlockMacArg {
-    const double *Khat;        // [ell][6][Nz/2+1][Ny/2+1][Hx]
+    const double *Khat;        // [ell][Nz/2+1][Ny/2+1][Hx][6]
     const double2 *ring_base;  // [ring][nrhs][3][Nz][Ny][Hx]
     double2 *far;              // [TB][nrhs][3][Nz][Ny][Hx]
     int Hx, Ny, Nz;
@@ -45,13 +45,14 @@ struct EpiArg {
     const double *chi, *schi, *inv_eps;
     const double *fir;       // device taps (nfir)
     int nfir;
-    int nloc;                // local history depth used (>= 3)
+    int nloc;                // local history depth used (>= 5)
     int slot_of[kMaxLocal + 1];  // real-ring slot of J_{n-k}, k = 1..nloc
     const double *Jring;     // [depth][nrhs][3][M]
     const double *S;         // [nrhs][3][M] convolution (normalised) or NULL at n = 1
     const WaveArg *waves;    // [nrhs]
     double glx8[8], glw8[8]; // 8-point rule on [-1/2, 1/2], weights summing to 1
-    double *rhs, *y, *uy;    // [nrhs][3][M]; uy = sqrt(chi) y
+    double *rhs, *y;         // [nrhs][3][M]
+    double *uy;              // sqrt(chi) y0 in the zero-haloed layout [nrhs][3][(W+2)(V+2)(U+2)]
 };
 
 struct CgScalars {
@@ -59,18 +60,25 @@ struct CgScalars {
     double pq, rr, bb;
 };
 
+// per right-hand side, read back by the host in one copy
+struct CgStatus {
+    int done;                // converged (set by the first iteration whose test passes)
+    int iters;               // iterations taken
+    double res;              // relative residual |r| / |b| at the last test
+};
+
 struct CgArg {
     long M;
     int U, V, W;
+    long Mp;                 // (U+2)(V+2)(W+2): vectors read by the stencil carry a zero halo
     int nrhs, nblk;          // nblk = ceil(M / 256): one voxel per thread
     double tol2;
     const double *schi, *c0, *inv_diag;
-    const double *rhs, *uy;
-    double *y, *r, *z, *p, *q, *u;
+    const double *rhs, *uy;  // uy, u: haloed layout [nrhs][3][Mp]
+    double *y, *r, *p, *q, *u;
     double *part;            // [nrhs][3][nblk]
     CgScalars *scal;         // [nrhs]
-    int *done, *iters;
-    double *res;
+    CgStatus *stat;          // [nrhs]
 };
 
 void launch_mac(const MacArg &a, hipStream_t st);

@@ -12,6 +12,8 @@ namespace mj {
 // Khat_k is real and has a definite parity in every frequency axis (K^aa even, K^ab odd in
 // D_a and D_b), so only the octant ky <= Ny/2, kz <= Nz/2 is stored and one load serves the
 // four mirror points (ky, Ny-ky) x (kz, Nz-kz) with sign flips on the odd components.
+// Layout [lag][octant point][xx, yy, zz, xy, xz, yz]: the six values of a point are one
+// 48-byte record.
 // One thread per octant point; G right-hand sides per thread share every Khat load.
 template <int G>
 __global__ void __launch_bounds__(256) k_mac(MacArg a)
@@ -48,11 +50,11 @@ __global__ void __launch_bounds__(256) k_mac(MacArg a)
             for (int c = 0; c < 3; c++) acc[g][p][c] = make_double2(0.0, 0.0);
 
     const long koct = (long)Hx * Nyo * Nzo;
-    const double *Kp = a.Khat + t;
+    const double *Kp = a.Khat + 6 * t;
     for (int k = 1; k <= a.nk; k++) {
         const double *Kk = Kp + (long)(k - 1) * 6 * koct;
-        const double kxx = Kk[0], kyy = Kk[koct], kzz = Kk[2 * koct];
-        const double kxy = Kk[3 * koct], kxz = Kk[4 * koct], kyz = Kk[5 * koct];
+        const double kxx = Kk[0], kyy = Kk[1], kzz = Kk[2];
+        const double kxy = Kk[3], kxz = Kk[4], kyz = Kk[5];
         int slot = a.slot_nm1 - (k - 1);
         slot %= a.ring;
         if (slot < 0) slot += a.ring;
@@ -119,7 +121,7 @@ void launch_mac(const MacArg &a, hipStream_t st)
 struct MirrorPoint {
     bool valid;
     long off;      // offset in one spectrum component [Nz][Ny][Hx]
-    long koff;     // offset in one Khat octant component
+    long koff;     // octant point index (its Khat record starts at 6 koff)
     double sy, sz; // parity signs of the odd components
 };
 
@@ -148,15 +150,18 @@ struct KVal {
     double xx, yy, zz, xy, xz, yz;
 };
 
-__device__ inline KVal load_k(const double *__restrict__ Kk, long koct, const MirrorPoint &mp)
+// the six values of one octant point (Kk points at its record)
+__device__ inline KVal load_k(const double *__restrict__ Kk, const MirrorPoint &mp)
 {
+    const double2 *K2 = (const double2 *)Kk;
+    const double2 a = K2[0], b = K2[1], c = K2[2];
     KVal k;
-    k.xx = Kk[0];
-    k.yy = Kk[koct];
-    k.zz = Kk[2 * koct];
-    k.xy = Kk[3 * koct] * mp.sy;
-    k.xz = Kk[4 * koct] * mp.sz;
-    k.yz = Kk[5 * koct] * mp.sy * mp.sz;
+    k.xx = a.x;
+    k.yy = a.y;
+    k.zz = b.x;
+    k.xy = b.y * mp.sy;
+    k.xz = c.x * mp.sz;
+    k.yz = c.y * mp.sy * mp.sz;
     return k;
 }
 
@@ -177,18 +182,27 @@ __device__ inline int ring_slot(int j, int ring)
 }
 
 // Far part.  Khat is real, so the real and imaginary parts of Jhat never mix: each lane
-// takes one part of one mirror point (lanes 2i, 2i+1 = real, imaginary of point i), which
-// halves the registers per lane.  The lag loop is unrolled by TB so that the sliding source
-// window lives in registers with compile-time slot indices: the source of lag k goes to slot
-// (k - 1) mod TB, and target t at lag k reads the slot written at lag k - t.
-template <int TB>
+// takes one part of one mirror point, which halves the registers per lane.  The TB = TG * G
+// targets of the block are split into G groups of TG over the lanes of a wave (group g owns
+// targets g TG .. g TG + TG - 1), so the registers per lane grow with TG, not TB.  For group
+// g, lag k is its local lag k' = k - g TG: the lag loop is unrolled by TG so that the sliding
+// source window lives in registers with compile-time slot indices; the source of local lag
+// k' (J at n_b - k') goes to slot (k - 1) mod TG and local target tt at lag k reads the slot
+// written at lag k - tt.  A group's sources are those of group 0 TG lags earlier, so the
+// extra loads hit in cache; K_k is the same for every group.
+template <int TG, int G, int PD>
 __global__ void __launch_bounds__(256) k_mac_far(BlockMacArg a)
 {
+    static_assert(64 % (2 * G) == 0, "lanes split evenly into groups");
+    static_assert(TG % PD == 0, "the prefetch buffers rotate with the slot window");
+    constexpr int kLanesPerGroup = 64 / G;
+    constexpr int kPointsPerWave = kLanesPerGroup / 2;
     const int Nyo = a.Ny / 2 + 1, Nzo = a.Nz / 2 + 1;
     const long nocts = (long)a.Hx * Nyo * Nzo;
     const int lane = threadIdx.x & 63;
-    const long o = blockIdx.x * 32L + (lane >> 1);
-    const int part = lane & 1;
+    const int g = lane / kLanesPerGroup, li = lane % kLanesPerGroup;
+    const long o = blockIdx.x * (long)kPointsPerWave + (li >> 1);
+    const int part = li & 1;
     const int m = threadIdx.x >> 6;
     if (o >= nocts) return;
     const int kx = (int)(o % a.Hx), qy = (int)((o / a.Hx) % Nyo), qz = (int)(o / ((long)a.Hx * Nyo));
@@ -200,63 +214,106 @@ __global__ void __launch_bounds__(256) k_mac_far(BlockMacArg a)
     const int r = blockIdx.y;
     const long plane2 = 2L * a.Nz * a.Ny * a.Hx;                           // one component, in doubles
     const long koct = nocts;
-    const double *ringd = (const double *)a.ring_base;
-    double acc[TB][3], jw[TB][3];
+    const int tg0 = g * TG;                                                // first target of the group
+    constexpr int TB = TG * G;
+    double acc[TG][3], jw[TG][3];
 #pragma unroll
-    for (int t = 0; t < TB; t++)
+    for (int t = 0; t < TG; t++)
 #pragma unroll
         for (int c = 0; c < 3; c++) acc[t][c] = jw[t][c] = 0.0;
-    const double *Kp = a.Khat + o;
-    const double *Jbase = ringd + (long)r * 3 * plane2 + off2;
-    const long slot_stride = (long)a.nrhs * 3 * plane2;
-    // one lag: source j = n_b - k into slot i (zero if j < 1, i.e. before the march started),
-    // then every target t takes slot (i - t) mod TB, the source of lag k - t
-    auto lag = [&](int k, int i, bool guard) {
-        const int j = a.nb - k;
-        if (!guard || j >= 1) {
-            const double *J = Jbase + (long)ring_slot(j, a.ring) * slot_stride;
-            jw[i][0] = J[0];
-            jw[i][1] = J[plane2];
-            jw[i][2] = J[2 * plane2];
-        } else {
-            jw[i][0] = jw[i][1] = jw[i][2] = 0.0;
-        }
-        const double *Kk = Kp + (long)(k - 1) * 6 * koct;
-        const double kxx = Kk[0], kyy = Kk[koct], kzz = Kk[2 * koct];
-        const double kxy = Kk[3 * koct] * sy, kxz = Kk[4 * koct] * sz, kyz = Kk[5 * koct] * sy * sz;
+    const unsigned joff = (unsigned)(off2 * 8), koff = (unsigned)(o * 48);
+    const char *Jbase = (const char *)((const double *)a.ring_base + (long)r * 3 * plane2);
+    const long slot_bytes = (long)a.nrhs * 3 * plane2 * 8, plane_bytes = plane2 * 8, koct_bytes = koct * 8;
+    const char *Kbase = (const char *)a.Khat;
+    // accumulate lag k with its source already in slot i: local target tt takes slot
+    // (i - tt) mod TG, the source of lag k - tt
+    auto accumulate = [&](int i, const double kv[6]) {
+        const double kxx = kv[0], kyy = kv[1], kzz = kv[2];
+        const double kxy = kv[3] * sy, kxz = kv[4] * sz, kyz = kv[5] * sy * sz;
 #pragma unroll
-        for (int t = 0; t < TB; t++) {
-            const int sl = (i - t + TB) % TB;
+        for (int t = 0; t < TG; t++) {
+            const int sl = (i - t + TG) % TG;
             const double j0 = jw[sl][0], j1 = jw[sl][1], j2 = jw[sl][2];
-            acc[t][0] += kxx * j0 + kxy * j1 + kxz * j2;
-            acc[t][1] += kxy * j0 + kyy * j1 + kyz * j2;
-            acc[t][2] += kxz * j0 + kyz * j1 + kzz * j2;
+            acc[t][0] = fma(kxz, j2, fma(kxy, j1, fma(kxx, j0, acc[t][0])));
+            acc[t][1] = fma(kyz, j2, fma(kyy, j1, fma(kxy, j0, acc[t][1])));
+            acc[t][2] = fma(kzz, j2, fma(kyz, j1, fma(kxz, j0, acc[t][2])));
         }
     };
-    // lags up to n_b - 1 have a source for every slot; later lags (at most TB - 1 of them, only
-    // early in the march) still feed targets t >= 1 through older slots
+    // loads of lag k: the lane's source sits in ring slot `slot`; ok = false (no source: the
+    // lag is a near lag of the group, or the source precedes the march) gives zeros
+    auto load_lag = [&](int k, int slot, bool ok, double jv[3], double kv[6]) {
+        const char *J = Jbase + slot * slot_bytes;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const double v = *(const double *)(J + c * plane_bytes + joff);
+            jv[c] = ok ? v : 0.0;
+        }
+        const double2 *K2 = (const double2 *)(Kbase + (long)(k - 1) * 6 * koct_bytes + koff);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const double2 v = K2[c];
+            kv[2 * c] = v.x;
+            kv[2 * c + 1] = v.y;
+        }
+    };
+    // lags up to n_b - 1 have a source for every group (group 0's source n_b - k >= 1); later
+    // lags (at most TB - 1 of them, only early in the march) still feed later targets
     const int kfull = min(a.nk, a.nb - 1);
     const int kend = min(a.nk, a.nb - 2 + TB);
     int k0 = 1;
-    // full groups of TB lags with valid sources: no branch in the unrolled body, so loads of
-    // later lags can be issued while earlier lags are being accumulated
-    for (; k0 + TB - 1 <= kfull; k0 += TB) {
+    // full groups of TG lags, software-pipelined by one lag: the loads of lag k + 1 are in
+    // flight while lag k is accumulated (the ring slot of the lane's source steps down by one
+    // per lag)
+    const int kgroups = kfull >= TG ? (kfull / TG) * TG : 0;
+    if (kgroups > 0) {
+        // PD lags in flight: buffer b = (k - 1) mod PD holds the loads of lag k
+        int slot = ring_slot(a.nb - 1 + tg0, a.ring);
+        double pj[PD][3], pk[PD][6];
 #pragma unroll
-        for (int i = 0; i < TB; i++) lag(k0 + i, i, false);
+        for (int d = 0; d < PD; d++) {
+            const int kd = 1 + d <= kgroups ? 1 + d : kgroups;
+            load_lag(kd, slot, kd > tg0, pj[d], pk[d]);
+            if (d + 1 < PD) slot = slot == 0 ? a.ring - 1 : slot - 1;
+        }
+        for (; k0 + TG - 1 <= kgroups; k0 += TG) {
+#pragma unroll
+            for (int i = 0; i < TG; i++) {
+                const int bi = i % PD;
+                double kv[6];
+#pragma unroll
+                for (int c = 0; c < 3; c++) jw[i][c] = pj[bi][c];
+#pragma unroll
+                for (int c = 0; c < 6; c++) kv[c] = pk[bi][c];
+                const int kn = k0 + i + PD;
+                slot = slot == 0 ? a.ring - 1 : slot - 1;
+                // past the last group this reloads a valid lag; the values are not used
+                load_lag(kn <= kgroups ? kn : kgroups, slot, kn > tg0, pj[bi], pk[bi]);
+                // keep the scheduler from sinking these loads down to their use
+                __builtin_amdgcn_sched_barrier(0);
+                accumulate(i, kv);
+            }
+        }
     }
-    for (; k0 <= kend; k0 += TB) {
+    for (; k0 <= kend; k0 += TG) {
 #pragma unroll
-        for (int i = 0; i < TB; i++)
-            if (k0 + i <= kend) lag(k0 + i, i, true);
+        for (int i = 0; i < TG; i++) {
+            const int k = k0 + i;
+            if (k > kend) break;
+            const int j = a.nb - k + tg0;
+            double kv[6];
+            load_lag(k, ring_slot(j, a.ring), k > tg0 && j >= 1, jw[i], kv);
+            accumulate(i, kv);
+        }
     }
     double *Fd = (double *)a.far;
 #pragma unroll
-    for (int t = 0; t < TB; t++) {
+    for (int tt = 0; tt < TG; tt++) {
+        const int t = tg0 + tt;
         if (t >= a.ntarget) break;
         double *F = Fd + ((long)t * a.nrhs + r) * 3 * plane2 + off2;
-        F[0] = acc[t][0];
-        F[plane2] = acc[t][1];
-        F[2 * plane2] = acc[t][2];
+        F[0] = acc[tt][0];
+        F[plane2] = acc[tt][1];
+        F[2 * plane2] = acc[tt][2];
     }
 }
 
@@ -271,15 +328,22 @@ __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
     const int t = a.t;
     double2 *F = a.far + ((long)t * a.nrhs + r) * 3 * plane + mp.off;
     double2 acc[3] = {F[0], F[plane], F[2 * plane]};
-    const double *Kp = a.Khat + mp.koff;
+    const double *Kp = a.Khat + 6 * mp.koff;
     const int n = a.nb + t;
-    for (int k = 1; k <= t; k++) {
-        const int j = n - k;
-        if (j < 1) continue;
-        const double2 *J = a.ring_base + ((long)ring_slot(j, a.ring) * a.nrhs + r) * 3 * plane + mp.off;
-        const double2 jv[3] = {J[0], J[plane], J[2 * plane]};
-        const KVal kv = load_k(Kp + (long)(k - 1) * 6 * koct, koct, mp);
-        kmul_acc(kv, jv, acc);
+    // lags beyond the kernel's support (k > nk) contribute nothing; sources before the
+    // march started (j < 1) are zero.  Two lags per pass so their loads overlap.
+    const int kmax = min(t, a.nk);
+    for (int k = 1; k <= kmax; k += 2) {
+        const bool two = k + 1 <= kmax;
+        const int j0 = n - k, j1 = n - k - 1;
+        const double2 *J0 = a.ring_base + ((long)ring_slot(j0, a.ring) * a.nrhs + r) * 3 * plane + mp.off;
+        const double2 *J1 = a.ring_base + ((long)ring_slot(two ? j1 : j0, a.ring) * a.nrhs + r) * 3 * plane + mp.off;
+        double2 jv0[3] = {J0[0], J0[plane], J0[2 * plane]};
+        double2 jv1[3] = {J1[0], J1[plane], J1[2 * plane]};
+        const KVal kv0 = load_k(Kp + (long)(k - 1) * 6 * koct, mp);
+        const KVal kv1 = load_k(Kp + (long)(two ? k : k - 1) * 6 * koct, mp);
+        if (j0 >= 1) kmul_acc(kv0, jv0, acc);
+        if (two && j1 >= 1) kmul_acc(kv1, jv1, acc);
     }
     F[0] = acc[0];
     F[plane] = acc[1];
@@ -289,11 +353,15 @@ __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
 {
     const long nocts = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
-    dim3 grd((unsigned)((nocts + 31) / 32), a.nrhs), blk(256);
+    // TB = TG * G targets per launch; points per block = 32 / G
+    auto grid = [&](int G) { return dim3((unsigned)((nocts + 32 / G - 1) / (32 / G)), a.nrhs); };
+    const dim3 blk(256);
     switch (tb) {
-    case 4: hipLaunchKernelGGL(k_mac_far<4>, grd, blk, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_mac_far<8>, grd, blk, 0, st, a); break;
-    default: throw ArgError("unsupported time block (4 or 8)");
+    case 4: hipLaunchKernelGGL((k_mac_far<4, 1, 2>), grid(1), blk, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_mac_far<8, 1, 2>), grid(1), blk, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_mac_far<8, 2, 2>), grid(2), blk, 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_mac_far<8, 4, 2>), grid(4), blk, 0, st, a); break;
+    default: throw ArgError("unsupported time block (4, 8, 16 or 32)");
     }
     MJ_CHECK(hipGetLastError());
 }
@@ -361,17 +429,21 @@ __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
         double rhs = sc > 0.0 ? b / sc : 0.0;
         double y0 = 0.0;
         if (sc > 0.0) {
-            const double inv = 1.0 / sc;
-            double y1 = 0, y2 = 0, y3 = 0;
-            if (e.n - 1 >= 1) y1 = e.Jring[(((long)e.slot_of[1] * e.nrhs + r) * 3 + c) * M + i] * inv;
-            if (e.n - 2 >= 1) y2 = e.Jring[(((long)e.slot_of[2] * e.nrhs + r) * 3 + c) * M + i] * inv;
-            if (e.n - 3 >= 1) y3 = e.Jring[(((long)e.slot_of[3] * e.nrhs + r) * 3 + c) * M + i] * inv;
-            y0 = 3.0 * y1 - 3.0 * y2 + y3;
+            // initial guess of the Z_0 solve: the quartic through the last five solutions
+            // (the current is smooth in time, so this lands close to y_n)
+            constexpr double cx[5] = {5.0, -10.0, 10.0, -5.0, 1.0};
+            double g = 0.0;
+#pragma unroll
+            for (int k = 1; k <= 5; k++)
+                if (e.n - k >= 1) g += cx[k - 1] * e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
+            y0 = g / sc;
         }
         const long o = ((long)r * 3 + c) * M + i;
         e.rhs[o] = rhs;
         e.y[o] = y0;
-        e.uy[o] = sc * y0;
+        const long Mp = (long)(e.U + 2) * (e.V + 2) * (e.W + 2);
+        const long ip = ((long)(z + 1) * (e.V + 2) + (v + 1)) * (e.U + 2) + (u + 1);
+        e.uy[((long)r * 3 + c) * Mp + ip] = sc * y0;
     }
 }
 
@@ -422,16 +494,15 @@ void upload_stencil(const double *K0_27x6)
     MJ_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_K0), K0_27x6, sizeof(double) * 27 * 6));
 }
 
-// sum_{D} K_0(D) u(m - D) at voxel i = (x, y, z)
-__device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ u, long i, int x, int y, int z,
-                                     double out[3])
+// sum_{D} K_0(D) u(m - D) at haloed index ip (the halo of u is zero, so no bounds tests)
+__device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ u, long ip, double out[3])
 {
-    const long M = a.M;
-    const long sy = a.U, sz = (long)a.U * a.V;
+    const long Mp = a.Mp;
+    const long sy = a.U + 2, sz = (long)(a.U + 2) * (a.V + 2);
     double acc0, acc1, acc2;
     {
         const double *k = &c_K0[13 * 6];
-        const double u0 = u[i], u1 = u[M + i], u2 = u[2 * M + i];
+        const double u0 = u[ip], u1 = u[Mp + ip], u2 = u[2 * Mp + ip];
         acc0 = k[0] * u0 + k[3] * u1 + k[4] * u2;
         acc1 = k[3] * u0 + k[1] * u1 + k[5] * u2;
         acc2 = k[4] * u0 + k[5] * u1 + k[2] * u2;
@@ -440,24 +511,10 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
     for (int o = 14; o < 27; o++) {
         // entry o = 13 + dx + 3 dy + 9 dz holds K_0(D); its pair is -D
         const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        const bool m_ok = (x - dx >= 0 && x - dx < a.U) && (y - dy >= 0 && y - dy < a.V) &&
-                          (z - dz >= 0 && z - dz < a.W);
-        const bool p_ok = (x + dx >= 0 && x + dx < a.U) && (y + dy >= 0 && y + dy < a.V) &&
-                          (z + dz >= 0 && z + dz < a.W);
         const long off = dx + dy * sy + dz * sz;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        if (m_ok) {
-            const long j = i - off;
-            s0 += u[j];
-            s1 += u[M + j];
-            s2 += u[2 * M + j];
-        }
-        if (p_ok) {
-            const long j = i + off;
-            s0 += u[j];
-            s1 += u[M + j];
-            s2 += u[2 * M + j];
-        }
+        const double s0 = u[ip - off] + u[ip + off];
+        const double s1 = u[Mp + ip - off] + u[Mp + ip + off];
+        const double s2 = u[2 * Mp + ip - off] + u[2 * Mp + ip + off];
         const double *k = &c_K0[o * 6];
         acc0 += k[0] * s0 + k[3] * s1 + k[4] * s2;
         acc1 += k[3] * s0 + k[1] * s1 + k[5] * s2;
@@ -466,6 +523,12 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
     out[0] = acc0;
     out[1] = acc1;
     out[2] = acc2;
+}
+
+__device__ inline long haloed(const CgArg &a, long i)
+{
+    const int x = (int)(i % a.U), y = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
+    return ((long)(z + 1) * (a.V + 2) + (y + 1)) * (a.U + 2) + (x + 1);
 }
 
 __device__ inline double block_sum(double v, double *sm)
@@ -510,21 +573,22 @@ __global__ void __launch_bounds__(1024) k_cg_reduce(const double *__restrict__ p
     }
 }
 
-// r = rhs - A y0 (uy = s y0), z = M^-1 r, u = s z, p = q = 0; scalars rz[0], rr, bb
+// r = rhs - A y0 (uy = s y0), u = s M^-1 r; scalars rz[0], rr, bb (z = M^-1 r is never stored)
 __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
 {
     const int r = blockIdx.y;
     const long M = a.M, base = (long)r * 3 * M;
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};   // rz, rr, bb
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[r] = CgStatus{0, 0, 0.0};
     if (i < M) {
         const double s = a.schi[i];
         const double md = a.inv_diag[i];
         double Ay[3] = {0.0, 0.0, 0.0};
+        const long ip = haloed(a, i), bp = (long)r * 3 * a.Mp;
         if (s != 0.0) {
-            const int x = (int)(i % a.U), y = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
             double Ku[3];
-            stencil_apply(a, a.uy + base, i, x, y, z, Ku);
+            stencil_apply(a, a.uy + bp, ip, Ku);
             const double c0 = a.c0[i];
             for (int c = 0; c < 3; c++) Ay[c] = c0 * a.y[base + c * M + i] - s * Ku[c];
         }
@@ -534,10 +598,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
             const double rv = s != 0.0 ? b - Ay[c] : 0.0;
             const double zv = md * rv;
             a.r[o] = rv;
-            a.z[o] = zv;
-            a.u[o] = s * zv;
-            a.p[o] = 0.0;
-            a.q[o] = 0.0;
+            a.u[bp + c * a.Mp + ip] = s * zv;
             v[0] += rv * zv;
             v[1] += rv * rv;
             v[2] += b * b;
@@ -552,20 +613,20 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
 {
     const int r = blockIdx.y;
     CgScalars *sc = a.scal + r;
-    if (a.done[r]) return;
+    if (a.stat[r].done) return;
     const double rr = sc->rr, bb = sc->bb;
     if (rr <= a.tol2 * bb || bb == 0.0) {
         // every block takes the same decision; block 0 records it
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.done[r] = 1;
-            a.iters[r] = it;
-            a.res[r] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            a.stat[r].done = 1;
+            a.stat[r].iters = it;
+            a.stat[r].res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         }
         return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.iters[r] = it;
-        a.res[r] = sqrt(rr / bb);
+        a.stat[r].iters = it;
+        a.stat[r].res = sqrt(rr / bb);
     }
     const double beta = it > 0 ? sc->rz[it & 1] / sc->rz[(it + 1) & 1] : 0.0;
     const long M = a.M, base = (long)r * 3 * M;
@@ -574,13 +635,13 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
     if (i < M) {
         const double s = a.schi[i];
         if (s != 0.0) {
-            const int x = (int)(i % a.U), y = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
             double Ku[3];
-            stencil_apply(a, a.u + base, i, x, y, z, Ku);
-            const double c0 = a.c0[i];
+            stencil_apply(a, a.u + (long)r * 3 * a.Mp, haloed(a, i), Ku);
+            const double c0 = a.c0[i], md = a.inv_diag[i];
             for (int c = 0; c < 3; c++) {
                 const long o = base + c * M + i;
-                const double zv = a.z[o];
+                const double zv = md * a.r[o];
+                // at it = 0, beta = 0 and p, q hold finite values of the previous solve
                 const double pv = zv + beta * a.p[o];
                 const double qv = (c0 * zv - s * Ku[c]) + beta * a.q[o];
                 a.p[o] = pv;
@@ -592,13 +653,13 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
     block_partials<1>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
 }
 
-// second half: alpha = rz_it / p.q;  y += alpha p;  r -= alpha q;  z = M^-1 r;  u = s z;
+// second half: alpha = rz_it / p.q;  y += alpha p;  r -= alpha q;  u = s M^-1 r;
 // scalars rz_{it+1} (other slot) and r.r
 __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
 {
     const int r = blockIdx.y;
     CgScalars *sc = a.scal + r;
-    if (a.done[r]) return;
+    if (a.stat[r].done) return;
     const double alpha = sc->rz[it & 1] / sc->pq;
     const long M = a.M, base = (long)r * 3 * M;
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -607,14 +668,14 @@ __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
         const double s = a.schi[i];
         if (s != 0.0) {
             const double md = a.inv_diag[i];
+            const long up = (long)r * 3 * a.Mp + haloed(a, i);
             for (int c = 0; c < 3; c++) {
                 const long o = base + c * M + i;
                 a.y[o] += alpha * a.p[o];
                 const double rv = a.r[o] - alpha * a.q[o];
                 const double zv = md * rv;
                 a.r[o] = rv;
-                a.z[o] = zv;
-                a.u[o] = s * zv;
+                a.u[up + c * a.Mp] = s * zv;
                 v[0] += rv * zv;
                 v[1] += rv * rv;
             }

@@ -120,7 +120,7 @@ def _rel(a, b):
     return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
 
 
-@pytest.mark.parametrize("with_fir,tb", [(False, 1), (True, 1), (False, 8), (True, 4)])
+@pytest.mark.parametrize("with_fir,tb", [(False, 1), (True, 1), (False, 8), (True, 4), (True, 16)])
 def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir, tb):
     """P_{n-1} through FFT -> spectral MAC -> inverse FFT (+ local and FIR terms) against the
     direct sum, random history over all ell lags, heterogeneous eps."""
@@ -149,7 +149,7 @@ def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir, tb):
 
 
 # ----------------------------------------------------------------------------- march
-@pytest.mark.parametrize("tb", [1, 4, 8])
+@pytest.mark.parametrize("tb", [1, 4, 8, 16, 32])
 def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb):
     """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8, with and without
     time blocking of the history sum."""
@@ -166,3 +166,71 @@ def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb):
     say("  rel L2", err, "cg iters", st["cg_iters"], "res", st["cg_res_max"])
     assert err <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("tb", [1, 4, 8, 16])
+def test_march_short_support(torch_cuda, tb):
+    """4 x 3 x 3 heterogeneous block with a 3-tap FIR: the kernel support (ell = 6 lags) is
+    shorter than the time block, so the near part must stop at the last lag."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n = 4, 3, 3, 60
+    say("march 4x3x3 time_block=%d" % tb)
+    eps = wl.random_eps(U, V, W, 17, 2.0, 10.0)
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("short", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 3.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1))
+    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    ref = mot.Oracle(prob, K=K).run(n)
+    s = make_solver(prob, time_block=tb)
+    assert s.ell < 8
+    Jt = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    s.run(n, Jt)
+    torch.cuda.synchronize()
+    err = _rel(Jt.cpu().numpy()[:, 0], ref)
+    say("  ell", s.ell, "rel L2", err)
+    assert err <= 1e-8
+    s.close()
+
+
+def _three_waves(U, V, W):
+    """Three different Gaussian plane waves: direction, polarisation, width and delay differ."""
+    dirs = [(0.0, 0.0, 1.0), (1.0, 0.0, 0.0), (0.0, 0.6, 0.8)]
+    pols = [(1.0, 0.0, 0.0), (0.0, 0.0, 1.0), (1.0, 0.0, 0.0)]
+    sig = [3.0, 4.0, 2.5]
+    return [wl.gaussian_wave(U, V, W, np.array(d), np.array(q), s_) for d, q, s_ in zip(dirs, pols, sig)]
+
+
+@pytest.mark.parametrize("tb", [1, 8, 16])
+def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb):
+    """Three right-hand sides marched together: each equals its own single-RHS march (the
+    per-RHS arithmetic is the same, so to rounding) and the oracle's march."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n = 6, 5, 4, 60
+    say("batched rhs 6x5x4 time_block=%d" % tb)
+    eps = wl.random_eps(U, V, W, 5, 1.0, 8.0)
+    waves = _three_waves(U, V, W)
+    fir = wl.binomial_highpass(5, 0.1)
+    prob = wl.Problem("batch", U, V, W, eps, waves, n, fir=fir)
+    s = make_solver(prob, time_block=tb)
+    Jb = torch.zeros((n, 3, 3, W, V, U), dtype=torch.float64, device="cuda")
+    s.run(n, Jb)
+    torch.cuda.synchronize()
+    Jb = Jb.cpu().numpy()
+    s.close()
+    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    for i, w in enumerate(waves):
+        p1 = wl.Problem("single", U, V, W, eps, [w], n, fir=fir)
+        s1 = make_solver(p1, time_block=tb)
+        J1 = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+        s1.run(n, J1)
+        torch.cuda.synchronize()
+        J1 = J1.cpu().numpy()[:, 0]
+        s1.close()
+        ref = mot.Oracle(p1, K=K).run(n)
+        e_single = _rel(Jb[:, i], J1)
+        e_oracle = _rel(Jb[:, i], ref)
+        say("  rhs", i, "vs single", e_single, "vs oracle", e_oracle)
+        assert e_single <= 1e-13
+        assert e_oracle <= 1e-8
