@@ -51,6 +51,8 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.or_conv_pairs.argtypes = [ctypes.c_double, ctypes.c_int, ip, ctypes.c_long, ip, ctypes.c_long, dp,
                                     ctypes.c_int, dp]
+        L.or_probe_kernels.argtypes = [ctypes.c_double, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_long,
+                                       ctypes.c_int, dp]
         L.or_box_integrals.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.or_plane_integral.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,

@@ -122,6 +122,36 @@ def conv_pairs(targets, sources, Js: np.ndarray, ngl: int = 16, r: float = 1.0) 
     return out
 
 
+def probe_kernels(probes, sources, kmax: int, ngl: int = 16, r: float = 1.0) -> np.ndarray:
+    """Kp[p][s][k][6] = K_k(r_p - r_s), k = 0..kmax, for probe points [np][3] (units of h from
+    the grid corner) and integer source voxels [ns][3] (centres at +1/2): eq:Z tested on a
+    virtual voxel centred at the probe."""
+    P = np.ascontiguousarray(np.asarray(probes, dtype=np.float64).reshape(-1, 3))
+    s = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((len(P), len(s), kmax + 1, 6))
+    lib().or_probe_kernels(r, int(kmax), dptr(P), len(P), iptr(s), len(s), int(ngl), dptr(out))
+    return out
+
+
+def probe_field(Kp: np.ndarray, J: np.ndarray, sources) -> np.ndarray:
+    """Scattered field at the probes, E^s_p(n) = sum_{k=0}^{kmax} sum_s K_k(r_p - r_s) J_{n-k}(s)
+    for n = 1..N (eps_0 = 1; J_{n'} = 0 for n' <= 0).  The scattered field of the
+    formulation (Sec. 2.1) is -J + S(J); the tested kernel K of eq:Z is S minus its local
+    part J, so K alone gives E^s at any test voxel, inside the scatterer or not.
+    J[n-1] = J_n with shape [N][3][W][V][U]; returns [N][np][3]."""
+    src = np.asarray(sources, dtype=np.int64).reshape(-1, 3)
+    Js = J[:, :, src[:, 2], src[:, 1], src[:, 0]]            # [N][3][ns]
+    N = J.shape[0]
+    kmax = Kp.shape[2] - 1
+    # full symmetric 3x3 per (p, s, k)
+    Kf = Kp[..., np.array(COMP).ravel()].reshape(Kp.shape[:3] + (3, 3))   # [np][ns][k][b][a]
+    E = np.zeros((N, Kp.shape[0], 3))
+    for n in range(1, N + 1):
+        for k in range(0, min(kmax, n - 1) + 1):
+            E[n - 1] += np.einsum("psba,as->pb", Kf[:, :, k], Js[n - 1 - k])
+    return E
+
+
 def history_sum(K: np.ndarray, Jh: np.ndarray, eps: np.ndarray, fir: np.ndarray, ell_: int) -> np.ndarray:
     """P_{n-1} = sum_{k>=1} Z^delta_k J_{n-k} (eq:PnMOT with Sec. 5.1's taps) for a history
     Jh[k-1] = J_{n-k}, k = 1..depth (missing lags count as zero currents):

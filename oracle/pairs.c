@@ -52,3 +52,43 @@ void or_conv_pairs(double r, int nlag, const int *tgt, long nt, const int *src, 
         for (int b = 0; b < 3; b++) out[b * nt + it] = acc[b];
     }
 }
+
+/*
+ * Kernel values seen from virtual test voxels (side h, centred at arbitrary points: the
+ * probes) for a list of source voxels, every lag k = 0..kmax computed on the spot:
+ *
+ *   out[p][s][k][6] = K_k(r_p - r_s),   r_s = source centre (u + 1/2, v + 1/2, w + 1/2)
+ *
+ * with zeros outside the lag support of the pair.  The scattered field at the probe is then
+ * E^s_p(n) = sum_k sum_s K_k(r_p - r_s) J_{n-k}(s): the scattered-field operator of the
+ * formulation (Sec. 2.1) tested like eq:Z on a voxel that is not part of the grid.
+ *
+ *   probe [np][3]  points in units of h from the grid corner
+ *   src   [ns][3]  integer voxel coordinates (u, v, w)
+ */
+void or_probe_kernels(double r, int kmax, const double *probe, long np, const int *src, long ns, int ngl,
+                      double *out)
+{
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (long ip = 0; ip < np; ip++)
+        for (long is = 0; is < ns; is++) {
+            double D[3], a2 = 0.0, b2 = 0.0;
+            for (int i = 0; i < 3; i++) {
+                D[i] = probe[3 * ip + i] - ((double)src[3 * is + i] + 0.5);
+                double d = fabs(D[i]);
+                double m = d - 1.0 > 0.0 ? d - 1.0 : 0.0;
+                a2 += m * m;
+                b2 += (d + 1.0) * (d + 1.0);
+            }
+            double rmin = sqrt(a2), rmax = sqrt(b2);
+            double *o = out + ((ip * ns + is) * (long)(kmax + 1)) * 6;
+            for (int k = 0; k <= kmax; k++) {
+                double *K = o + 6 * k;
+                if (!(r * (k + 1) > rmin && r * (k - 2) < rmax)) {
+                    for (int c = 0; c < 6; c++) K[c] = 0.0;
+                    continue;
+                }
+                or_kernel_entry(r, k, D[0], D[1], D[2], ngl, K);
+            }
+        }
+}

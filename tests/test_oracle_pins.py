@@ -431,3 +431,102 @@ def test_fir17_stabilises_without_distorting():
     assert np.abs(J1).max() < 1.5 * a0
     assert np.abs(J1[-10:]).max() < 0.2 * a0
     assert np.abs(J1 - J0).max() < 0.05 * a0
+
+
+# ----------------------------------------------------------------------------- off-grid offsets
+# Probes see the grid from a virtual test voxel at an arbitrary point, so the kernels are
+# needed at non-integer offsets D.  The same identities pin them there.
+NEAR_REAL = [(1.3, -0.7, 0.45), (2.61, 1.17, -0.38), (0.0, 0.0, 1.75)]
+# the virtual voxel overlapping a source voxel off-centre: 1/R is singular inside the
+# overlap away from every symmetry plane and the quadrature reaches only ~1e-9 there
+OVERLAP_REAL = (0.5, 0.25, 0.0)
+FAR_REAL = [(4.37, -2.81, 1.55), (7.2, 3.9, -5.45), (11.5, 0.5, 0.5)]
+
+
+@pytest.mark.parametrize("D", NEAR_REAL + FAR_REAL[:1])
+def test_static_sum_equals_newell_offgrid(D):
+    Ks = kernel_lags(D)
+    N = pins.newell_tensor(D)
+    assert np.abs(Ks.sum(0) + N).max() < 5e-14
+
+
+@pytest.mark.parametrize("D", FAR_REAL)
+def test_static_sum_far_field_offgrid(D):
+    Ks = kernel_lags(D)
+    ref = pins.overlap_gl(D, pins.static_second_derivative)
+    assert np.abs(Ks.sum(0) - ref).max() < 1e-11 * np.abs(Ks).max()
+
+
+@pytest.mark.parametrize("D", NEAR_REAL + FAR_REAL)
+def test_first_moment_offgrid(D):
+    Ks = kernel_lags(D)
+    k = np.arange(len(Ks))[:, None]
+    assert np.abs((k * Ks).sum(0) - 0.5 * Ks.sum(0)).max() < 1e-11 * np.abs(Ks).max()
+
+
+@pytest.mark.parametrize("D", FAR_REAL)
+def test_second_moment_far_field_offgrid(D):
+    Ks = kernel_lags(D)
+    k = np.arange(len(Ks))[:, None]
+    static = pins.overlap_gl(D, pins.static_second_derivative)
+    ref = 0.5 * static - pins.overlap_gl(D, pins.second_moment_integrand)
+    assert np.abs((k ** 2 * Ks).sum(0) - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("D", NEAR_REAL + FAR_REAL[:1])
+def test_trace_identity_offgrid(D):
+    """tr sum_k K_k(D) = -Lam(D): the delta of the Laplacian picks the overlap of the cubes."""
+    Ks = kernel_lags(D)
+    lam = np.prod([max(1.0 - abs(d), 0.0) for d in D])
+    assert abs(Ks.sum(0)[:3].sum() + lam) < 1e-13
+
+
+def test_offgrid_parity_and_continuity():
+    """K^aa is even and K^ab odd in D_a and D_b at any offset; K is continuous in D, so an
+    offset 1e-9 from a grid point gives the grid point's values."""
+    D = (2.3, -1.4, 0.6)
+    for k in range(0, 7):
+        K = mot.kernel_entry(k, D)
+        Km = mot.kernel_entry(k, (-D[0], D[1], D[2]))
+        assert np.allclose(Km, K * np.array([1, 1, 1, -1, -1, 1]), rtol=0, atol=1e-15 * max(1, np.abs(K).max()))
+    for k in range(0, 6):
+        a = mot.kernel_entry(k, (3, 1, 2))
+        b = mot.kernel_entry(k, (3 + 1e-9, 1 - 1e-9, 2 + 1e-9))
+        assert np.abs(a - b).max() < 1e-7 * max(np.abs(a).max(), 1e-3)
+
+
+def test_overlapping_offgrid_reduced_accuracy():
+    Ks = kernel_lags(OVERLAP_REAL)
+    N = pins.newell_tensor(OVERLAP_REAL)
+    assert np.abs(Ks.sum(0) + N).max() < 5e-9 * np.abs(N).max()
+    lam = np.prod([max(1.0 - abs(d), 0.0) for d in OVERLAP_REAL])
+    assert abs(Ks.sum(0)[:3].sum() + lam) < 5e-9
+
+
+def test_probe_field_at_voxel_centres_closes_the_march_equation():
+    """A probe at the centre of a grid voxel m sees E^s = K (*) J; the march solves
+    sum_k c_k J_{n-k} = chi (<E^i> + K (*) J) there (c_k = T(k dt)/eps + delta_k), so
+    E^s_m(n) = (1/chi) sum_k c_k J_{n-k}(m) - <E^i>_m(n).  This pins the probe path (centres,
+    the k = 0 term, the contraction) against the march itself."""
+    U, V, W, n = 4, 4, 3, 30
+    eps = wl.random_eps(U, V, W, 8, 2.0, 9.0)
+    k, p = wl.XPOL_PLUS_Z
+    fir = wl.binomial_highpass(3, 0.1)
+    prob = wl.Problem("probe-pin", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], n, fir=fir)
+    o = mot.Oracle(prob)
+    J = o.run(n)
+    cells = [(1, 2, 1), (3, 0, 2), (0, 3, 0)]
+    probes = [(u + 0.5, v + 0.5, w + 0.5) for u, v, w in cells]
+    src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U)]
+    Kp = mot.probe_kernels(probes, src, o.ell)
+    E = mot.probe_field(Kp, J, src)
+    c = mot.local_coefficients(eps, fir, o.ell)
+    chi = mot.chi_of(eps)
+    err = 0.0
+    for n_ in range(1, n + 1):
+        Ei = mot.excitation(U, V, W, eps, prob.waves[0], n_)
+        for ip, (u, v, w) in enumerate(cells):
+            lhs = sum(c[kk][w, v, u] * J[n_ - 1 - kk][:, w, v, u] for kk in range(min(n_, len(c))))
+            ref = lhs / chi[w, v, u] - Ei[:, w, v, u] / chi[w, v, u]
+            err = max(err, np.abs(E[n_ - 1, ip] - ref).max() / (np.abs(ref).max() + 1e-300))
+    assert err < 1e-9
