@@ -76,7 +76,7 @@ typedef struct {
  *   k = 0..ell, on the device (eq:Z, Sec. 2.3), transforms them to spectra on the
  *   zero-padded grid (circulant embedding, Appendix A) and allocates the march state.  The march starts at n = 0 with J_{n'} = 0, n' <= 0.
  *   Returns MJ_EINVAL for invalid sizes/values, MJ_ENOMEM if the device memory
- *   needed (reported by mj_memory_bytes) does not fit.
+ *   needed (mj_info entry 8 reports what was allocated) does not fit.
  */
 int mj_create(const mj_config *cfg, mj_solver **out);
 
@@ -87,11 +87,12 @@ void mj_destroy(mj_solver *s);
 const char *mj_last_error(const mj_solver *s);
 
 /*
- * mj_info -- sizes of the solver.  out (host, n entries used, n <= 12):
+ * mj_info -- sizes of the solver.  out (host, n entries used, n <= 16):
  *   [0] ell  [1] Nx [2] Ny [3] Nz (padded FFT sizes)  [4] time block B
  *   [5] history depth kept in real space  [6] n_rhs  [7] current step n
  *   [8] device bytes allocated  [9] kernel generation time (ms)  [10] spectra time (ms)
- *   [11] number of FIR taps
+ *   [11] number of FIR taps  [12] probes  [13] lag window per probe pair
+ *   [14] probe pairs  [15] probe kernel generation time (ms)
  */
 int mj_info(const mj_solver *s, double *out, int32_t n);
 
@@ -113,6 +114,38 @@ int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, cons
  *   J_n holds the last iterate).
  */
 int mj_run(mj_solver *s, int32_t n_steps, double *J_hist);
+
+/*
+ * mj_set_probes -- points where the scattered field is sampled during the march.
+ *   pos: host [n_probes][3], same length unit as h, origin at the grid corner (voxel
+ *   (u, v, w) is centred at ((u + 1/2) h, (v + 1/2) h, (w + 1/2) h)); copied.  0 <= n_probes
+ *   <= 65536; n_probes = 0 removes the probes.  Allowed only at n = 0 (after mj_create or
+ *   mj_reset), else MJ_ESTATE.
+ *   The field is the scattered-field operator of the formulation (Sec. 2.1) tested, like
+ *   eq:Z, on a virtual voxel of side h centred at the probe (eps_0 = 1):
+ *     E^s_p(n) = sum_{k=0}^{ell} sum_{m'} K_k(r_p - r_m') J_{n-k}(m')
+ *   over the voxels m' with eps_r != 1.  (K is S(J) less its local part J, and the
+ *   scattered field is S(J) - J, so no local term appears, inside the scatterer or not.)
+ *   The kernel values of every (probe, voxel) pair's lag window are generated on the
+ *   device here, once; the march adds one pass over them per step.  Accuracy: the probe's
+ *   voxel should not overlap a scatterer voxel off-centre (within one h on every axis),
+ *   where the quadrature reaches only ~1e-9.
+ */
+int mj_set_probes(mj_solver *s, int32_t n_probes, const double *pos);
+
+/*
+ * mj_march -- mj_run with the probe output: probe_hist (device, nullable)
+ *   [n_steps][n_rhs][n_probes][3] receives E^s_p(n) of every step.
+ */
+int mj_march(mj_solver *s, int32_t n_steps, double *J_hist, double *probe_hist);
+
+/*
+ * mj_probe_kernel_values -- K_k(r_p - r_m') as the probe path generates it, for n host
+ *   requests: probe[n] (index into the probes set by mj_set_probes), voxel[n][3] (u, v, w)
+ *   and lag[n] (>= 0).  out (host) [n][6]: xx, yy, zz, xy, xz, yz.
+ */
+int mj_probe_kernel_values(mj_solver *s, int32_t n, const int32_t *probe, const int32_t *voxel,
+                           const int32_t *lag, double *out);
 
 /* mj_reset -- restart the march at n = 0 (all past currents zero). */
 int mj_reset(mj_solver *s);
@@ -137,11 +170,12 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
 
 /*
  * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
- *   in ms per step, and CG statistics.  out (host, n <= 13): [0] forward FFT  [1] history
+ *   in ms per step, and CG statistics.  out (host, n <= 14): [0] forward FFT  [1] history
  *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total
  *   [6] mean CG iterations  [7] max final relative residual  [8] steps timed
  *   [9] max CG iterations  [10] mean duration of one far-part MAC launch (time-blocked,
- *   once per block)  [11] far-part launches  [12] mean duration of one near-part launch.
+ *   once per block)  [11] far-part launches  [12] mean duration of one near-part launch
+ *   [13] probes.  [5] includes [13].
  */
 int mj_stats(const mj_solver *s, double *out, int32_t n);
 

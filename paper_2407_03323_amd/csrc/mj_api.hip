@@ -85,9 +85,15 @@ struct mj_solver {
     int nblk = 1;
     int n = 0;
     std::string err;
+    // probes: scattered field at test voxels centred at arbitrary points
+    std::vector<double> eps_h;
+    int np = 0, nw = 0;
+    long npairs = 0;
+    double *probe_pos = nullptr, *ptable = nullptr, *ppart = nullptr, *pout = nullptr;
+    int *pair_vox = nullptr, *pair_kmin = nullptr, *row_start = nullptr;
     // statistics of the last run
-    double t_gen_ms = 0, t_spec_ms = 0;
-    double stat[13] = {};
+    double t_gen_ms = 0, t_spec_ms = 0, t_probe_ms = 0;
+    double stat[14] = {};
     Events events;
 
     template <class T>
@@ -114,6 +120,18 @@ struct mj_solver {
         if (cgstat_h) (void)hipHostFree(cgstat_h);
     }
 
+    void dfree(void *&ptr)
+    {
+        if (!ptr) return;
+        for (size_t i = 0; i < allocs.size(); i++)
+            if (allocs[i] == ptr) {
+                allocs.erase(allocs.begin() + (long)i);
+                break;
+            }
+        (void)hipFree(ptr);
+        ptr = nullptr;
+    }
+
     long spec_plane() const { return (long)Nz * Ny * Hx; }
     long koct() const { return (long)Hx * (Ny / 2 + 1) * (Nz / 2 + 1); }
     int slotS(int j) const { return j % ell; }
@@ -121,7 +139,9 @@ struct mj_solver {
 
     void create(const mj_config &c);
     void build_spectra();
-    void run(int n_steps, double *Jout);
+    void run(int n_steps, double *Jout, double *Pout);
+    void set_probes(int n_probes, const double *pos);
+    void offgrid_values(int n, const int *probe, const int *vox, const int *lag, double *out);
     void solve_z0();
     void history_sum(const double *Jh, int depth, double *P);
 };
@@ -150,6 +170,7 @@ void mj_solver::create(const mj_config &c)
     for (double d : fir)
         if (!std::isfinite(d)) throw ArgError("FIR taps must be finite");
     std::vector<double> eps(c.eps_r, c.eps_r + M);
+    eps_h = eps;
     for (double e : eps)
         if (!(e >= 1.0) || !std::isfinite(e)) throw ArgError("eps_r must be finite and >= 1");
     // eq:Ell
@@ -363,10 +384,10 @@ void mj_solver::solve_z0()
     cg_guess = mx + 1;
 }
 
-void mj_solver::run(int n_steps, double *Jout)
+void mj_solver::run(int n_steps, double *Jout, double *Pout)
 {
     if (!waves_set) throw std::logic_error("plane waves not set (mj_set_plane_waves)");
-    events.ensure((size_t)6 * std::max(n_steps, 1));
+    events.ensure((size_t)7 * std::max(n_steps, 1));
     double cg_iter_sum = 0, cg_res_max = 0, cg_iter_max = 0;
     bool noconv = false;
     const long sp = spec_plane();
@@ -395,7 +416,7 @@ void mj_solver::run(int n_steps, double *Jout)
     }
     std::vector<char> step_far(n_steps, 0);
     for (int s = 0; s < n_steps; s++) {
-        hipEvent_t *ev = &events.ev[(size_t)6 * s];
+        hipEvent_t *ev = &events.ev[(size_t)7 * s];
         MJ_CHECK(hipEventRecord(ev[0], st));
         n += 1;
         const bool hist = n >= 2;
@@ -478,6 +499,25 @@ void mj_solver::run(int n_steps, double *Jout)
         mj::launch_cg_finish(y, schi, M, nrhs, Jr + (size_t)slotR(n) * nrhs * 3 * M,
                              Jout ? Jout + (size_t)s * nrhs * 3 * M : nullptr, st);
         MJ_CHECK(hipEventRecord(ev[5], st));
+        if (np > 0) {
+            mj::ProbeStepArg pa{};
+            pa.table = ptable;
+            pa.pair_vox = pair_vox;
+            pa.pair_kmin = pair_kmin;
+            pa.row_start = row_start;
+            pa.np = np;
+            pa.ell = ell;
+            pa.nw = nw;
+            pa.nrhs = nrhs;
+            pa.n = n;
+            pa.M = M;
+            pa.Jring = Jr;
+            pa.rdepth = rdepth;
+            pa.part = ppart;
+            pa.out = Pout ? Pout + (size_t)s * nrhs * np * 3 : pout;
+            mj::launch_probes(pa, st);
+        }
+        MJ_CHECK(hipEventRecord(ev[6], st));
         for (int i = 0; i < nrhs; i++) {
             cg_iter_sum += cgstat_h[i].iters;
             cg_iter_max = std::max(cg_iter_max, (double)cgstat_h[i].iters);
@@ -486,11 +526,11 @@ void mj_solver::run(int n_steps, double *Jout)
         }
     }
     MJ_CHECK(hipStreamSynchronize(st));
-    double ph[6] = {0, 0, 0, 0, 0, 0};
+    double ph[6] = {0, 0, 0, 0, 0, 0}, probe_ms = 0;
     double far_ms = 0, near_ms = 0;
     int nfar = 0, nnear = 0;
     for (int s = 0; s < n_steps; s++) {
-        hipEvent_t *ev = &events.ev[(size_t)6 * s];
+        hipEvent_t *ev = &events.ev[(size_t)7 * s];
         for (int k = 0; k < 5; k++) {
             float ms = 0;
             MJ_CHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
@@ -498,8 +538,10 @@ void mj_solver::run(int n_steps, double *Jout)
             if (k == 1 && step_far[s] == 1) { far_ms += ms; nfar++; }
             if (k == 1 && step_far[s] == 2) { near_ms += ms; nnear++; }
         }
-        float tot = 0;
-        MJ_CHECK(hipEventElapsedTime(&tot, ev[0], ev[5]));
+        float pms = 0, tot = 0;
+        MJ_CHECK(hipEventElapsedTime(&pms, ev[5], ev[6]));
+        probe_ms += pms;
+        MJ_CHECK(hipEventElapsedTime(&tot, ev[0], ev[6]));
         ph[5] += tot;
     }
     const double ns = std::max(n_steps, 1);
@@ -511,6 +553,7 @@ void mj_solver::run(int n_steps, double *Jout)
     stat[10] = nfar ? far_ms / nfar : 0.0;
     stat[11] = nfar;
     stat[12] = nnear ? near_ms / nnear : 0.0;
+    stat[13] = probe_ms / ns;
     if (noconv) throw std::range_error("Z_0 solve did not converge");
 }
 
@@ -559,6 +602,152 @@ void mj_solver::history_sum(const double *Jh, int depth, double *P)
     mj::launch_history_local(Jh, depth, S, chi, inv_eps, fir_d, (int)fir.size(), M, P, st);
     MJ_CHECK(hipStreamSynchronize(st));
     n = 0;
+}
+
+// Probes: test voxels of side h centred at arbitrary points.  Pairs (probe, scatterer voxel)
+// whose lag window [kmin, kmin + nw) meets 0..ell are kept, per probe sorted by kmin, with the
+// kernel values of their window generated on the device once.
+void mj_solver::set_probes(int n_probes, const double *pos)
+{
+    if (n != 0) throw std::logic_error("probes are set before the first step (or after mj_reset)");
+    if (n_probes < 0 || n_probes > 65536) throw ArgError("n_probes must be in [0, 65536]");
+    if (n_probes > 0 && !pos) throw ArgError("probe positions are NULL");
+    for (int i = 0; i < 3 * n_probes; i++)
+        if (!std::isfinite(pos[i])) throw ArgError("probe positions must be finite");
+    // drop a previous set
+    dfree((void *&)probe_pos);
+    dfree((void *&)ptable);
+    dfree((void *&)ppart);
+    dfree((void *&)pout);
+    dfree((void *&)pair_vox);
+    dfree((void *&)pair_kmin);
+    dfree((void *&)row_start);
+    np = 0;
+    nw = 0;
+    npairs = 0;
+    if (n_probes == 0) return;
+    const double r = c_dt / h;
+    std::vector<double> P(3 * (size_t)n_probes);
+    for (size_t i = 0; i < P.size(); i++) P[i] = pos[i] / h;
+    std::vector<int> src;
+    for (long m = 0; m < M; m++)
+        if (eps_h[m] != 1.0) src.push_back((int)m);
+    struct Pair {
+        int kmin, vox;
+    };
+    std::vector<int> pp, pv, pk, rs((size_t)n_probes * (ell + 2));
+    int nwin = 1;
+    for (int p = 0; p < n_probes; p++) {
+        std::vector<Pair> list;
+        for (int m : src) {
+            const int u = m % U, v = (m / U) % V, w = m / (U * V);
+            const double d[3] = {P[3 * p] - (u + 0.5), P[3 * p + 1] - (v + 0.5), P[3 * p + 2] - (w + 0.5)};
+            double a2 = 0, b2 = 0;
+            for (int i = 0; i < 3; i++) {
+                const double ad = std::fabs(d[i]);
+                const double e = ad > 1.0 ? ad - 1.0 : 0.0;
+                a2 += e * e;
+                b2 += (ad + 1.0) * (ad + 1.0);
+            }
+            // lags with r(k + 1) > R_min and r(k - 2) < R_max
+            const int kmin = std::max(0, (int)std::floor(std::sqrt(a2) / r));
+            const int kmax = std::min(ell, (int)std::ceil(std::sqrt(b2) / r + 2.0) - 1);
+            if (kmin > kmax) continue;
+            nwin = std::max(nwin, kmax - kmin + 1);
+            list.push_back({kmin, m});
+        }
+        std::stable_sort(list.begin(), list.end(), [](const Pair &a, const Pair &b) { return a.kmin < b.kmin; });
+        const int base = (int)pp.size();
+        size_t q = 0;
+        for (int kk = 0; kk <= ell + 1; kk++) {
+            while (q < list.size() && list[q].kmin < kk) q++;
+            rs[(size_t)p * (ell + 2) + kk] = base + (int)q;
+        }
+        for (const Pair &x : list) {
+            pp.push_back(p);
+            pv.push_back(x.vox);
+            pk.push_back(x.kmin);
+        }
+    }
+    np = n_probes;
+    nw = nwin;
+    npairs = (long)pp.size();
+    probe_pos = dalloc<double>(P.size(), "probe positions");
+    pair_vox = dalloc<int>(std::max<size_t>(pv.size(), 1), "probe pairs");
+    pair_kmin = dalloc<int>(std::max<size_t>(pk.size(), 1), "probe windows");
+    row_start = dalloc<int>(rs.size(), "probe rows");
+    int *pair_probe = dalloc<int>(std::max<size_t>(pp.size(), 1), "probe pair owners");
+    ptable = dalloc<double>((size_t)std::max<long>(npairs, 1) * nw * 6, "probe kernel table");
+    ppart = dalloc<double>((size_t)nrhs * np * (ell + 1) * 3, "probe partial sums");
+    pout = dalloc<double>((size_t)nrhs * np * 3, "probe field");
+    MJ_CHECK(hipMemcpy(probe_pos, P.data(), sizeof(double) * P.size(), hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(row_start, rs.data(), sizeof(int) * rs.size(), hipMemcpyHostToDevice));
+    if (npairs > 0) {
+        MJ_CHECK(hipMemcpy(pair_vox, pv.data(), sizeof(int) * pv.size(), hipMemcpyHostToDevice));
+        MJ_CHECK(hipMemcpy(pair_kmin, pk.data(), sizeof(int) * pk.size(), hipMemcpyHostToDevice));
+        MJ_CHECK(hipMemcpy(pair_probe, pp.data(), sizeof(int) * pp.size(), hipMemcpyHostToDevice));
+        hipEvent_t e0, e1;
+        MJ_CHECK(hipEventCreate(&e0));
+        MJ_CHECK(hipEventCreate(&e1));
+        MJ_CHECK(hipEventRecord(e0, st));
+        mj::gen_offgrid_table(probe_pos, pair_probe, pair_vox, pair_kmin, npairs, U, V, nw, ell, nquad, ptable, st);
+        MJ_CHECK(hipEventRecord(e1, st));
+        MJ_CHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        MJ_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        t_probe_ms = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    dfree((void *&)pair_probe);
+    // the probe rows read J_{n-k} for k = 0..ell from the real-space ring
+    if (rdepth < ell + 1) {
+        dfree((void *&)Jr);
+        rdepth = ell + 1;
+        Jr = dalloc<double>((size_t)rdepth * nrhs * 3 * M, "current history");
+    }
+    MJ_CHECK(hipStreamSynchronize(st));
+}
+
+// Kernel values at (probe, voxel, lag) triples through the same off-grid generator.
+void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const int *lag, double *out)
+{
+    if (cnt <= 0) return;
+    if (!probe_pos) throw std::logic_error("no probes set");
+    std::vector<int> pp(cnt), pv(cnt), pk(cnt);
+    for (int i = 0; i < cnt; i++) {
+        if (probe[i] < 0 || probe[i] >= np) throw ArgError("probe index out of range");
+        const int u = vox3[3 * i], v = vox3[3 * i + 1], w = vox3[3 * i + 2];
+        if (u < 0 || u >= U || v < 0 || v >= V || w < 0 || w >= W) throw ArgError("voxel out of range");
+        if (lag[i] < 0) throw ArgError("lag < 0");
+        pp[i] = probe[i];
+        pv[i] = u + U * (v + V * w);
+        pk[i] = lag[i];
+    }
+    int *d_p = nullptr, *d_v = nullptr, *d_k = nullptr;
+    double *d_o = nullptr;
+    try {
+        MJ_CHECK(hipMalloc(&d_p, sizeof(int) * cnt));
+        MJ_CHECK(hipMalloc(&d_v, sizeof(int) * cnt));
+        MJ_CHECK(hipMalloc(&d_k, sizeof(int) * cnt));
+        MJ_CHECK(hipMalloc(&d_o, sizeof(double) * 6 * cnt));
+        MJ_CHECK(hipMemcpy(d_p, pp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
+        MJ_CHECK(hipMemcpy(d_v, pv.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
+        MJ_CHECK(hipMemcpy(d_k, pk.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
+        mj::gen_offgrid_table(probe_pos, d_p, d_v, d_k, cnt, U, V, 1, 0x7fffffff, nquad, d_o, st);
+        MJ_CHECK(hipStreamSynchronize(st));
+        MJ_CHECK(hipMemcpy(out, d_o, sizeof(double) * 6 * cnt, hipMemcpyDeviceToHost));
+    } catch (...) {
+        (void)hipFree(d_p);
+        (void)hipFree(d_v);
+        (void)hipFree(d_k);
+        (void)hipFree(d_o);
+        throw;
+    }
+    (void)hipFree(d_p);
+    (void)hipFree(d_v);
+    (void)hipFree(d_k);
+    (void)hipFree(d_o);
 }
 
 // ============================================================================ C ABI
@@ -618,10 +807,11 @@ const char *mj_last_error(const mj_solver *s) { return s ? s->err.c_str() : g_er
 int mj_info(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    double v[12] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
-                    (double)s->nloc, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
-                    s->t_spec_ms, (double)s->fir.size()};
-    for (int i = 0; i < n && i < 12; i++) out[i] = v[i];
+    double v[16] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
+                    (double)s->rdepth, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
+                    s->t_spec_ms, (double)s->fir.size(), (double)s->np, (double)s->nw, (double)s->npairs,
+                    s->t_probe_ms};
+    for (int i = 0; i < n && i < 16; i++) out[i] = v[i];
     return MJ_OK;
 }
 
@@ -656,7 +846,28 @@ int mj_run(mj_solver *s, int32_t n_steps, double *J_hist)
 {
     if (!s) return MJ_EINVAL;
     if (n_steps < 0) return fail(s, MJ_EINVAL, "n_steps < 0");
-    return guarded(s, [&] { s->run(n_steps, J_hist); });
+    return guarded(s, [&] { s->run(n_steps, J_hist, nullptr); });
+}
+
+int mj_march(mj_solver *s, int32_t n_steps, double *J_hist, double *probe_hist)
+{
+    if (!s) return MJ_EINVAL;
+    if (n_steps < 0) return fail(s, MJ_EINVAL, "n_steps < 0");
+    return guarded(s, [&] { s->run(n_steps, J_hist, probe_hist); });
+}
+
+int mj_set_probes(mj_solver *s, int32_t n_probes, const double *pos)
+{
+    if (!s) return MJ_EINVAL;
+    return guarded(s, [&] { s->set_probes(n_probes, pos); });
+}
+
+int mj_probe_kernel_values(mj_solver *s, int32_t n, const int32_t *probe, const int32_t *voxel,
+                           const int32_t *lag, double *out)
+{
+    if (!s) return MJ_EINVAL;
+    if (n < 0 || (n > 0 && (!probe || !voxel || !lag || !out))) return fail(s, MJ_EINVAL, "bad arguments");
+    return guarded(s, [&] { s->offgrid_values(n, probe, voxel, lag, out); });
 }
 
 int mj_reset(mj_solver *s)
@@ -704,7 +915,7 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
 int mj_stats(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    for (int i = 0; i < n && i < 13; i++) out[i] = s->stat[i];
+    for (int i = 0; i < n && i < 14; i++) out[i] = s->stat[i];
     return MJ_OK;
 }
 

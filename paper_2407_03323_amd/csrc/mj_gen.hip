@@ -87,7 +87,7 @@ __host__ __device__ inline void sort_fixed(double *a)
 // Every array index is a compile-time constant.
 template <int AX>
 __host__ __device__ inline void node_contrib(double m[kMoments], const double y[3], double ny, double wgt, int s,
-                                             int s1, int s2, const int D[3], int a, const double *g3x,
+                                             int s1, int s2, const double D[3], int a, const double *g3x,
                                              const double *g3w)
 {
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
@@ -161,12 +161,12 @@ constexpr int kMaxGrade = 6;   // graded tau points towards the foot (ratio 3)
 // glx/glw: nq-point rule on [-1,1]; g3x/g3w: 3-point rule.
 template <int AX, int E>
 __host__ __device__ inline void gen_edge(int nq, const double *glx, const double *glw, const double *g3x,
-                                         const double *g3w, const int D[3], int a, int s, int s1, int s2, int iv,
+                                         const double *g3w, const double D[3], int a, int s, int s1, int s2, int iv,
                                          int iq, double m[kMoments])
 {
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
     const double Ra = (double)a, Rb = (double)(a + 1);
-    const double c = (double)(D[AX] + s);
+    const double c = D[AX] + s;
     const double lo1 = s1 > 0 ? D[A1] : D[A1] - 1, lo2 = s2 > 0 ? D[A2] : D[A2] - 1;
     const double hi1 = lo1 + 1.0, hi2 = lo2 + 1.0;
     // edge e: signed distance p of its line from the foot; range [e0, e1] of the edge coordinate
@@ -258,7 +258,7 @@ __host__ __device__ inline void gen_edge(int nq, const double *glx, const double
 
 template <int AX>
 __host__ __device__ inline void gen_square(int nq, const double *glx, const double *glw, const double *g3x,
-                                           const double *g3w, const int D[3], int a, int s, int s1, int s2, int iv,
+                                           const double *g3w, const double D[3], int a, int s, int s1, int s2, int iv,
                                            int iq, double m[kMoments])
 {
     gen_edge<AX, 0>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
@@ -273,7 +273,7 @@ __host__ __device__ inline int gen_items(int nq) { return 36 * 5 * nq; }
 // Item index -> (unit square, s-interval, s-node); the four edges of the square are
 // handled inside the item.  Dispatch on the plane axis.
 __host__ __device__ inline void gen_item(int nq, const double *glx, const double *glw, const double *g3x,
-                                         const double *g3w, const int D[3], int a, int it, double m[kMoments])
+                                         const double *g3w, const double D[3], int a, int it, double m[kMoments])
 {
     const int iq = it % nq;
     const int rest = it / nq;
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict_
 {
     const int idx = blockIdx.x;
     const int dx = idx % ga.Uo, dy = (idx / ga.Uo) % ga.Vo, dz = idx / (ga.Uo * ga.Vo);
-    const int D[3] = {dx, dy, dz};
+    const double D[3] = {(double)dx, (double)dy, (double)dz};
     int a_lo, nsh;
     shell_range(dx, dy, dz, a_lo, nsh);
     double *out = mom + (size_t)idx * kMaxShells * kMoments;
@@ -330,11 +330,9 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict_
     }
 }
 
-// K_k at octant offset (dx,dy,dz) >= 0 from the shell moments.
-__host__ __device__ inline void kernel_from_moments(const double *mom_d, int dx, int dy, int dz, int k, double K[6])
+// K_k at an octant offset >= 0 from the moments of its shells a_lo .. a_lo + nsh - 1.
+__host__ __device__ inline void kernel_from_shells(const double *mom_d, int a_lo, int nsh, int k, double K[6])
 {
-    int a_lo, nsh;
-    shell_range(dx, dy, dz, a_lo, nsh);
     for (int i = 0; i < 6; i++) K[i] = 0.0;
     // B(k+1-|d|) on shell k-p as a quadratic in v = |d| - a:  p=0: (1-v)^2/2, p=1: (1+2v-2v^2)/2, p=2: v^2/2
     const double cg[3][3] = {{0.5, -1.0, 0.5}, {0.5, 1.0, -1.0}, {0.0, 0.0, 0.5}};
@@ -349,6 +347,14 @@ __host__ __device__ inline void kernel_from_moments(const double *mom_d, int dx,
             K[3 + pr] += cg[p][0] * m[9 + 3 * pr] + cg[p][1] * m[9 + 3 * pr + 1] + cg[p][2] * m[9 + 3 * pr + 2];
     }
     for (int i = 0; i < 6; i++) K[i] *= kInvFourPi;
+}
+
+// K_k at integer octant offset (dx,dy,dz) >= 0 from the shell moments.
+__host__ __device__ inline void kernel_from_moments(const double *mom_d, int dx, int dy, int dz, int k, double K[6])
+{
+    int a_lo, nsh;
+    shell_range(dx, dy, dz, a_lo, nsh);
+    kernel_from_shells(mom_d, a_lo, nsh, k, K);
     // exact zeros of the odd components on their symmetry planes
     if (dx == 0 || dy == 0) K[3] = 0.0;
     if (dx == 0 || dz == 0) K[4] = 0.0;
@@ -392,6 +398,103 @@ __global__ void k_kernel_values(const double *__restrict__ mom, int Uo, int Vo, 
     double K[6];
     kernel_at(mom, Uo, Vo, Wo, lag[i], off[3 * i], off[3 * i + 1], off[3 * i + 2], K);
     for (int c = 0; c < 6; c++) out[6 * i + c] = K[c];
+}
+
+// ---------------------------------------------------------------------------- off-grid offsets
+// Shell range for a real octant offset D >= 0 (the distances between points of the two
+// voxels lie in [|max(D - 1, 0)|, |D + 1|]).
+__host__ __device__ inline void shell_range_real(const double D[3], int &a_lo, int &nsh)
+{
+    double a2 = 0.0, b2 = 0.0;
+    for (int i = 0; i < 3; i++) {
+        const double e = D[i] > 1.0 ? D[i] - 1.0 : 0.0;
+        a2 += e * e;
+        b2 += (D[i] + 1.0) * (D[i] + 1.0);
+    }
+    a_lo = (int)floor(sqrt(a2));
+    int hi = (int)ceil(sqrt(b2));
+    nsh = hi - a_lo;
+    if (nsh > kMaxShells) nsh = kMaxShells;   // cannot happen: R_max - R_min <= 2 sqrt 3
+}
+
+// K_k for k = kmin .. kmin + nw - 1 at the signed real offset Ds, serially (host checks and
+// reference): fold to the octant, quadrature of every shell, parity signs.
+__host__ __device__ inline void fold_offset(const double Ds[3], double D[3], double sg[3])
+{
+    for (int i = 0; i < 3; i++) {
+        D[i] = Ds[i] < 0.0 ? -Ds[i] : Ds[i];
+        sg[i] = Ds[i] < 0.0 ? -1.0 : 1.0;
+    }
+}
+
+__host__ __device__ inline void finish_offgrid(const double D[3], const double sg[3], double K[6])
+{
+    if (D[0] == 0.0 || D[1] == 0.0) K[3] = 0.0;
+    if (D[0] == 0.0 || D[2] == 0.0) K[4] = 0.0;
+    if (D[1] == 0.0 || D[2] == 0.0) K[5] = 0.0;
+    K[3] *= sg[0] * sg[1];
+    K[4] *= sg[0] * sg[2];
+    K[5] *= sg[1] * sg[2];
+}
+
+struct OffgridArg {
+    const double *pos;        // [np][3] test-voxel centres, units of h from the grid corner
+    const int *pair_probe;    // [npairs]
+    const int *pair_vox;      // [npairs] source voxel, linear index u + U (v + V w)
+    const int *pair_kmin;     // [npairs] first lag of the window
+    int U, V;
+    int nw;                   // lags per pair
+    int kmax;                 // lags above kmax are stored as zero
+    double *out;              // [npairs][nw][6]
+};
+
+// One 64-lane block per (test voxel, source voxel) pair: shell moments by the same face
+// quadrature as the grid kernels, then the pair's window of lags.
+__global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, GenArg ga)
+{
+    const long i = blockIdx.x;
+    const int p = oa.pair_probe[i], vox = oa.pair_vox[i];
+    const int u = vox % oa.U, v = (vox / oa.U) % oa.V, w = vox / (oa.U * oa.V);
+    const double Ds[3] = {oa.pos[3 * p] - (u + 0.5), oa.pos[3 * p + 1] - (v + 0.5), oa.pos[3 * p + 2] - (w + 0.5)};
+    double D[3], sg[3];
+    fold_offset(Ds, D, sg);
+    int a_lo, nsh;
+    shell_range_real(D, a_lo, nsh);
+    const int nq = ga.nq;
+    __shared__ double glx[kMaxQ], glw[kMaxQ], g3x[3], g3w[3];
+    __shared__ double mom[kMaxShells * kMoments];
+    for (int t = threadIdx.x; t < kMaxQ; t += kGenThreads) {
+        glx[t] = ga.glx[t];
+        glw[t] = ga.glw[t];
+    }
+    if (threadIdx.x < 3) {
+        g3x[threadIdx.x] = ga.g3x[threadIdx.x];
+        g3w[threadIdx.x] = ga.g3w[threadIdx.x];
+    }
+    __syncthreads();
+    const int nitems = gen_items(nq);
+    for (int sh = 0; sh < nsh; sh++) {
+        double m[kMoments];
+#pragma unroll
+        for (int t = 0; t < kMoments; t++) m[t] = 0.0;
+        for (int it = threadIdx.x; it < nitems; it += kGenThreads) gen_item(nq, glx, glw, g3x, g3w, D, a_lo + sh, it, m);
+#pragma unroll
+        for (int t = 0; t < kMoments; t++) {
+            const double s_ = wave_sum(m[t]);
+            if (threadIdx.x == 0) mom[sh * kMoments + t] = s_;
+        }
+    }
+    __syncthreads();
+    for (int wl = threadIdx.x; wl < oa.nw; wl += kGenThreads) {
+        const int k = oa.pair_kmin[i] + wl;
+        double K[6] = {0, 0, 0, 0, 0, 0};
+        if (k <= oa.kmax) {
+            kernel_from_shells(mom, a_lo, nsh, k, K);
+            finish_offgrid(D, sg, K);
+        }
+        double *o = oa.out + (i * oa.nw + wl) * 6;
+        for (int c = 0; c < 6; c++) o[c] = K[c];
+    }
 }
 
 // Gauss-Legendre rule on [-1, 1]: roots of P_n by Newton's method from Tricomi's initial
@@ -464,6 +567,31 @@ void gen_kernel_values(const GenResult &g, int n, const int *lag_dev, const int 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_kernel_values, dim3((n + 127) / 128), dim3(128), 0, st, g.moments, g.Uo, g.Vo, g.Wo, n,
                        lag_dev, off_dev, out_dev);
+    MJ_CHECK(hipGetLastError());
+}
+
+void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const int *pair_vox_dev,
+                       const int *pair_kmin_dev, long npairs, int U, int V, int nw, int kmax, int nquad,
+                       double *out_dev, hipStream_t st)
+{
+    if (npairs <= 0) return;
+    if (nquad < 4 || nquad > kMaxQ) throw ArgError("quad_order must be in [4, 24]");
+    if (npairs > 0x7fffffffL) throw ArgError("too many probe pairs");
+    GenArg ga{};
+    ga.nq = nquad;
+    legendre_rule(nquad, ga.glx, ga.glw);
+    legendre_rule(3, ga.g3x, ga.g3w);
+    OffgridArg oa{};
+    oa.pos = pos_dev;
+    oa.pair_probe = pair_probe_dev;
+    oa.pair_vox = pair_vox_dev;
+    oa.pair_kmin = pair_kmin_dev;
+    oa.U = U;
+    oa.V = V;
+    oa.nw = nw;
+    oa.kmax = kmax;
+    oa.out = out_dev;
+    hipLaunchKernelGGL(k_offgrid_table, dim3((unsigned)npairs), dim3(kGenThreads), 0, st, oa, ga);
     MJ_CHECK(hipGetLastError());
 }
 

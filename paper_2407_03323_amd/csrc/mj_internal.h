@@ -84,6 +84,13 @@ void gen_moments(GenResult &g, int U, int V, int W, int nquad, hipStream_t st);
 // K_k on the full periodic grid [6][Nz][Ny][Nx] (real), from the octant moments
 void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *grid, hipStream_t st);
 // K_k(D) for a list of (k, D): out[n][6]
+// Kernels seen from test voxels centred at arbitrary points pos[p] (units of h from the grid
+// corner) for source voxels pair_vox (linear index), lags pair_kmin .. pair_kmin + nw - 1
+// (zero above kmax): out[pair][nw][6].
+void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const int *pair_vox_dev,
+                       const int *pair_kmin_dev, long npairs, int U, int V, int nw, int kmax, int nquad,
+                       double *out_dev, hipStream_t st);
+
 void gen_kernel_values(const GenResult &g, int n, const int *lag_dev, const int *off_dev, double *out_dev,
                        hipStream_t st);
 

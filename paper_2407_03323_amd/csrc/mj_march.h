@@ -81,8 +81,27 @@ struct CgArg {
     CgStatus *stat;          // [nrhs]
 };
 
+// Scattered field at probe points: E^s_p(n) = sum_{k=0}^{ell} sum_s K_k(r_p - r_s) J_{n-k}(s)
+// over the source voxels s of the scatterer.  Pairs (p, s) are stored per probe sorted by the
+// first lag kmin of their window, so the sources that lag k reaches through window slot
+// k - kmin form one contiguous run: row (p, k) = pairs [row_start[p][max(0, k-nw+1)],
+// row_start[p][k+1]).
+struct ProbeStepArg {
+    const double *table;     // [npairs][nw][6]
+    const int *pair_vox;     // [npairs]
+    const int *pair_kmin;    // [npairs]
+    const int *row_start;    // [np][ell + 2]
+    int np, ell, nw, nrhs, n;
+    long M;
+    const double *Jring;     // [rdepth][nrhs][3][M]
+    int rdepth;
+    double *part;            // [nrhs][np][ell + 1][3]
+    double *out;             // [nrhs][np][3]
+};
+
 void launch_mac(const MacArg &a, hipStream_t st);
 void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st);
+void launch_probes(const ProbeStepArg &a, hipStream_t st);
 void launch_mac_near(const BlockMacArg &a, hipStream_t st);
 void launch_epilogue(const EpiArg &e, hipStream_t st);
 void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,

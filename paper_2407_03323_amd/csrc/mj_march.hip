@@ -731,4 +731,66 @@ void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, dou
     MJ_CHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------- probes
+// One wave per row (p, k): the sources whose lag window holds k, each through its window slot
+// k - kmin, against J_{n-k}; lanes stride over the run and the wave sums in fixed order.
+__global__ void __launch_bounds__(256) k_probe_rows(ProbeStepArg a)
+{
+    const int lane = threadIdx.x & 63;
+    const long row = blockIdx.x * 4L + (threadIdx.x >> 6);
+    const int r = blockIdx.y;
+    const int L1 = a.ell + 1;
+    if (row >= (long)a.np * L1) return;
+    const int p = (int)(row / L1), k = (int)(row % L1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int j = a.n - k;
+    if (j >= 1) {
+        const int *rs = a.row_start + (long)p * (a.ell + 2);
+        const int lo = rs[k - a.nw + 1 > 0 ? k - a.nw + 1 : 0], hi = rs[k + 1];
+        const double *J = a.Jring + ((long)(j % a.rdepth) * a.nrhs + r) * 3 * a.M;
+        for (int q = lo + lane; q < hi; q += 64) {
+            const int wl = k - a.pair_kmin[q];
+            const double *K = a.table + ((long)q * a.nw + wl) * 6;
+            const long m = a.pair_vox[q];
+            const double jx = J[m], jy = J[a.M + m], jz = J[2 * a.M + m];
+            acc[0] += K[0] * jx + K[3] * jy + K[4] * jz;
+            acc[1] += K[3] * jx + K[1] * jy + K[5] * jz;
+            acc[2] += K[4] * jx + K[5] * jy + K[2] * jz;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
+    if (lane == 0) {
+        double *o = a.part + (((long)r * a.np + p) * L1 + k) * 3;
+        o[0] = acc[0];
+        o[1] = acc[1];
+        o[2] = acc[2];
+    }
+}
+
+// E^s_p(n) = sum over the rows k = 0 .. ell, in order
+__global__ void k_probe_sum(ProbeStepArg a)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)a.nrhs * a.np * 3) return;
+    const int c = (int)(t % 3);
+    const long rp = t / 3;
+    const int L1 = a.ell + 1;
+    const double *src = a.part + rp * L1 * 3 + c;
+    double s = 0.0;
+    for (int k = 0; k < L1; k++) s += src[3 * k];
+    a.out[t] = s;
+}
+
+void launch_probes(const ProbeStepArg &a, hipStream_t st)
+{
+    const long rows = (long)a.np * (a.ell + 1);
+    hipLaunchKernelGGL(k_probe_rows, dim3((unsigned)((rows + 3) / 4), a.nrhs), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+    const long nt = (long)a.nrhs * a.np * 3;
+    hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+}
+
 }  // namespace mj

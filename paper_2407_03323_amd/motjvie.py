@@ -65,8 +65,12 @@ def load_library(path: str = LIB_PATH):
     L.mj_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, dp]
     L.mj_stats.argtypes = [vp, dp, ctypes.c_int32]
     L.mj_fft_roundtrip.argtypes = [vp, vp, vp, vp]
+    L.mj_set_probes.argtypes = [vp, ctypes.c_int32, dp]
+    L.mj_march.argtypes = [vp, ctypes.c_int32, vp, vp]
+    L.mj_probe_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, ip, dp]
     for f in ("mj_create", "mj_info", "mj_set_plane_waves", "mj_run", "mj_reset", "mj_history_sum",
-              "mj_kernel_values", "mj_stats", "mj_fft_roundtrip"):
+              "mj_kernel_values", "mj_stats", "mj_fft_roundtrip", "mj_set_probes", "mj_march",
+              "mj_probe_kernel_values"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -137,11 +141,12 @@ class Solver:
             pass
 
     def info(self) -> dict:
-        out = np.zeros(12)
-        self._check(self._lib.mj_info(self._h, _dptr(out), 12))
-        keys = ["ell", "Nx", "Ny", "Nz", "time_block", "local_depth", "n_rhs", "n", "device_bytes",
-                "gen_ms", "spectra_ms", "n_fir"]
-        return {k: (int(v) if k not in ("gen_ms", "spectra_ms") else float(v)) for k, v in zip(keys, out)}
+        out = np.zeros(16)
+        self._check(self._lib.mj_info(self._h, _dptr(out), 16))
+        keys = ["ell", "Nx", "Ny", "Nz", "time_block", "real_depth", "n_rhs", "n", "device_bytes",
+                "gen_ms", "spectra_ms", "n_fir", "n_probes", "probe_window", "probe_pairs", "probe_gen_ms"]
+        ms = ("gen_ms", "spectra_ms", "probe_gen_ms")
+        return {k: (int(v) if k not in ms else float(v)) for k, v in zip(keys, out)}
 
     @property
     def ell(self) -> int:
@@ -160,11 +165,33 @@ class Solver:
         self._check(self._lib.mj_set_plane_waves(self._h, _dptr(k), _dptr(p), _dptr(wd), _dptr(t0), _dptr(a),
                                                  _dptr(rr)))
 
-    def run(self, n_steps: int, J_out=None):
-        """March n_steps; J_out (optional) is a CUDA tensor [n_steps][n_rhs][3][W][V][U]."""
+    def set_probes(self, pos):
+        """Probe points [n][3] (units of h, origin at the grid corner); before the first step."""
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        self.n_probes = len(pos)
+        self._check(self._lib.mj_set_probes(self._h, len(pos), _dptr(pos) if len(pos) else None))
+
+    def run(self, n_steps: int, J_out=None, probes_out=None):
+        """March n_steps; J_out (optional) is a CUDA tensor [n_steps][n_rhs][3][W][V][U],
+        probes_out (optional) a CUDA tensor [n_steps][n_rhs][n_probes][3]."""
         if J_out is not None:
             assert J_out.numel() == n_steps * self.n_rhs * 3 * self.M
-        self._check(self._lib.mj_run(self._h, int(n_steps), _tptr(J_out, "J_out")))
+        if probes_out is None:
+            self._check(self._lib.mj_run(self._h, int(n_steps), _tptr(J_out, "J_out")))
+            return
+        assert probes_out.numel() == n_steps * self.n_rhs * getattr(self, "n_probes", 0) * 3
+        self._check(self._lib.mj_march(self._h, int(n_steps), _tptr(J_out, "J_out"),
+                                       _tptr(probes_out, "probes_out")))
+
+    def probe_kernel_values(self, probe, voxels, lags) -> np.ndarray:
+        probe = np.ascontiguousarray(np.asarray(probe, dtype=np.int32))
+        vox = np.ascontiguousarray(np.asarray(voxels, dtype=np.int32).reshape(-1, 3))
+        lags = np.ascontiguousarray(np.asarray(lags, dtype=np.int32))
+        out = np.zeros((len(lags), 6))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        self._check(self._lib.mj_probe_kernel_values(self._h, len(lags), probe.ctypes.data_as(ip),
+                                                     vox.ctypes.data_as(ip), lags.ctypes.data_as(ip), _dptr(out)))
+        return out
 
     def reset(self):
         self._check(self._lib.mj_reset(self._h))
@@ -185,10 +212,11 @@ class Solver:
         return out
 
     def stats(self) -> dict:
-        out = np.zeros(13)
-        self._check(self._lib.mj_stats(self._h, _dptr(out), 13))
+        out = np.zeros(14)
+        self._check(self._lib.mj_stats(self._h, _dptr(out), 14))
         keys = ["fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms", "z0_ms", "step_ms", "cg_iters",
-                "cg_res_max", "steps", "cg_iters_max", "far_launch_ms", "far_launches", "near_launch_ms"]
+                "cg_res_max", "steps", "cg_iters_max", "far_launch_ms", "far_launches", "near_launch_ms",
+                "probe_ms"]
         return dict(zip(keys, out.tolist()))
 
     def fft_roundtrip(self, x, X=None, y=None):

@@ -234,3 +234,75 @@ def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb):
         say("  rhs", i, "vs single", e_single, "vs oracle", e_oracle)
         assert e_single <= 1e-13
         assert e_oracle <= 1e-8
+
+
+# ----------------------------------------------------------------------------- probes
+def test_probes_match_oracle(torch_cuda):
+    """Scattered field at probe points (a Fibonacci sphere around the block, plus two points
+    at voxel centres inside it) over a 50-step march of a 6 x 5 x 4 heterogeneous block with a
+    5-tap FIR: GPU march + probe rows against the oracle's march + direct probe sum."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n = 6, 5, 4, 50
+    say("probes 6x5x4")
+    eps = wl.random_eps(U, V, W, 12, 1.0, 8.0)
+    eps[0, 0, 0] = 1.0                                   # one voxel outside the scatterer
+    k, p = wl.XPOL_PLUS_Z
+    fir = wl.binomial_highpass(5, 0.1)
+    prob = wl.Problem("probes", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.5)], n, fir=fir)
+    probes = np.concatenate([wl.fibonacci_sphere(8, 6.0, (U / 2, V / 2, W / 2)),
+                             np.array([[2.5, 1.5, 0.5], [4.5, 3.5, 2.5]])])
+    ell = mot.ell(U, V, W)
+    K = oracle_kernel_table(U, V, W, ell)
+    J = mot.Oracle(prob, K=K).run(n)
+    src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U) if eps[w, v, u] != 1.0]
+    ref = mot.probe_field(mot.probe_kernels(probes, src, ell), J, src)
+    s = make_solver(prob, time_block=8)
+    s.set_probes(probes)
+    info = s.info()
+    Pt = torch.zeros((n, 1, len(probes), 3), dtype=torch.float64, device="cuda")
+    s.run(n, None, Pt)
+    torch.cuda.synchronize()
+    got = Pt.cpu().numpy()[:, 0]
+    err = _rel(got, ref)
+    say("  pairs", info["probe_pairs"], "window", info["probe_window"], "rel L2", err)
+    assert info["probe_pairs"] == len(probes) * len(src)
+    assert err <= 1e-8
+    s.close()
+
+
+def test_probe_kernels_sampled_C2(torch_cuda):
+    """The probe path's kernel values at the 32^3 sphere configuration (32 probes on a sphere
+    of radius 24 h): sampled (probe, voxel, lag) triples inside the lag support against the
+    oracle's quadrature (24-point rule: off-grid offsets converge more slowly there)."""
+    from oracle import mot
+    prob = wl.config("C2")
+    say("probe kernels C2")
+    s = make_solver(prob, time_block=8)
+    s.set_probes(prob.probes)
+    info = s.info()
+    say("  pairs", info["probe_pairs"], "window", info["probe_window"], "gen ms", info["probe_gen_ms"])
+    rng = np.random.default_rng(7)
+    src = np.argwhere(prob.eps != 1.0)[:, ::-1]          # (u, v, w)
+    pi, vox, lag = [], [], []
+    while len(lag) < 48:
+        p_ = int(rng.integers(len(prob.probes)))
+        m = src[int(rng.integers(len(src)))]
+        D = prob.probes[p_] - (m + 0.5)
+        rmin = np.sqrt(sum(max(abs(d) - 1, 0) ** 2 for d in D))
+        k = int(np.floor(rmin)) + int(rng.integers(0, 5))
+        if k > info["ell"]:
+            continue
+        pi.append(p_)
+        vox.append(m)
+        lag.append(k)
+    got = s.probe_kernel_values(pi, vox, lag)
+    worst = 0.0
+    for i in range(len(lag)):
+        D = prob.probes[pi[i]] - (np.asarray(vox[i]) + 0.5)
+        ref = mot.kernel_entry(lag[i], D, ngl=24)
+        scale = max(np.abs(mot.kernel_entry(k_, D, ngl=24)).max() for k_ in range(max(0, lag[i] - 2), lag[i] + 3))
+        worst = max(worst, np.abs(got[i] - ref).max() / scale)
+    say("  worst rel", worst)
+    assert worst <= 1e-11
+    s.close()
