@@ -71,6 +71,11 @@ def local_coefficients(eps: np.ndarray, fir: np.ndarray, kmax: int) -> np.ndarra
 def excitation(U, V, W, eps, wave, n: int, nquad: int = 8) -> np.ndarray:
     """E_n(m) = chi_m (1/h^3) Int_{V_m} E^i(r, n dt) dV  (eq:E, test voxel m and step n),
     the voxel average taken with an nquad^3 Gauss-Legendre rule."""
+    return chi_of(eps)[None] * incident_average(U, V, W, wave, n, nquad)
+
+
+def incident_average(U, V, W, wave, n: int, nquad: int = 8) -> np.ndarray:
+    """<E^i>_m(n dt) = (1/h^3) Int_{V_m} E^i(r, n dt) dV, [3][W][V][U]."""
     x, w = np.polynomial.legendre.leggauss(nquad)
     x = 0.5 * x
     w = 0.5 * w
@@ -87,8 +92,7 @@ def excitation(U, V, W, eps, wave, n: int, nquad: int = 8) -> np.ndarray:
                 s = x[i] * k[0] + x[j] * k[1] + x[l] * k[2]
                 avg += w[i] * w[j] * w[l] * np.exp(-((tc - s) / wave.width) ** 2)
     avg *= wave.amp
-    chi = chi_of(eps)
-    return np.stack([chi * avg * p[0], chi * avg * p[1], chi * avg * p[2]])
+    return np.stack([avg * p[0], avg * p[1], avg * p[2]])
 
 
 def conv(K: np.ndarray, Jh: np.ndarray, targets=None) -> np.ndarray:
@@ -236,3 +240,76 @@ class Oracle:
         if return_P:
             return J[1:], np.array(Ps)
         return J[1:]
+
+    # ------------------------------------------------------------------ adjoint
+    def adjoint(self, g: np.ndarray) -> np.ndarray:
+        """lambda_1..lambda_N of the transposed march for adjoint sources g[j-1] = g_j:
+        the march is the block lower-triangular Toeplitz system sum_k Z_k J_{n-k} = E_n, so
+        its transpose runs backward,
+            Z_0^T lambda_j = g_j - sum_{k=1}^{ell} Z_k^T lambda_{j+k},
+        with Z_k^T = diag(c_k) - K_k (*) (chi .) because every K_k is a symmetric operator
+        (K^ab(D) = K^ba(D) = K^ab(-D), reciprocity of eq:Z).  lambda_j = 0 for j > N."""
+        p = self.p
+        W, V, U = p.W, p.V, p.U
+        N = g.shape[0]
+        chi = chi_of(p.eps)
+        c = local_coefficients(p.eps, self.fir, self.depth)
+        lu_t = spla.splu(self.Z0.T.tocsc())
+        lam = np.zeros((N + 2 + self.depth, 3, W, V, U))     # lam[j] = lambda_j, zero beyond N
+        for j in range(N, 0, -1):
+            b = g[j - 1].copy()
+            for k in range(1, self.depth + 1):
+                if j + k > N:
+                    break
+                b -= c[k][None] * lam[j + k]
+            kk = min(self.ell, N - j)
+            if kk >= 1:
+                nu = np.ascontiguousarray(np.array([chi[None] * lam[j + k] for k in range(1, kk + 1)]))
+                b += conv(self.K[: kk + 1], nu)
+            lam[j] = lu_t.solve(b.ravel()).reshape(3, W, V, U)
+        return lam[1:N + 1]
+
+    def gradient_terms(self, J: np.ndarray, rhs: int = 0) -> np.ndarray:
+        """B_n(m) = <E^i>_m(n) + sum_{k=0}^{ell} (T(k dt) J_{n-k}(m) + (K_k (*) J_{n-k})(m)), the
+        factor of lambda_n(m) / eps_m^2 in dPhi/deps_m (derivative of eq:Z and eq:E in eps:
+        d c_k/d eps = -T(k dt)/eps^2, d chi/d eps = 1/eps^2)."""
+        p = self.p
+        N = J.shape[0]
+        B = np.zeros_like(J)
+        K0 = np.ascontiguousarray(np.stack([self.K[0], self.K[0]]))
+        for n in range(1, N + 1):
+            lo = max(0, n - 1 - self.ell)
+            Jh = np.ascontiguousarray(J[lo:n - 1][::-1])          # Jh[k-1] = J_{n-k}, k >= 1
+            Bn = incident_average(p.U, p.V, p.W, p.waves[rhs], n)
+            Bn = Bn + tbasis(0) * J[n - 1] + conv(K0, np.ascontiguousarray(J[n - 1:n]))
+            if n >= 2:
+                Bn = Bn + tbasis(1) * J[n - 2]
+                Bn = Bn + conv(self.K[: len(Jh) + 1], Jh)
+            B[n - 1] = Bn
+        return B
+
+    def probe_objective_gradient(self, n_steps: int, probes, rhs: int = 0):
+        """Phi = sum_n sum_p |E^s_p(n)|^2 over the march and dPhi/deps_m for every voxel,
+        by the discrete adjoint: g_j = dPhi/dJ_j = 2 sum_k sum_p K_k(r_p - r_m) E^s_p(j+k),
+        lambda from adjoint(), dPhi/deps_m = sum_n lambda_n(m) . B_n(m) / eps_m^2.
+        Returns (Phi, grad[W][V][U], E^s[N][np][3])."""
+        p = self.p
+        W, V, U = p.W, p.V, p.U
+        J = self.run(n_steps, rhs)
+        src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U)]
+        Kp = probe_kernels(probes, src, self.ell)
+        E = probe_field(Kp, J, src)
+        phi = float((E ** 2).sum())
+        Kf = Kp[..., np.array(COMP).ravel()].reshape(Kp.shape[:3] + (3, 3))   # [np][M][k][b][a]
+        N = n_steps
+        g = np.zeros((N, 3, W, V, U))
+        for j in range(1, N + 1):
+            acc = np.zeros((3, len(src)))
+            for k in range(0, min(self.ell, N - j) + 1):
+                acc += 2.0 * np.einsum("pmba,pb->am", Kf[:, :, k], E[j + k - 1])
+            g[j - 1] = acc.reshape(3, W, V, U)
+        lam = self.adjoint(g)
+        B = self.gradient_terms(J, rhs)
+        grad = (lam * B).sum(axis=(0, 1)) / p.eps ** 2
+        return phi, grad, E
+

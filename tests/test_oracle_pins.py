@@ -530,3 +530,78 @@ def test_probe_field_at_voxel_centres_closes_the_march_equation():
             ref = lhs / chi[w, v, u] - Ei[:, w, v, u] / chi[w, v, u]
             err = max(err, np.abs(E[n_ - 1, ip] - ref).max() / (np.abs(ref).max() + 1e-300))
     assert err < 1e-9
+
+
+# ----------------------------------------------------------------------------- adjoint
+def _adjoint_problem():
+    U, V, W, n = 4, 3, 3, 30
+    eps = wl.random_eps(U, V, W, 3, 2.0, 9.0)
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("adj", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1))
+    return prob, wl.fibonacci_sphere(4, 4.0, (2.0, 1.5, 1.5))
+
+
+def test_adjoint_dot_product():
+    """<lambda, E> = <g, J> for the march Z J = E and its transpose Z^T lambda = g, random
+    E and g: the backward recursion is the exact transpose of the forward one."""
+    prob, _ = _adjoint_problem()
+    o = mot.Oracle(prob)
+    N = 25
+    rng = np.random.default_rng(11)
+    E = rng.standard_normal((N, 3, prob.W, prob.V, prob.U))
+    g = rng.standard_normal((N, 3, prob.W, prob.V, prob.U))
+    J = o.run(N, excite=lambda n: E[n - 1])
+    lam = o.adjoint(g)
+    a, b = float((lam * E).sum()), float((g * J).sum())
+    assert abs(a - b) < 1e-11 * max(abs(a), abs(b))
+
+
+def test_adjoint_gradient_matches_finite_differences():
+    """dPhi/deps_m of Phi = sum_n sum_p |E^s_p(n)|^2 against central differences (delta 1e-6)
+    of the forward march at three voxels."""
+    prob, probes = _adjoint_problem()
+    o = mot.Oracle(prob)
+    n = prob.n_steps
+    phi, grad, _ = o.probe_objective_gradient(n, probes)
+    src = [(u, v, w) for w in range(prob.W) for v in range(prob.V) for u in range(prob.U)]
+    Kp = mot.probe_kernels(probes, src, o.ell)
+    for (u, v, w) in [(0, 0, 0), (2, 1, 1), (3, 2, 2)]:
+        vals = []
+        for sgn in (1.0, -1.0):
+            e2 = prob.eps.copy()
+            e2[w, v, u] += sgn * 1e-6
+            p2 = wl.Problem("adj", prob.U, prob.V, prob.W, e2, prob.waves, n, fir=prob.fir)
+            J = mot.Oracle(p2, K=o.K).run(n)
+            vals.append(float((mot.probe_field(Kp, J, src) ** 2).sum()))
+        fd = (vals[0] - vals[1]) / 2e-6
+        assert abs(fd - grad[w, v, u]) < 1e-6 * np.abs(grad).max()
+
+
+def test_adjoint_gradient_local_form():
+    """With the forward equation satisfied, the gradient term reduces to a local one:
+    dPhi/deps_m = 1/(eps (eps - 1)) sum_n lambda_n(m) . sum_k (T(k dt) + delta_k) J_{n-k}(m)."""
+    prob, probes = _adjoint_problem()
+    o = mot.Oracle(prob)
+    n = prob.n_steps
+    phi, grad, E = o.probe_objective_gradient(n, probes)
+    J = o.run(n)
+    src = [(u, v, w) for w in range(prob.W) for v in range(prob.V) for u in range(prob.U)]
+    Kp = mot.probe_kernels(probes, src, o.ell)
+    Kf = Kp[..., np.array(mot.COMP).ravel()].reshape(Kp.shape[:3] + (3, 3))
+    g = np.zeros_like(J)
+    for j in range(1, n + 1):
+        acc = np.zeros((3, len(src)))
+        for k in range(0, min(o.ell, n - j) + 1):
+            acc += 2.0 * np.einsum("pmba,pb->am", Kf[:, :, k], E[j + k - 1])
+        g[j - 1] = acc.reshape(J.shape[1:])
+    lam = o.adjoint(g)
+    fir = np.asarray(prob.fir)
+    loc = np.zeros_like(J)
+    for m in range(1, n + 1):
+        for k in range(0, min(m, max(3, len(fir)))):
+            w_ = mot.tbasis(k) + (fir[k] if k < len(fir) else 0.0)
+            loc[m - 1] += w_ * J[m - 1 - k]
+    eps = prob.eps
+    ref = (lam * loc).sum(axis=(0, 1)) / (eps * (eps - 1.0))
+    assert np.abs(ref - grad).max() < 1e-9 * np.abs(grad).max()
