@@ -147,6 +147,35 @@ int mj_march(mj_solver *s, int32_t n_steps, double *J_hist, double *probe_hist);
 int mj_probe_kernel_values(mj_solver *s, int32_t n, const int32_t *probe, const int32_t *voxel,
                            const int32_t *lag, double *out);
 
+/*
+ * mj_set_eps -- new relative permittivities (host [W][V][U], >= 1, copied) for the same
+ *   grid: chi, the local coefficients c_k, Z_0 and its preconditioner are rebuilt; the
+ *   interaction kernels do not depend on eps and are kept.  Only at n = 0, else MJ_ESTATE.
+ */
+int mj_set_eps(mj_solver *s, const double *eps_r);
+
+/*
+ * mj_adjoint_gradient -- objective Phi = sum_{n=1}^{n_steps} sum_rhs sum_p |E^s_p(n)|^2 over
+ *   the probes set by mj_set_probes, and its gradient with respect to eps_r of every voxel,
+ *   by the transposed (adjoint) march: with the march written as the block lower-triangular
+ *   Toeplitz system sum_k Z_k J_{n-k} = E_n (eq:MatrixEquation), lambda solves
+ *     Z_0^T lambda_j = dPhi/dJ_j - sum_{k>=1} Z_k^T lambda_{j+k},
+ *     Z_k^T = diag(c_k) - K_k (*) (chi .)   (every K_k is symmetric: reciprocity of eq:Z),
+ *   marched backward through the same FFT history sum, and
+ *     dPhi/deps_m = sum_n lambda_n(m) . B_n(m) / eps_m^2,
+ *     B_n = <E^i>(n) + sum_{k=0}^{ell} (T(k dt) J_{n-k} + K_k (*) J_{n-k}).
+ *   Checkpointing: the forward march is run once, keeping the real-space history needed to
+ *   restart it every ckpt_every steps (rounded up to a multiple of the time block; <= 0:
+ *   one segment, nothing recomputed); the backward pass recomputes each segment from its
+ *   checkpoint before marching back through it.  Memory: (segments - 1) (ell + 1) plus one
+ *   segment of 3 M n_rhs values, and a second set of rings for the adjoint march.
+ *   phi: host, nullable.  dphi_deps: device [W][V][U] (overwritten).  probe_hist: device,
+ *   nullable, [n_steps][n_rhs][n_probes][3] receives the forward probe field.  Starts at
+ *   n = 0 (else MJ_ESTATE) and leaves the march at n = 0.
+ */
+int mj_adjoint_gradient(mj_solver *s, int32_t n_steps, int32_t ckpt_every, double *phi, double *dphi_deps,
+                        double *probe_hist);
+
 /* mj_reset -- restart the march at n = 0 (all past currents zero). */
 int mj_reset(mj_solver *s);
 
@@ -170,12 +199,13 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
 
 /*
  * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
- *   in ms per step, and CG statistics.  out (host, n <= 14): [0] forward FFT  [1] history
+ *   in ms per step, and CG statistics.  out (host, n <= 17): [0] forward FFT  [1] history
  *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total
  *   [6] mean CG iterations  [7] max final relative residual  [8] steps timed
  *   [9] max CG iterations  [10] mean duration of one far-part MAC launch (time-blocked,
  *   once per block)  [11] far-part launches  [12] mean duration of one near-part launch
- *   [13] probes.  [5] includes [13].
+ *   [13] probes.  [5] includes [13].  After mj_adjoint_gradient: [14] forward pass (ms,
+ *   whole run)  [15] backward pass with recomputation (ms)  [16] segments.
  */
 int mj_stats(const mj_solver *s, double *out, int32_t n);
 

@@ -3,4 +3,4 @@
 The computation lives in libmotjvie.so (C interface: include/motjvie.h); this package
 only builds it (build.py) and marshals arguments to it (motjvie.py).
 """
-from .motjvie import MotJvieError, Solver, load_library, solver_for  # noqa: F401
+from .motjvie import MotJvieError, ProbeObjective, Solver, load_library, solver_for  # noqa: F401

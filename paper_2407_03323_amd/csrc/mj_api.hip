@@ -90,10 +90,12 @@ struct mj_solver {
     int np = 0, nw = 0;
     long npairs = 0;
     double *probe_pos = nullptr, *ptable = nullptr, *ppart = nullptr, *pout = nullptr;
-    int *pair_vox = nullptr, *pair_kmin = nullptr, *row_start = nullptr;
+    int *pair_vox = nullptr, *pair_kmin = nullptr, *row_start = nullptr, *pinv = nullptr;
+    // transposed march: local history lambda, and the right-hand side before its sqrt(chi) scaling
+    double *Lr = nullptr, *bq = nullptr;
     // statistics of the last run
     double t_gen_ms = 0, t_spec_ms = 0, t_probe_ms = 0;
-    double stat[14] = {};
+    double stat[17] = {};
     Events events;
 
     template <class T>
@@ -139,7 +141,24 @@ struct mj_solver {
 
     void create(const mj_config &c);
     void build_spectra();
+    void set_material(const double *eps);
+    struct StepIO {
+        hipEvent_t *ev = nullptr;       // 7 events, or NULL
+        double *Jout = nullptr;         // forward: J_n copy
+        double *Pout = nullptr;         // forward: probe field of the step (else the internal buffer)
+        bool skip_probes = false;
+        double *Bout = nullptr;         // forward: gradient term B_n
+        char *far_kind = nullptr;       // 1 far launch, 2 near launch
+        bool adjoint = false;           // transposed march
+        const double *G = nullptr;      // adjoint: source g_j
+        const double *Bj = nullptr;     // adjoint: B_j for the gradient (NULL: none)
+        double *grad = nullptr;         // adjoint: gradient accumulator
+    };
+    mj::EpiArg epi_arg() const;
+    mj::AdjArg adj_arg() const;
+    void step(const StepIO &io);
     void run(int n_steps, double *Jout, double *Pout);
+    void adjoint_gradient(int n_steps, int ckpt_every, double *phi, double *grad_dev, double *probe_hist);
     void set_probes(int n_probes, const double *pos);
     void offgrid_values(int n, const int *probe, const int *vox, const int *lag, double *out);
     void solve_z0();
@@ -187,37 +206,16 @@ void mj_solver::create(const mj_config &c)
     nloc = std::max(5, (int)fir.size() - 1);   // >= 5: the solve's initial guess uses five steps
     rdepth = nloc + 1;
 
-    // material
-    std::vector<double> chi_h(M), schi_h(M), ie_h(M), c0_h(M);
-    const double d0 = fir.empty() ? 0.0 : fir[0];
-    for (long i = 0; i < M; i++) {
-        chi_h[i] = (eps[i] - 1.0) / eps[i];
-        schi_h[i] = std::sqrt(chi_h[i]);
-        ie_h[i] = 1.0 / eps[i];
-        c0_h[i] = 0.5 * ie_h[i] + d0;   // T(0)/eps + delta_0
-    }
     chi = dalloc<double>(M, "chi");
     schi = dalloc<double>(M, "sqrt chi");
     inv_eps = dalloc<double>(M, "1/eps");
     c0 = dalloc<double>(M, "c0");
     inv_diag = dalloc<double>(M, "Jacobi");
-    MJ_CHECK(hipMemcpy(chi, chi_h.data(), M * 8, hipMemcpyHostToDevice));
-    MJ_CHECK(hipMemcpy(schi, schi_h.data(), M * 8, hipMemcpyHostToDevice));
-    MJ_CHECK(hipMemcpy(inv_eps, ie_h.data(), M * 8, hipMemcpyHostToDevice));
-    MJ_CHECK(hipMemcpy(c0, c0_h.data(), M * 8, hipMemcpyHostToDevice));
     fir_d = dalloc<double>(std::max<size_t>(fir.size(), 1), "fir");
     if (!fir.empty()) MJ_CHECK(hipMemcpy(fir_d, fir.data(), fir.size() * 8, hipMemcpyHostToDevice));
 
     build_spectra();
-
-    // Jacobi preconditioner diag(A) = c_0 - chi K_0^{bb}(0)
-    const double k0self = K0_27[13 * 6 + 0];
-    std::vector<double> idg(M);
-    for (long i = 0; i < M; i++) {
-        double d = c0_h[i] - chi_h[i] * k0self;
-        idg[i] = chi_h[i] > 0.0 ? 1.0 / d : 0.0;
-    }
-    MJ_CHECK(hipMemcpy(inv_diag, idg.data(), M * 8, hipMemcpyHostToDevice));
+    set_material(eps.data());
 
     // march state
     const long sp = spec_plane();
@@ -252,6 +250,31 @@ void mj_solver::create(const mj_config &c)
     bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hx + (size_t)3 * nrhs * W * Ny * Hx);
     n = 0;
     MJ_CHECK(hipStreamSynchronize(st));
+}
+
+// chi, sqrt chi, 1/eps, c_0 = T(0)/eps + delta_0 and the Jacobi preconditioner
+// diag(A) = c_0 - chi K_0^{bb}(0) of the symmetrised Z_0 (needs K_0 from build_spectra)
+void mj_solver::set_material(const double *eps)
+{
+    for (long i = 0; i < M; i++)
+        if (!(eps[i] >= 1.0) || !std::isfinite(eps[i])) throw ArgError("eps_r must be finite and >= 1");
+    eps_h.assign(eps, eps + M);
+    std::vector<double> chi_h(M), schi_h(M), ie_h(M), c0_h(M), idg(M);
+    const double d0 = fir.empty() ? 0.0 : fir[0];
+    const double k0self = K0_27[13 * 6 + 0];
+    for (long i = 0; i < M; i++) {
+        chi_h[i] = (eps[i] - 1.0) / eps[i];
+        schi_h[i] = std::sqrt(chi_h[i]);
+        ie_h[i] = 1.0 / eps[i];
+        c0_h[i] = 0.5 * ie_h[i] + d0;   // T(0)/eps + delta_0
+        const double d = c0_h[i] - chi_h[i] * k0self;
+        idg[i] = chi_h[i] > 0.0 ? 1.0 / d : 0.0;
+    }
+    MJ_CHECK(hipMemcpy(chi, chi_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(schi, schi_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(inv_eps, ie_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(c0, c0_h.data(), M * 8, hipMemcpyHostToDevice));
+    MJ_CHECK(hipMemcpy(inv_diag, idg.data(), M * 8, hipMemcpyHostToDevice));
 }
 
 void mj_solver::build_spectra()
@@ -384,122 +407,144 @@ void mj_solver::solve_z0()
     cg_guess = mx + 1;
 }
 
-void mj_solver::run(int n_steps, double *Jout, double *Pout)
+// 8-point Gauss-Legendre on [-1/2, 1/2] (weights summing to 1), long double Newton
+static void gl8_half(double *x, double *w)
 {
-    if (!waves_set) throw std::logic_error("plane waves not set (mj_set_plane_waves)");
-    events.ensure((size_t)7 * std::max(n_steps, 1));
-    double cg_iter_sum = 0, cg_res_max = 0, cg_iter_max = 0;
-    bool noconv = false;
-    const long sp = spec_plane();
-    double glx8[8], glw8[8];
-    {
-        // 8-point Gauss-Legendre on [-1/2, 1/2] (weights summing to 1), long double Newton
-        const long double pi = 3.141592653589793238462643383279502884L;
-        for (int i = 0; i < 8; i++) {
-            long double zz = cosl(pi * (i + 0.75L) / 8.5L);
-            long double dp = 0;
-            for (int itn = 0; itn < 50; itn++) {
-                long double p0 = 1, p1 = zz;
-                for (int j = 2; j <= 8; j++) {
-                    long double p2 = ((2 * j - 1) * zz * p1 - (j - 1) * p0) / j;
-                    p0 = p1;
-                    p1 = p2;
-                }
-                dp = 8 * (zz * p1 - p0) / (zz * zz - 1);
-                long double d = p1 / dp;
-                zz -= d;
-                if (fabsl(d) < 1e-19L) break;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < 8; i++) {
+        long double zz = cosl(pi * (i + 0.75L) / 8.5L);
+        long double dp = 0;
+        for (int itn = 0; itn < 50; itn++) {
+            long double p0 = 1, p1 = zz;
+            for (int j = 2; j <= 8; j++) {
+                long double p2 = ((2 * j - 1) * zz * p1 - (j - 1) * p0) / j;
+                p0 = p1;
+                p1 = p2;
             }
-            glx8[i] = (double)(0.5L * zz);
-            glw8[i] = (double)(1.0L / ((1 - zz * zz) * dp * dp));
+            dp = 8 * (zz * p1 - p0) / (zz * zz - 1);
+            long double d = p1 / dp;
+            zz -= d;
+            if (fabsl(d) < 1e-19L) break;
         }
+        x[i] = (double)(0.5L * zz);
+        w[i] = (double)(1.0L / ((1 - zz * zz) * dp * dp));
     }
-    std::vector<char> step_far(n_steps, 0);
-    for (int s = 0; s < n_steps; s++) {
-        hipEvent_t *ev = &events.ev[(size_t)7 * s];
-        MJ_CHECK(hipEventRecord(ev[0], st));
-        n += 1;
-        const bool hist = n >= 2;
-        if (hist) {
-            const int j = n - 1;
-            mj::fft3d_forward(fft, Jr + (size_t)slotR(j) * nrhs * 3 * M, ring + (size_t)slotS(j) * nrhs * 3 * sp,
-                              3 * nrhs, st);
+}
+
+mj::EpiArg mj_solver::epi_arg() const
+{
+    mj::EpiArg e{};
+    e.M = M;
+    e.U = U;
+    e.V = V;
+    e.W = W;
+    e.nrhs = nrhs;
+    e.n = n;
+    e.h = h;
+    e.c_dt = c_dt;
+    e.chi = chi;
+    e.schi = schi;
+    e.inv_eps = inv_eps;
+    e.fir = fir_d;
+    e.nfir = (int)fir.size();
+    e.nloc = nloc;
+    for (int k = 1; k <= nloc; k++) e.slot_of[k] = n - k >= 1 ? slotR(n - k) : 0;
+    e.Jring = Jr;
+    e.waves = waves_d;
+    gl8_half(e.glx8, e.glw8);
+    e.rhs = rhs;
+    e.y = y;
+    e.uy = uy;
+    return e;
+}
+
+// One step n -> n + 1 of the march on the current track: FFT of the newest source, spectral
+// history sum (plain or time-blocked), inverse FFT, right-hand side, Z_0 solve, and the
+// outputs asked for.  io.adjoint runs the transposed march instead (sources nu, local
+// history lambda in Lr, right-hand side from io.G).
+void mj_solver::step(const StepIO &io)
+{
+    const long sp = spec_plane();
+    hipEvent_t *ev = io.ev;
+    if (ev) MJ_CHECK(hipEventRecord(ev[0], st));
+    n += 1;
+    const bool hist = n >= 2;
+    if (hist) {
+        const int j = n - 1;
+        mj::fft3d_forward(fft, Jr + (size_t)slotR(j) * nrhs * 3 * M, ring + (size_t)slotS(j) * nrhs * 3 * sp,
+                          3 * nrhs, st);
+    }
+    if (ev) MJ_CHECK(hipEventRecord(ev[1], st));
+    const double2 *spec = Shat;
+    int far_kind = 0;
+    if (hist && B == 1) {
+        mj::MacArg a{};
+        a.Khat = Khat;
+        a.ring_base = ring;
+        a.Shat = Shat;
+        a.Hx = Hx;
+        a.Ny = Ny;
+        a.Nz = Nz;
+        a.nk = std::min(ell, n - 1);
+        a.ring = ell;
+        a.slot_nm1 = slotS(n - 1);
+        a.nrhs = nrhs;
+        mj::launch_mac(a, st);
+    } else if (hist) {
+        // blocks of B steps starting at n_b = 2, 2 + B, ...: the far part of every step of the
+        // block is formed at n_b, when all of its sources are in the ring
+        const int t = (n - 2) % B;
+        mj::BlockMacArg a{};
+        a.Khat = Khat;
+        a.ring_base = ring;
+        a.far = farbuf;
+        a.Hx = Hx;
+        a.Ny = Ny;
+        a.Nz = Nz;
+        a.nk = ell;
+        a.ring = ell;
+        a.nb = n - t;
+        a.ntarget = B;
+        a.t = t;
+        a.nrhs = nrhs;
+        if (t == 0) mj::launch_mac_far(a, B, st);
+        else mj::launch_mac_near(a, st);
+        far_kind = t == 0 ? 1 : 2;
+        spec = farbuf + (size_t)t * nrhs * 3 * sp;
+    }
+    if (io.far_kind) *io.far_kind = (char)far_kind;
+    if (ev) MJ_CHECK(hipEventRecord(ev[2], st));
+    if (hist) mj::fft3d_inverse(fft, spec, S, 3 * nrhs, st);
+    if (ev) MJ_CHECK(hipEventRecord(ev[3], st));
+    mj::EpiArg e = epi_arg();
+    e.S = hist ? S : nullptr;
+    if (io.adjoint) {
+        e.Lring = Lr;
+        e.G = io.G;
+        e.bq = bq;
+        mj::launch_adj_epilogue(e, st);
+    } else {
+        mj::launch_epilogue(e, st);
+    }
+    if (ev) MJ_CHECK(hipEventRecord(ev[4], st));
+    solve_z0();
+    double *Jn = Jr + (size_t)slotR(n) * nrhs * 3 * M;
+    mj::launch_cg_finish(y, schi, M, nrhs, Jn, io.Jout, st);
+    if (ev) MJ_CHECK(hipEventRecord(ev[5], st));
+    if (io.adjoint) {
+        mj::AdjArg a = adj_arg();
+        a.y = y;
+        a.nu = Jn;
+        a.bq = bq;
+        a.lam = Lr + (size_t)slotR(n) * nrhs * 3 * M;
+        mj::launch_adj_lambda(a, st);
+        if (io.Bj) {
+            a.Bj = io.Bj;
+            a.grad = io.grad;
+            mj::launch_grad_accum(a, st);
         }
-        MJ_CHECK(hipEventRecord(ev[1], st));
-        const double2 *spec = Shat;
-        if (hist && B == 1) {
-            mj::MacArg a{};
-            a.Khat = Khat;
-            a.ring_base = ring;
-            a.Shat = Shat;
-            a.Hx = Hx;
-            a.Ny = Ny;
-            a.Nz = Nz;
-            a.nk = std::min(ell, n - 1);
-            a.ring = ell;
-            a.slot_nm1 = slotS(n - 1);
-            a.nrhs = nrhs;
-            mj::launch_mac(a, st);
-        } else if (hist) {
-            // blocks of B steps starting at n_b = 2, 2 + B, ...: the far part of every step of the
-            // block is formed at n_b, when all of its sources are in the ring
-            const int t = (n - 2) % B;
-            mj::BlockMacArg a{};
-            a.Khat = Khat;
-            a.ring_base = ring;
-            a.far = farbuf;
-            a.Hx = Hx;
-            a.Ny = Ny;
-            a.Nz = Nz;
-            a.nk = ell;
-            a.ring = ell;
-            a.nb = n - t;
-            a.ntarget = B;
-            a.t = t;
-            a.nrhs = nrhs;
-            if (t == 0) mj::launch_mac_far(a, B, st);
-            else mj::launch_mac_near(a, st);
-            step_far[s] = t == 0 ? 1 : 2;
-            spec = farbuf + (size_t)t * nrhs * 3 * sp;
-        }
-        MJ_CHECK(hipEventRecord(ev[2], st));
-        if (hist) mj::fft3d_inverse(fft, spec, S, 3 * nrhs, st);
-        MJ_CHECK(hipEventRecord(ev[3], st));
-        {
-            mj::EpiArg e{};
-            e.M = M;
-            e.U = U;
-            e.V = V;
-            e.W = W;
-            e.nrhs = nrhs;
-            e.n = n;
-            e.h = h;
-            e.c_dt = c_dt;
-            e.chi = chi;
-            e.schi = schi;
-            e.inv_eps = inv_eps;
-            e.fir = fir_d;
-            e.nfir = (int)fir.size();
-            e.nloc = nloc;
-            for (int k = 1; k <= nloc; k++) e.slot_of[k] = n - k >= 1 ? slotR(n - k) : 0;
-            e.Jring = Jr;
-            e.S = hist ? S : nullptr;
-            e.waves = waves_d;
-            for (int i = 0; i < 8; i++) {
-                e.glx8[i] = glx8[i];
-                e.glw8[i] = glw8[i];
-            }
-            e.rhs = rhs;
-            e.y = y;
-            e.uy = uy;
-            mj::launch_epilogue(e, st);
-        }
-        MJ_CHECK(hipEventRecord(ev[4], st));
-        solve_z0();
-        mj::launch_cg_finish(y, schi, M, nrhs, Jr + (size_t)slotR(n) * nrhs * 3 * M,
-                             Jout ? Jout + (size_t)s * nrhs * 3 * M : nullptr, st);
-        MJ_CHECK(hipEventRecord(ev[5], st));
-        if (np > 0) {
+    } else {
+        if (np > 0 && !io.skip_probes) {
             mj::ProbeStepArg pa{};
             pa.table = ptable;
             pa.pair_vox = pair_vox;
@@ -514,10 +559,48 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout)
             pa.Jring = Jr;
             pa.rdepth = rdepth;
             pa.part = ppart;
-            pa.out = Pout ? Pout + (size_t)s * nrhs * np * 3 : pout;
+            pa.out = io.Pout ? io.Pout : pout;
             mj::launch_probes(pa, st);
         }
-        MJ_CHECK(hipEventRecord(ev[6], st));
+        if (io.Bout)
+            mj::launch_grad_term(e, Jn, n >= 2 ? Jr + (size_t)slotR(n - 1) * nrhs * 3 * M : nullptr, io.Bout, st);
+    }
+    if (ev) MJ_CHECK(hipEventRecord(ev[6], st));
+}
+
+mj::AdjArg mj_solver::adj_arg() const
+{
+    mj::AdjArg a{};
+    a.M = M;
+    a.U = U;
+    a.V = V;
+    a.W = W;
+    a.nrhs = nrhs;
+    a.table = ptable;
+    a.pair_kmin = pair_kmin;
+    a.inv = pinv;
+    a.np = np;
+    a.nw = nw;
+    a.schi = schi;
+    a.c0 = c0;
+    a.inv_eps = inv_eps;
+    return a;
+}
+
+void mj_solver::run(int n_steps, double *Jout, double *Pout)
+{
+    if (!waves_set) throw std::logic_error("plane waves not set (mj_set_plane_waves)");
+    events.ensure((size_t)7 * std::max(n_steps, 1));
+    double cg_iter_sum = 0, cg_res_max = 0, cg_iter_max = 0;
+    bool noconv = false;
+    std::vector<char> step_far(n_steps, 0);
+    for (int s = 0; s < n_steps; s++) {
+        StepIO io;
+        io.ev = &events.ev[(size_t)7 * s];
+        io.Jout = Jout ? Jout + (size_t)s * nrhs * 3 * M : nullptr;
+        io.Pout = Pout ? Pout + (size_t)s * nrhs * np * 3 : nullptr;
+        io.far_kind = &step_far[s];
+        step(io);
         for (int i = 0; i < nrhs; i++) {
             cg_iter_sum += cgstat_h[i].iters;
             cg_iter_max = std::max(cg_iter_max, (double)cgstat_h[i].iters);
@@ -622,6 +705,7 @@ void mj_solver::set_probes(int n_probes, const double *pos)
     dfree((void *&)pair_vox);
     dfree((void *&)pair_kmin);
     dfree((void *&)row_start);
+    dfree((void *&)pinv);
     np = 0;
     nw = 0;
     npairs = 0;
@@ -629,9 +713,10 @@ void mj_solver::set_probes(int n_probes, const double *pos)
     const double r = c_dt / h;
     std::vector<double> P(3 * (size_t)n_probes);
     for (size_t i = 0; i < P.size(); i++) P[i] = pos[i] / h;
-    std::vector<int> src;
-    for (long m = 0; m < M; m++)
-        if (eps_h[m] != 1.0) src.push_back((int)m);
+    // every voxel is a source: voxels with eps_r = 1 carry no current in the march, but the
+    // transposed march needs the probe kernels there (their lambda enters the eps-gradient)
+    std::vector<int> src((size_t)M);
+    for (long m = 0; m < M; m++) src[(size_t)m] = (int)m;
     struct Pair {
         int kmin, vox;
     };
@@ -676,6 +761,12 @@ void mj_solver::set_probes(int n_probes, const double *pos)
     pair_vox = dalloc<int>(std::max<size_t>(pv.size(), 1), "probe pairs");
     pair_kmin = dalloc<int>(std::max<size_t>(pk.size(), 1), "probe windows");
     row_start = dalloc<int>(rs.size(), "probe rows");
+    {
+        std::vector<int> inv((size_t)n_probes * M, -1);
+        for (size_t q = 0; q < pp.size(); q++) inv[(size_t)pp[q] * M + pv[q]] = (int)q;
+        pinv = dalloc<int>(inv.size(), "probe pair index");
+        MJ_CHECK(hipMemcpy(pinv, inv.data(), sizeof(int) * inv.size(), hipMemcpyHostToDevice));
+    }
     int *pair_probe = dalloc<int>(std::max<size_t>(pp.size(), 1), "probe pair owners");
     ptable = dalloc<double>((size_t)std::max<long>(npairs, 1) * nw * 6, "probe kernel table");
     ppart = dalloc<double>((size_t)nrhs * np * (ell + 1) * 3, "probe partial sums");
@@ -748,6 +839,175 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
     (void)hipFree(d_v);
     (void)hipFree(d_k);
     (void)hipFree(d_o);
+}
+
+// Gradient of Phi = sum_{n=1}^{N} sum_r sum_p |E^s_{r,p}(n)|^2 with respect to eps_r of every
+// voxel, by the transposed march (see mj_march.hip) with checkpointing:
+//  1. forward march of all N steps, keeping the probe field of every step and, at the start
+//     of every segment but the first, the real-space history J_{n0-ell-1} .. J_{n0-1} that a
+//     restart at n0 needs; segments start at time-block starts, so a restart begins with a
+//     far-part launch like the original march did;
+//  2. segments from last to first: recompute the segment's forward steps from its checkpoint
+//     (the last one is kept from step 1), storing B_n, then run the transposed march over the
+//     segment's steps in reversed time, accumulating lambda_n . B_n / eps^2.
+// The recomputed steps repeat the original arithmetic exactly.  Leaves the march at n = 0.
+void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *grad_dev, double *probe_hist)
+{
+    if (!waves_set) throw std::logic_error("plane waves not set (mj_set_plane_waves)");
+    if (np <= 0) throw std::logic_error("the objective is the probe field: set probes first");
+    if (n != 0) throw std::logic_error("the gradient run starts at n = 0 (mj_reset)");
+    if (N < 1) throw ArgError("n_steps must be >= 1");
+    if (rdepth < ell + 1) throw std::logic_error("probe history depth");
+    // segment starts: 1, then block starts 2 + c L with L a multiple of the time block
+    int L = ckpt_every > 0 ? ckpt_every : N;
+    if (B > 1) L = ((L + B - 1) / B) * B;
+    std::vector<int> starts{1};
+    for (long s0 = 2 + (long)L; s0 <= N; s0 += L) starts.push_back((int)s0);
+    const int C = (int)starts.size();
+    auto seg_end = [&](int c) { return c + 1 < C ? starts[c + 1] - 1 : N; };
+    int maxseg = 0;
+    for (int c = 0; c < C; c++) maxseg = std::max(maxseg, seg_end(c) - starts[c] + 1);
+    const size_t vec = (size_t)nrhs * 3 * M;
+    const size_t win = (size_t)ell + 1;
+    const long sp = spec_plane();
+    std::vector<void *> tmp;
+    auto talloc = [&](size_t bytes, const char *what) {
+        void *ptr = nullptr;
+        if (hipMalloc(&ptr, std::max<size_t>(bytes, 8)) != hipSuccess) {
+            (void)hipGetLastError();
+            for (void *q : tmp) (void)hipFree(q);
+            throw MemError(std::string("device allocation failed: ") + what);
+        }
+        tmp.push_back(ptr);
+        return ptr;
+    };
+    double *Ehist = (double *)talloc(sizeof(double) * (size_t)N * nrhs * np * 3, "probe history");
+    double *ckpt = (double *)talloc(sizeof(double) * (size_t)std::max(C - 1, 1) * win * vec, "checkpoints");
+    double *Bbuf = (double *)talloc(sizeof(double) * (size_t)maxseg * vec, "gradient terms");
+    double *G = (double *)talloc(sizeof(double) * vec, "adjoint source");
+    double *bqb = (double *)talloc(sizeof(double) * vec, "adjoint rhs");
+    double2 *ring_a = (double2 *)talloc(sizeof(double2) * (size_t)ell * nrhs * 3 * sp, "adjoint ring");
+    double2 *far_a = B > 1 ? (double2 *)talloc(sizeof(double2) * (size_t)B * nrhs * 3 * sp, "adjoint blocks") : nullptr;
+    double *nu_r = (double *)talloc(sizeof(double) * (size_t)rdepth * vec, "adjoint history");
+    double *lam_r = (double *)talloc(sizeof(double) * (size_t)rdepth * vec, "adjoint local history");
+    MJ_CHECK(hipMemsetAsync(grad_dev, 0, sizeof(double) * M, st));
+    double2 *const ring_f = ring, *const far_f = farbuf;
+    double *const Jr_f = Jr;
+    hipEvent_t tev[3];
+    for (auto &tv : tev) MJ_CHECK(hipEventCreate(&tv));
+    MJ_CHECK(hipEventRecord(tev[0], st));
+    bool noconv = false;
+    auto check_cg = [&] {
+        for (int i = 0; i < nrhs; i++)
+            if (!cgstat_h[i].done) noconv = true;
+    };
+    try {
+        // 1. forward
+        const int last0 = starts[C - 1];
+        int next_ck = 1;
+        for (int t = 1; t <= N; t++) {
+            StepIO io;
+            io.Pout = Ehist + (size_t)(t - 1) * nrhs * np * 3;
+            io.Bout = t >= last0 ? Bbuf + (size_t)(t - last0) * vec : nullptr;
+            step(io);
+            check_cg();
+            if (next_ck < C && t + 1 == starts[next_ck]) {
+                // J_j for j = t - ell .. t (those with j >= 1) from the real-space ring
+                for (int j = std::max(1, t - ell); j <= t; j++)
+                    MJ_CHECK(hipMemcpyAsync(ckpt + ((size_t)(next_ck - 1) * win + (size_t)(j - (t - ell))) * vec,
+                                            Jr + (size_t)slotR(j) * vec, sizeof(double) * vec,
+                                            hipMemcpyDeviceToDevice, st));
+                next_ck++;
+            }
+        }
+        if (probe_hist)
+            MJ_CHECK(hipMemcpyAsync(probe_hist, Ehist, sizeof(double) * (size_t)N * nrhs * np * 3,
+                                    hipMemcpyDeviceToDevice, st));
+        std::vector<double> Eh((size_t)N * nrhs * np * 3);
+        MJ_CHECK(hipMemcpyAsync(Eh.data(), Ehist, sizeof(double) * Eh.size(), hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipStreamSynchronize(st));
+        double ph = 0.0;
+        for (double v : Eh) ph += v * v;
+        if (phi) *phi = ph;
+        MJ_CHECK(hipEventRecord(tev[1], st));
+        // 2. backward; the transposed march has its own rings, swapped in while it runs
+        int n_adj = 0;
+        for (int c = C - 1; c >= 0; c--) {
+            const int s0 = starts[c], s1 = seg_end(c);
+            if (c < C - 1) {
+                // restart the forward march at s0 from its checkpoint and recompute the segment
+                n = s0 - 1;
+                if (c > 0) {
+                    const int j0 = s0 - 1 - ell;   // first stored step
+                    for (int j = std::max(1, j0); j <= s0 - 1; j++) {
+                        const double *src = ckpt + ((size_t)(c - 1) * win + (size_t)(j - j0)) * vec;
+                        MJ_CHECK(hipMemcpyAsync(Jr + (size_t)slotR(j) * vec, src, sizeof(double) * vec,
+                                                hipMemcpyDeviceToDevice, st));
+                        if (j <= s0 - 2)
+                            mj::fft3d_forward(fft, src, ring + (size_t)slotS(j) * nrhs * 3 * sp, 3 * nrhs, st);
+                    }
+                }
+                for (int t = s0; t <= s1; t++) {
+                    StepIO io;
+                    io.skip_probes = true;
+                    io.Bout = Bbuf + (size_t)(t - s0) * vec;
+                    step(io);
+                    check_cg();
+                }
+            }
+            // transposed march over j = s1 .. s0 (reversed step n' = N + 1 - j)
+            ring = ring_a;
+            farbuf = far_a;
+            Jr = nu_r;
+            Lr = lam_r;
+            bq = bqb;
+            n = n_adj;
+            for (int j = s1; j >= s0; j--) {
+                mj::AdjArg a = adj_arg();
+                a.Ehist = Ehist;
+                a.N = N;
+                a.j = j;
+                a.G = G;
+                mj::launch_adj_source(a, st);
+                StepIO io;
+                io.adjoint = true;
+                io.G = G;
+                io.Bj = Bbuf + (size_t)(j - s0) * vec;
+                io.grad = grad_dev;
+                step(io);
+                check_cg();
+            }
+            n_adj = n;
+            ring = ring_f;
+            farbuf = far_f;
+            Jr = Jr_f;
+            Lr = nullptr;
+            bq = nullptr;
+        }
+        MJ_CHECK(hipEventRecord(tev[2], st));
+        MJ_CHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        ring = ring_f;
+        farbuf = far_f;
+        Jr = Jr_f;
+        Lr = nullptr;
+        bq = nullptr;
+        for (void *q : tmp) (void)hipFree(q);
+        for (auto &tv : tev) (void)hipEventDestroy(tv);
+        n = 0;
+        throw;
+    }
+    float f_ms = 0, b_ms = 0;
+    MJ_CHECK(hipEventElapsedTime(&f_ms, tev[0], tev[1]));
+    MJ_CHECK(hipEventElapsedTime(&b_ms, tev[1], tev[2]));
+    stat[14] = f_ms;
+    stat[15] = b_ms;
+    stat[16] = C;
+    for (void *q : tmp) (void)hipFree(q);
+    for (auto &tv : tev) (void)hipEventDestroy(tv);
+    n = 0;
+    if (noconv) throw std::range_error("Z_0 solve did not converge");
 }
 
 // ============================================================================ C ABI
@@ -856,6 +1116,23 @@ int mj_march(mj_solver *s, int32_t n_steps, double *J_hist, double *probe_hist)
     return guarded(s, [&] { s->run(n_steps, J_hist, probe_hist); });
 }
 
+int mj_set_eps(mj_solver *s, const double *eps_r)
+{
+    if (!s || !eps_r) return MJ_EINVAL;
+    return guarded(s, [&] {
+        if (s->n != 0) throw std::logic_error("eps is changed at n = 0 (after mj_create or mj_reset)");
+        s->set_material(eps_r);
+    });
+}
+
+int mj_adjoint_gradient(mj_solver *s, int32_t n_steps, int32_t ckpt_every, double *phi, double *dphi_deps,
+                        double *probe_hist)
+{
+    if (!s || !dphi_deps) return MJ_EINVAL;
+    if (n_steps < 1) return fail(s, MJ_EINVAL, "n_steps < 1");
+    return guarded(s, [&] { s->adjoint_gradient(n_steps, ckpt_every, phi, dphi_deps, probe_hist); });
+}
+
 int mj_set_probes(mj_solver *s, int32_t n_probes, const double *pos)
 {
     if (!s) return MJ_EINVAL;
@@ -915,7 +1192,7 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
 int mj_stats(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    for (int i = 0; i < n && i < 14; i++) out[i] = s->stat[i];
+    for (int i = 0; i < n && i < 17; i++) out[i] = s->stat[i];
     return MJ_OK;
 }
 

@@ -53,6 +53,30 @@ struct EpiArg {
     double glx8[8], glw8[8]; // 8-point rule on [-1/2, 1/2], weights summing to 1
     double *rhs, *y;         // [nrhs][3][M]
     double *uy;              // sqrt(chi) y0 in the zero-haloed layout [nrhs][3][(W+2)(V+2)(U+2)]
+    // transposed march only
+    const double *Lring;     // lambda history [depth][nrhs][3][M] (the local terms act on lambda)
+    const double *G;         // adjoint source g_j [nrhs][3][M]
+    double *bq;              // b'_j, kept for the voxels with chi = 0 [nrhs][3][M]
+};
+
+// Adjoint of the probe objective and the eps-gradient (see mj_march.hip).
+struct AdjArg {
+    long M;
+    int U, V, W, nrhs;
+    // adjoint source from the stored probe field
+    const double *table;     // probe kernel table [npairs][nw][6]
+    const int *pair_kmin;    // [npairs]
+    const int *inv;          // [np][M] pair of (probe, voxel), -1 if none
+    const double *Ehist;     // [N][nrhs][np][3]
+    int np, nw, N, j;        // j: forward step of this adjoint step
+    double *G;               // out [nrhs][3][M]
+    // lambda from the solve
+    const double *y, *schi, *c0, *bq, *nu;   // nu: [nrhs][3][M] of this step
+    double *lam;             // out [nrhs][3][M]
+    // gradient
+    const double *Bj;        // B_j [nrhs][3][M]
+    const double *inv_eps;
+    double *grad;            // [M], accumulated
 };
 
 struct CgScalars {
@@ -102,6 +126,11 @@ struct ProbeStepArg {
 void launch_mac(const MacArg &a, hipStream_t st);
 void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st);
 void launch_probes(const ProbeStepArg &a, hipStream_t st);
+void launch_grad_term(const EpiArg &e, const double *Jn, const double *Jn1, double *Bout, hipStream_t st);
+void launch_adj_source(const AdjArg &a, hipStream_t st);
+void launch_adj_epilogue(const EpiArg &e, hipStream_t st);
+void launch_adj_lambda(const AdjArg &a, hipStream_t st);
+void launch_grad_accum(const AdjArg &a, hipStream_t st);
 void launch_mac_near(const BlockMacArg &a, hipStream_t st);
 void launch_epilogue(const EpiArg &e, hipStream_t st);
 void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,

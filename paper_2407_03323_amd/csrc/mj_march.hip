@@ -793,4 +793,190 @@ void launch_probes(const ProbeStepArg &a, hipStream_t st)
     MJ_CHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------- adjoint
+// The march is the block lower-triangular Toeplitz system sum_k Z_k J_{n-k} = E_n
+// (eq:MatrixEquation, eq:MOTInversion); its transpose runs backward in time,
+//   Z_0^T lambda_j = g_j - sum_{k>=1} Z_k^T lambda_{j+k},  Z_k^T = diag(c_k) - K_k (*) (chi .),
+// since every K_k is a symmetric operator (K^ab(D) = K^ba(D) = K^ab(-D)).  With nu = chi lambda
+// the sum over k >= 1 is the same spectral history sum as the forward one, in reversed time.
+// For the objective Phi = sum_n sum_p |E^s_p(n)|^2 and dc_k/deps = -T(k dt)/eps^2,
+// dchi/deps = 1/eps^2, dE_n/deps = <E^i>/eps^2:
+//   dPhi/deps_m = sum_n lambda_n(m) . B_n(m) / eps_m^2,
+//   B_n = <E^i>(n) + sum_{k=0}^{ell} (T(k dt) J_{n-k} + K_k (*) J_{n-k}).
+
+// (K_0 (*) x)(m) on the plain (non-haloed) layout, with bounds tests
+__device__ inline void stencil_plain(const double *__restrict__ x, long M, int U, int V, int W, int u, int v, int w,
+                                     double out[3])
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const int su = u - dx, sv = v - dy, sw = w - dz;
+        if (su < 0 || su >= U || sv < 0 || sv >= V || sw < 0 || sw >= W) continue;
+        const long j = ((long)sw * V + sv) * U + su;
+        const double x0 = x[j], x1 = x[M + j], x2 = x[2 * M + j];
+        const double *k = &c_K0[o * 6];
+        a0 += k[0] * x0 + k[3] * x1 + k[4] * x2;
+        a1 += k[3] * x0 + k[1] * x1 + k[5] * x2;
+        a2 += k[4] * x0 + k[5] * x1 + k[2] * x2;
+    }
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+}
+
+// B_n for every voxel (forward steps of the gradient run).  Jn, Jn1: J_n and J_{n-1}
+// ([nrhs][3][M], Jn1 NULL at n = 1); e.S holds sum_{k>=1} K_k (*) J_{n-k} of this step.
+__global__ void __launch_bounds__(256) k_grad_term(EpiArg e, const double *__restrict__ Jn,
+                                                   const double *__restrict__ Jn1, double *__restrict__ Bout)
+{
+    const long M = e.M;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= M) return;
+    const int u = (int)(i % e.U), v = (int)((i / e.U) % e.V), w = (int)(i / ((long)e.U * e.V));
+    const WaveArg wa = e.waves[r];
+    const double avg = wave_average(wa, e, u, v, w, e.n * e.c_dt);
+    double k0[3];
+    stencil_plain(Jn + (long)r * 3 * M, M, e.U, e.V, e.W, u, v, w, k0);
+    for (int c = 0; c < 3; c++) {
+        const long o = ((long)r * 3 + c) * M + i;
+        double b = avg * wa.pol[c] + 0.5 * Jn[o] + k0[c];   // T(0) = T(dt) = 1/2, T(k dt) = 0 for k >= 2
+        if (Jn1) b += 0.5 * Jn1[o];
+        if (e.S) b += e.S[o];
+        Bout[o] = b;
+    }
+}
+
+// g_j(m) = dPhi/dJ_j(m) = 2 sum_p sum_{k=0}^{ell} K_k(r_p - r_m) E^s_p(j + k), E^s_p(n) = 0 for n > N
+__global__ void __launch_bounds__(256) k_adj_source(AdjArg a)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= a.M) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < a.np; p++) {
+        const int q = a.inv[(long)p * a.M + i];
+        if (q < 0) continue;
+        const int kmin = a.pair_kmin[q];
+        for (int wl = 0; wl < a.nw; wl++) {
+            const int jj = a.j + kmin + wl;
+            if (jj > a.N) break;
+            const double *K = a.table + ((long)q * a.nw + wl) * 6;
+            const double *E = a.Ehist + (((long)(jj - 1) * a.nrhs + r) * a.np + p) * 3;
+            acc[0] += K[0] * E[0] + K[3] * E[1] + K[4] * E[2];
+            acc[1] += K[3] * E[0] + K[1] * E[1] + K[5] * E[2];
+            acc[2] += K[4] * E[0] + K[5] * E[1] + K[2] * E[2];
+        }
+    }
+    for (int c = 0; c < 3; c++) a.G[((long)r * 3 + c) * a.M + i] = 2.0 * acc[c];
+}
+
+// b'_j = g_j - sum_{k=1}^{nloc} c_k lambda_{j+k} + sum_{k>=1} K_k (*) nu_{j+k}; the solve takes
+// A mu = sqrt(chi) b' (Z_0^T = D^-1 A D), started from the quartic extrapolation of mu = nu / sqrt(chi).
+// The ring slots count the reversed step n' = N + 1 - j, so "n' - k" is step j + k.
+__global__ void __launch_bounds__(256) k_adj_epilogue(EpiArg e)
+{
+    const long M = e.M;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= M) return;
+    const double sc = e.schi[i];
+    const int u = (int)(i % e.U), v = (int)((i / e.U) % e.V), z = (int)(i / ((long)e.U * e.V));
+    const double c1 = 0.5 * e.inv_eps[i] + (e.nfir > 1 ? e.fir[1] : 0.0);
+    const long Mp = (long)(e.U + 2) * (e.V + 2) * (e.W + 2);
+    const long ip = ((long)(z + 1) * (e.V + 2) + (v + 1)) * (e.U + 2) + (u + 1);
+    for (int c = 0; c < 3; c++) {
+        const long o = ((long)r * 3 + c) * M + i;
+        double b = e.G[o] + (e.S ? e.S[o] : 0.0);
+        for (int k = 1; k <= e.nloc; k++) {
+            if (e.n - k < 1) break;
+            const double ck = (k == 1) ? c1 : (k < e.nfir ? e.fir[k] : 0.0);
+            if (ck == 0.0) continue;
+            b -= ck * e.Lring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
+        }
+        e.bq[o] = b;
+        double y0 = 0.0;
+        if (sc > 0.0) {
+            constexpr double cx[5] = {5.0, -10.0, 10.0, -5.0, 1.0};
+            double g = 0.0;
+#pragma unroll
+            for (int k = 1; k <= 5; k++)
+                if (e.n - k >= 1) g += cx[k - 1] * e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
+            y0 = g / sc;
+        }
+        e.rhs[o] = sc * b;
+        e.y[o] = y0;
+        e.uy[((long)r * 3 + c) * Mp + ip] = sc * y0;
+    }
+}
+
+// lambda_j = mu / sqrt(chi) where chi > 0; where chi = 0 the row of Z_0^T reads
+// c_0 lambda - K_0 (*) nu = b', so lambda = (b' + K_0 (*) nu) / c_0 there.
+__global__ void __launch_bounds__(256) k_adj_lambda(AdjArg a)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= a.M) return;
+    const double sc = a.schi[i];
+    const long M = a.M;
+    if (sc > 0.0) {
+        for (int c = 0; c < 3; c++) {
+            const long o = ((long)r * 3 + c) * M + i;
+            a.lam[o] = a.y[o] / sc;
+        }
+        return;
+    }
+    const int u = (int)(i % a.U), v = (int)((i / a.U) % a.V), w = (int)(i / ((long)a.U * a.V));
+    double kn[3];
+    stencil_plain(a.nu + (long)r * 3 * M, M, a.U, a.V, a.W, u, v, w, kn);
+    for (int c = 0; c < 3; c++) {
+        const long o = ((long)r * 3 + c) * M + i;
+        a.lam[o] = (a.bq[o] + kn[c]) / a.c0[i];
+    }
+}
+
+// grad(m) += sum_r lambda_j(m) . B_j(m) / eps_m^2
+__global__ void __launch_bounds__(256) k_grad_accum(AdjArg a)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= a.M) return;
+    double s = 0.0;
+    for (int r = 0; r < a.nrhs; r++)
+        for (int c = 0; c < 3; c++) {
+            const long o = ((long)r * 3 + c) * a.M + i;
+            s += a.lam[o] * a.Bj[o];
+        }
+    const double ie = a.inv_eps[i];
+    a.grad[i] += s * ie * ie;
+}
+
+static dim3 voxel_grid(long M, int nrhs) { return dim3((unsigned)((M + 255) / 256), nrhs); }
+
+void launch_grad_term(const EpiArg &e, const double *Jn, const double *Jn1, double *Bout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grad_term, voxel_grid(e.M, e.nrhs), dim3(256), 0, st, e, Jn, Jn1, Bout);
+    MJ_CHECK(hipGetLastError());
+}
+void launch_adj_source(const AdjArg &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_source, voxel_grid(a.M, a.nrhs), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+}
+void launch_adj_epilogue(const EpiArg &e, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_epilogue, voxel_grid(e.M, e.nrhs), dim3(256), 0, st, e);
+    MJ_CHECK(hipGetLastError());
+}
+void launch_adj_lambda(const AdjArg &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_lambda, voxel_grid(a.M, a.nrhs), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+}
+void launch_grad_accum(const AdjArg &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grad_accum, dim3((unsigned)((a.M + 255) / 256)), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+}
+
 }  // namespace mj

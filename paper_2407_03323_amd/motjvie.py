@@ -68,9 +68,11 @@ def load_library(path: str = LIB_PATH):
     L.mj_set_probes.argtypes = [vp, ctypes.c_int32, dp]
     L.mj_march.argtypes = [vp, ctypes.c_int32, vp, vp]
     L.mj_probe_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, ip, dp]
+    L.mj_set_eps.argtypes = [vp, dp]
+    L.mj_adjoint_gradient.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, vp, vp]
     for f in ("mj_create", "mj_info", "mj_set_plane_waves", "mj_run", "mj_reset", "mj_history_sum",
               "mj_kernel_values", "mj_stats", "mj_fft_roundtrip", "mj_set_probes", "mj_march",
-              "mj_probe_kernel_values"):
+              "mj_probe_kernel_values", "mj_set_eps", "mj_adjoint_gradient"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -211,12 +213,27 @@ class Solver:
                                                offs.ctypes.data_as(ip), _dptr(out)))
         return out
 
+    def set_eps(self, eps):
+        """New eps_r [W][V][U] for the same grid (kernels kept); at n = 0."""
+        e = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(self.W, self.V, self.U))
+        self._keep = (e,) + tuple(self._keep[1:])
+        self._check(self._lib.mj_set_eps(self._h, _dptr(e)))
+
+    def adjoint_gradient(self, n_steps: int, grad_out, ckpt_every: int = 0, probes_out=None) -> float:
+        """Phi = sum |E^s|^2 over n_steps and the probes; grad_out (CUDA tensor [W][V][U])
+        receives dPhi/deps_r.  Returns Phi."""
+        assert grad_out.numel() == self.M
+        phi = ctypes.c_double()
+        self._check(self._lib.mj_adjoint_gradient(self._h, int(n_steps), int(ckpt_every), ctypes.byref(phi),
+                                                  _tptr(grad_out, "grad_out"), _tptr(probes_out, "probes_out")))
+        return phi.value
+
     def stats(self) -> dict:
-        out = np.zeros(14)
-        self._check(self._lib.mj_stats(self._h, _dptr(out), 14))
+        out = np.zeros(17)
+        self._check(self._lib.mj_stats(self._h, _dptr(out), 17))
         keys = ["fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms", "z0_ms", "step_ms", "cg_iters",
                 "cg_res_max", "steps", "cg_iters_max", "far_launch_ms", "far_launches", "near_launch_ms",
-                "probe_ms"]
+                "probe_ms", "adjoint_forward_ms", "adjoint_backward_ms", "adjoint_segments"]
         return dict(zip(keys, out.tolist()))
 
     def fft_roundtrip(self, x, X=None, y=None):
@@ -230,3 +247,44 @@ def solver_for(problem, **kw) -> Solver:
     if problem.waves:
         s.set_plane_waves(problem.waves)
     return s
+
+
+class ProbeObjective:
+    """Phi(eps_r) = sum_n sum_p |E^s_p(n)|^2 as a torch.autograd.Function: forward runs the
+    march and the transposed march (mj_adjoint_gradient) on one Solver whose probes and
+    plane waves are set; backward returns grad_output * dPhi/deps_r.  The kernels stay, only
+    eps changes between calls (mj_set_eps)."""
+
+    def __init__(self, solver: Solver, n_steps: int, ckpt_every: int = 0):
+        self.solver = solver
+        self.n_steps = int(n_steps)
+        self.ckpt_every = int(ckpt_every)
+        self._fn = None
+
+    def function(self):
+        import torch
+        outer = self
+
+        class _Phi(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, eps):
+                s = outer.solver
+                s.reset()
+                s.set_eps(eps.detach().double().cpu().numpy())
+                grad = torch.zeros((s.W, s.V, s.U), dtype=torch.float64, device="cuda")
+                phi = s.adjoint_gradient(outer.n_steps, grad, outer.ckpt_every)
+                ctx.save_for_backward(grad.to(eps.device, eps.dtype))
+                return torch.tensor(phi, dtype=eps.dtype, device=eps.device)
+
+            @staticmethod
+            def backward(ctx, g):
+                (grad,) = ctx.saved_tensors
+                return g * grad
+
+        return _Phi
+
+    def __call__(self, eps):
+        if self._fn is None:
+            self._fn = self.function()
+        return self._fn.apply(eps)
+

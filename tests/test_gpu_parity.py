@@ -266,7 +266,7 @@ def test_probes_match_oracle(torch_cuda):
     got = Pt.cpu().numpy()[:, 0]
     err = _rel(got, ref)
     say("  pairs", info["probe_pairs"], "window", info["probe_window"], "rel L2", err)
-    assert info["probe_pairs"] == len(probes) * len(src)
+    assert info["probe_pairs"] == len(probes) * U * V * W     # every voxel, all within reach
     assert err <= 1e-8
     s.close()
 
@@ -305,4 +305,105 @@ def test_probe_kernels_sampled_C2(torch_cuda):
         worst = max(worst, np.abs(got[i] - ref).max() / scale)
     say("  worst rel", worst)
     assert worst <= 1e-11
+    s.close()
+
+
+# ----------------------------------------------------------------------------- adjoint
+def _adjoint_case():
+    U, V, W, n = 5, 4, 3, 40
+    eps = wl.random_eps(U, V, W, 21, 2.0, 9.0)
+    eps[0, 0, 0] = 1.0                                   # a voxel outside the scatterer
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("adj", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1))
+    probes = wl.fibonacci_sphere(4, 5.0, (U / 2, V / 2, W / 2))
+    return prob, probes
+
+
+@pytest.fixture(scope="module")
+def adjoint_oracle():
+    from oracle import mot
+    prob, probes = _adjoint_case()
+    K = oracle_kernel_table(prob.U, prob.V, prob.W, mot.ell(prob.U, prob.V, prob.W))
+    phi, grad, E = mot.Oracle(prob, K=K).probe_objective_gradient(prob.n_steps, probes)
+    return prob, probes, phi, grad
+
+
+@pytest.mark.parametrize("tb,ckpt", [(1, 0), (1, 9), (8, 0), (8, 9), (16, 5)])
+def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt):
+    """Phi and dPhi/deps_r of every voxel (one with eps_r = 1) from the transposed march,
+    with and without checkpoint/recompute segments, against the oracle's direct adjoint."""
+    torch = torch_cuda
+    prob, probes, phi_ref, grad_ref = adjoint_oracle
+    say("adjoint 5x4x3 time_block=%d ckpt_every=%d" % (tb, ckpt))
+    s = make_solver(prob, time_block=tb)
+    s.set_probes(probes)
+    g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    phi = s.adjoint_gradient(prob.n_steps, g, ckpt)
+    torch.cuda.synchronize()
+    grad = g.cpu().numpy()
+    st = s.stats()
+    e_phi = abs(phi - phi_ref) / abs(phi_ref)
+    e_g = _rel(grad, grad_ref)
+    say("  phi rel", e_phi, "grad rel L2", e_g, "segments", st["adjoint_segments"])
+    assert e_phi <= 1e-10
+    assert e_g <= 1e-8
+    s.close()
+
+
+def test_adjoint_gradient_finite_differences(torch_cuda):
+    """Central differences (delta = 1e-6) of Phi from the GPU march at five voxels of a
+    reduced version of the design problem (a 24^3 block eps_r = 10 with an 8^3 design
+    region of eps_r in [1, 12], 8 probes on a sphere of radius 24 h, 160 steps)."""
+    torch = torch_cuda
+    U = 24
+    rng = np.random.default_rng(4)
+    eps = np.full((U, U, U), 10.0)
+    eps[8:16, 8:16, 8:16] = rng.uniform(1.0, 12.0, (8, 8, 8))
+    k, p = wl.XPOL_PLUS_Z
+    n = 160
+    prob = wl.Problem("c4-small", U, U, U, eps, [wl.gaussian_wave(U, U, U, k, p, 4.0)], n,
+                      fir=wl.binomial_highpass(17, 0.1))
+    probes = wl.fibonacci_sphere(8, 24.0, (U / 2, U / 2, U / 2))
+    say("adjoint FD 24^3")
+    s = make_solver(prob, time_block=8, cg_rtol=1e-14)
+    s.set_probes(probes)
+    g = torch.zeros((U, U, U), dtype=torch.float64, device="cuda")
+    phi0 = s.adjoint_gradient(n, g, 48)
+    grad = g.cpu().numpy()
+    design = np.argwhere(eps[8:16, 8:16, 8:16] >= 1.01) + 8
+    pick = design[rng.choice(len(design), 5, replace=False)]
+    Pt = torch.zeros((n, 1, len(probes), 3), dtype=torch.float64, device="cuda")
+    worst = 0.0
+    for (w, v, u) in pick:
+        vals = []
+        for sgn in (1.0, -1.0):
+            e2 = eps.copy()
+            e2[w, v, u] += sgn * 1e-6
+            s.reset()
+            s.set_eps(e2)
+            s.run(n, None, Pt)
+            torch.cuda.synchronize()
+            vals.append(float((Pt.cpu().numpy() ** 2).sum()))
+        fd = (vals[0] - vals[1]) / 2e-6
+        err = abs(fd - grad[w, v, u]) / np.abs(grad).max()
+        say("  voxel", (u, v, w), "fd", fd, "adjoint", grad[w, v, u], "err", err)
+        worst = max(worst, err)
+    assert worst <= 1e-5
+    s.close()
+
+
+def test_probe_objective_autograd(torch_cuda, adjoint_oracle):
+    """torch.autograd through ProbeObjective returns the oracle's gradient."""
+    torch = torch_cuda
+    from paper_2407_03323_amd import ProbeObjective
+    prob, probes, phi_ref, grad_ref = adjoint_oracle
+    s = make_solver(prob, time_block=8)
+    s.set_probes(probes)
+    obj = ProbeObjective(s, prob.n_steps, ckpt_every=16)
+    eps = torch.tensor(prob.eps, dtype=torch.float64, requires_grad=True)
+    phi = obj(eps)
+    (gr,) = torch.autograd.grad(3.0 * phi, eps)
+    assert abs(phi.item() - phi_ref) <= 1e-10 * abs(phi_ref)
+    assert _rel(gr.numpy(), 3.0 * grad_ref) <= 1e-8
     s.close()
