@@ -35,8 +35,12 @@ WORKLOADS = {
 
 
 def mac_source_digest() -> str:
-    with open(os.path.join(ROOT, "paper_2407_03323_amd", "csrc", "mj_march.hip"), "rb") as fh:
-        return hashlib.sha1(fh.read()).hexdigest()[:12]
+    """Digest of the far-part MAC kernel's source (from its header comment to the next kernel)."""
+    with open(os.path.join(ROOT, "paper_2407_03323_amd", "csrc", "mj_march.hip")) as fh:
+        src = fh.read()
+    a = src.index("// Far part.")
+    b = src.index("// near part of step", a)
+    return hashlib.sha1(src[a:b].encode()).hexdigest()[:12]
 
 
 def mac_traffic(workload: str):
@@ -82,6 +86,73 @@ def cpu_baseline(prob, ell: int, target_seconds: float = 20.0):
                       "(%.1f s), scaled to %d targets and %d lags" % (nt2, M, nlag, ell, dt2, M, ell)}
 
 
+def timed_march(solver, steps: int, warmup: int, probes_out=None):
+    """Wall time of `steps` march steps after `warmup` untimed ones (device synchronised)."""
+    import torch
+    if warmup:
+        solver.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.run(steps, None, probes_out)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def batched_ratio(steps: int = 16):
+    """C3: 16 plane waves marched together against one, on the 64^3 heterogeneous grid.
+    Throughput counted per right-hand side (voxel.RHS.steps/s) of the batched march over
+    the single-RHS march of the same grid."""
+    import torch
+    import workloads as wl
+    from paper_2407_03323_amd import motjvie
+    prob = wl.config("C3")
+    out = {"workload": "C3: 64^3 eps_r box-smoothed U[2,20], 16 plane waves sigma=6 dt, 17-tap FIR",
+           "steps": steps}
+    for nr in (16, 1):
+        s = motjvie.Solver(prob.U, prob.V, prob.W, prob.eps, fir=prob.fir, n_rhs=nr)
+        s.set_plane_waves(prob.waves[:nr])
+        ell = s.ell
+        dt = timed_march(s, steps, ell + 8)
+        out["rhs%d_voxel_rhs_steps_per_s" % nr] = prob.M * steps * nr / dt
+        out["rhs%d_ms_per_step" % nr] = 1e3 * dt / steps
+        s.close()
+        del s
+        torch.cuda.synchronize()
+    out["per_rhs_speedup"] = out["rhs16_voxel_rhs_steps_per_s"] / out["rhs1_voxel_rhs_steps_per_s"]
+    return out
+
+
+def adjoint_ratio(n_steps: int = 800, ckpt: int = 50):
+    """C4: gradient of sum |E^s|^2 over 32 probes (radius 48 h) with respect to eps_r of all
+    48^3 voxels by the checkpointed transposed march, against the plain forward march of the
+    same steps with the probes."""
+    import torch
+    import workloads as wl
+    from paper_2407_03323_amd import motjvie
+    prob = wl.config("C4")
+    s = motjvie.solver_for(prob)
+    t0 = time.perf_counter()
+    s.set_probes(prob.probes)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    P = torch.zeros((n_steps, 1, len(prob.probes), 3), dtype=torch.float64, device="cuda")
+    t_fwd = timed_march(s, n_steps, 0, P)
+    s.reset()
+    g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.adjoint_gradient(n_steps, g, ckpt)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    return {"workload": "C4: 48^3 eps_r=10 with a 16^3 design region U[1,12], 32 probes r=48h, 17-tap FIR",
+            "steps": n_steps, "ckpt_every": ckpt, "segments": int(st["adjoint_segments"]),
+            "forward_s": t_fwd, "gradient_s": t_adj, "gradient_over_forward": t_adj / t_fwd,
+            "gradient_forward_pass_ms": st["adjoint_forward_ms"],
+            "gradient_backward_pass_ms": st["adjoint_backward_ms"], "probe_table_s": t_table}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=-1, help="default: ell + 8")
     ap.add_argument("--workload", default="C5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched (C3) and adjoint (C4) ratios")
     ap.add_argument("--time-block", type=int, default=0, help="steps per time block (0 = library default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
@@ -190,6 +262,12 @@ def main():
     solver.close()
     del solver
     torch.cuda.synchronize()
+    if not args.no_extras:
+        line["batched"] = batched_ratio()
+        print("batched: %.3g per-RHS speedup" % line["batched"]["per_rhs_speedup"], file=sys.stderr, flush=True)
+        line["adjoint"] = adjoint_ratio()
+        print("adjoint: gradient/forward %.2f" % line["adjoint"]["gradient_over_forward"], file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, ell)
     print(json.dumps(line), flush=True)

@@ -556,6 +556,7 @@ void mj_solver::step(const StepIO &io)
             pa.nrhs = nrhs;
             pa.n = n;
             pa.M = M;
+            pa.npairs = npairs;
             pa.Jring = Jr;
             pa.rdepth = rdepth;
             pa.part = ppart;
@@ -581,6 +582,7 @@ mj::AdjArg mj_solver::adj_arg() const
     a.inv = pinv;
     a.np = np;
     a.nw = nw;
+    a.npairs = npairs;
     a.schi = schi;
     a.c0 = c0;
     a.inv_eps = inv_eps;

@@ -445,7 +445,8 @@ struct OffgridArg {
     int U, V;
     int nw;                   // lags per pair
     int kmax;                 // lags above kmax are stored as zero
-    double *out;              // [npairs][nw][6]
+    long npairs;
+    double *out;              // [nw][npairs][6]: for one window slot, consecutive pairs are adjacent
 };
 
 // One 64-lane block per (test voxel, source voxel) pair: shell moments by the same face
@@ -492,7 +493,7 @@ __global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, Ge
             kernel_from_shells(mom, a_lo, nsh, k, K);
             finish_offgrid(D, sg, K);
         }
-        double *o = oa.out + (i * oa.nw + wl) * 6;
+        double *o = oa.out + ((long)wl * oa.npairs + i) * 6;
         for (int c = 0; c < 6; c++) o[c] = K[c];
     }
 }
@@ -590,6 +591,7 @@ void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const i
     oa.V = V;
     oa.nw = nw;
     oa.kmax = kmax;
+    oa.npairs = npairs;
     oa.out = out_dev;
     hipLaunchKernelGGL(k_offgrid_table, dim3((unsigned)npairs), dim3(kGenThreads), 0, st, oa, ga);
     MJ_CHECK(hipGetLastError());

@@ -86,7 +86,7 @@ void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *
 // K_k(D) for a list of (k, D): out[n][6]
 // Kernels seen from test voxels centred at arbitrary points pos[p] (units of h from the grid
 // corner) for source voxels pair_vox (linear index), lags pair_kmin .. pair_kmin + nw - 1
-// (zero above kmax): out[pair][nw][6].
+// (zero above kmax): out[nw][pair][6].
 void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const int *pair_vox_dev,
                        const int *pair_kmin_dev, long npairs, int U, int V, int nw, int kmax, int nquad,
                        double *out_dev, hipStream_t st);

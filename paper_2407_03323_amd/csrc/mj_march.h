@@ -64,11 +64,12 @@ struct AdjArg {
     long M;
     int U, V, W, nrhs;
     // adjoint source from the stored probe field
-    const double *table;     // probe kernel table [npairs][nw][6]
+    const double *table;     // probe kernel table [nw][npairs][6]
     const int *pair_kmin;    // [npairs]
     const int *inv;          // [np][M] pair of (probe, voxel), -1 if none
     const double *Ehist;     // [N][nrhs][np][3]
     int np, nw, N, j;        // j: forward step of this adjoint step
+    long npairs;
     double *G;               // out [nrhs][3][M]
     // lambda from the solve
     const double *y, *schi, *c0, *bq, *nu;   // nu: [nrhs][3][M] of this step
@@ -111,12 +112,12 @@ struct CgArg {
 // k - kmin form one contiguous run: row (p, k) = pairs [row_start[p][max(0, k-nw+1)],
 // row_start[p][k+1]).
 struct ProbeStepArg {
-    const double *table;     // [npairs][nw][6]
+    const double *table;     // [nw][npairs][6]
     const int *pair_vox;     // [npairs]
     const int *pair_kmin;    // [npairs]
     const int *row_start;    // [np][ell + 2]
     int np, ell, nw, nrhs, n;
-    long M;
+    long M, npairs;
     const double *Jring;     // [rdepth][nrhs][3][M]
     int rdepth;
     double *part;            // [nrhs][np][ell + 1][3]

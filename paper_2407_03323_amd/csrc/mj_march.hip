@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(256) k_probe_rows(ProbeStepArg a)
         const double *J = a.Jring + ((long)(j % a.rdepth) * a.nrhs + r) * 3 * a.M;
         for (int q = lo + lane; q < hi; q += 64) {
             const int wl = k - a.pair_kmin[q];
-            const double *K = a.table + ((long)q * a.nw + wl) * 6;
+            const double *K = a.table + ((long)wl * a.npairs + q) * 6;
             const long m = a.pair_vox[q];
             const double jx = J[m], jy = J[a.M + m], jz = J[2 * a.M + m];
             acc[0] += K[0] * jx + K[3] * jy + K[4] * jz;
@@ -862,7 +862,7 @@ __global__ void __launch_bounds__(256) k_adj_source(AdjArg a)
         for (int wl = 0; wl < a.nw; wl++) {
             const int jj = a.j + kmin + wl;
             if (jj > a.N) break;
-            const double *K = a.table + ((long)q * a.nw + wl) * 6;
+            const double *K = a.table + ((long)wl * a.npairs + q) * 6;
             const double *E = a.Ehist + (((long)(jj - 1) * a.nrhs + r) * a.np + p) * 3;
             acc[0] += K[0] * E[0] + K[3] * E[1] + K[4] * E[2];
             acc[1] += K[3] * E[0] + K[1] * E[1] + K[5] * E[2];
