@@ -17,16 +17,17 @@ namespace {
 
 thread_local std::string g_err;
 
-__global__ void k_extract_octant(const double2 *__restrict__ X, int Hx, int Ny, int Nz, double scale,
+__global__ void k_extract_octant(const double2 *__restrict__ X, int Hx, int Hp, int Ny, int Nz, double scale,
                                  double *__restrict__ out)
 {
     const int Nyo = Ny / 2 + 1, Nzo = Nz / 2 + 1;
-    const long n = (long)Hx * Nyo * Nzo;
+    const long n = (long)Hp * Nyo * Nzo;
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int kx = (int)(t % Hx), qy = (int)((t / Hx) % Nyo), qz = (int)(t / ((long)Hx * Nyo));
-    const long plane = (long)Nz * Ny * Hx;
-    for (int c = 0; c < 6; c++) out[6 * t + c] = scale * X[c * plane + ((long)qz * Ny + qy) * Hx + kx].x;
+    const int kx = (int)(t % Hp), qy = (int)((t / Hp) % Nyo), qz = (int)(t / ((long)Hp * Nyo));
+    const long plane = (long)Nz * Ny * Hp;
+    for (int c = 0; c < 6; c++)
+        out[6 * t + c] = kx < Hx ? scale * X[c * plane + ((long)qz * Ny + qy) * Hp + kx].x : 0.0;
 }
 
 struct Events {
@@ -53,7 +54,7 @@ struct mj_solver {
     long M = 0;
     double h = 1.0, c_dt = 1.0;
     int nrhs = 1, ell = 0;
-    int Nx = 0, Ny = 0, Nz = 0, Hx = 0;
+    int Nx = 0, Ny = 0, Nz = 0, Hx = 0, Hp = 0;
     std::vector<double> fir;
     double cg_rtol = 1e-12;
     int cg_maxit = 200;
@@ -134,8 +135,8 @@ struct mj_solver {
         ptr = nullptr;
     }
 
-    long spec_plane() const { return (long)Nz * Ny * Hx; }
-    long koct() const { return (long)Hx * (Ny / 2 + 1) * (Nz / 2 + 1); }
+    long spec_plane() const { return (long)Nz * Ny * Hp; }
+    long koct() const { return (long)Hp * (Ny / 2 + 1) * (Nz / 2 + 1); }
     int slotS(int j) const { return j % ell; }
     int slotR(int j) const { return j % rdepth; }
 
@@ -200,6 +201,7 @@ void mj_solver::create(const mj_config &c)
     Ny = mj::fft_pick_size(2 * V - 1);
     Nz = mj::fft_pick_size(2 * W - 1);
     Hx = Nx / 2 + 1;
+    Hp = mj::spectrum_pitch(Hx);
     B = c.time_block > 0 ? c.time_block : 8;
     if (B != 1 && B != 4 && B != 8 && B != 16 && B != 32)
         throw ArgError("time_block must be 0 (auto), 1, 4, 8, 16 or 32");
@@ -247,7 +249,7 @@ void mj_solver::create(const mj_config &c)
     waves_d = dalloc<mj::WaveArg>(nrhs, "waves");
     MJ_CHECK(hipHostMalloc((void **)&cgstat_h, sizeof(mj::CgStatus) * nrhs, hipHostMallocDefault));
     mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz);
-    bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hx + (size_t)3 * nrhs * W * Ny * Hx);
+    bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hp + (size_t)3 * nrhs * W * Ny * Hp);
     n = 0;
     MJ_CHECK(hipStreamSynchronize(st));
 }
@@ -330,12 +332,12 @@ void mj_solver::build_spectra()
     try {
         mj::fft3d_init(kf, Nx, Ny, Nz, 6, Nx, Ny, Nz);
         if (hipMalloc(&grid, 6 * ng * sizeof(double)) != hipSuccess) throw MemError("kernel grid");
-        if (hipMalloc(&X, 6 * (size_t)Nz * Ny * Hx * sizeof(double2)) != hipSuccess) throw MemError("kernel spectrum");
+        if (hipMalloc(&X, 6 * (size_t)Nz * Ny * Hp * sizeof(double2)) != hipSuccess) throw MemError("kernel spectrum");
         const double scale = 1.0 / ((double)Nx * Ny * Nz);
         for (int k = 1; k <= ell; k++) {
             mj::gen_kernel_grid(gen, k, Nx, Ny, Nz, grid, st);
             mj::fft3d_forward(kf, grid, X, 6, st);
-            hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((ko + 255) / 256)), dim3(256), 0, st, X, Hx, Ny, Nz,
+            hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((ko + 255) / 256)), dim3(256), 0, st, X, Hx, Hp, Ny, Nz,
                                scale, Khat + (size_t)(k - 1) * 6 * ko);
             MJ_CHECK(hipGetLastError());
         }
@@ -483,6 +485,7 @@ void mj_solver::step(const StepIO &io)
         a.ring_base = ring;
         a.Shat = Shat;
         a.Hx = Hx;
+        a.Hp = Hp;
         a.Ny = Ny;
         a.Nz = Nz;
         a.nk = std::min(ell, n - 1);
@@ -499,6 +502,7 @@ void mj_solver::step(const StepIO &io)
         a.ring_base = ring;
         a.far = farbuf;
         a.Hx = Hx;
+        a.Hp = Hp;
         a.Ny = Ny;
         a.Nz = Nz;
         a.nk = ell;
@@ -658,6 +662,7 @@ void mj_solver::history_sum(const double *Jh, int depth, double *P)
         a.ring_base = ring;
         a.Shat = Shat;
         a.Hx = Hx;
+        a.Hp = Hp;
         a.Ny = Ny;
         a.Nz = Nz;
         a.nk = ell;
@@ -672,6 +677,7 @@ void mj_solver::history_sum(const double *Jh, int depth, double *P)
         a.ring_base = ring;
         a.far = farbuf;
         a.Hx = Hx;
+        a.Hp = Hp;
         a.Ny = Ny;
         a.Nz = Nz;
         a.nk = ell;
@@ -1202,8 +1208,12 @@ int mj_fft_roundtrip(mj_solver *s, const double *x, double *X, double *yout)
 {
     if (!s || !x) return MJ_EINVAL;
     return guarded(s, [&] {
-        double2 *Xd = X ? (double2 *)X : s->Shat;
+        // the spectrum is held with row pitch Hp; the caller's X has rows of Hx
+        double2 *Xd = s->Shat;
         mj::fft3d_forward(s->fft, x, Xd, 3, s->st);
+        if (X)
+            MJ_CHECK(hipMemcpy2DAsync(X, sizeof(double2) * s->Hx, Xd, sizeof(double2) * s->Hp, sizeof(double2) * s->Hx,
+                                      (size_t)3 * s->Nz * s->Ny, hipMemcpyDeviceToDevice, s->st));
         if (yout) mj::fft3d_inverse(s->fft, Xd, yout, 3, s->st);
         MJ_CHECK(hipStreamSynchronize(s->st));
     });

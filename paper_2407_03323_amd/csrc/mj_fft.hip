@@ -200,9 +200,10 @@ __device__ inline void gather_tile(int total, Get get, Put put)
 
 // ---------------------------------------------------------------------------- x pass
 // Forward: rows of U reals (row r at x + r*U), nrows rows; two rows per pencil.
-// Output: rows of Hx complex at X + r*Hx.
+// Output: rows of Hx complex at X + r*Hp.
 __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict__ x, double2 *__restrict__ X,
-                                                        int nrows, int U, int Hx, PlanArg pl, const double2 *tw, int P)
+                                                        int nrows, int U, int Hx, int Hp, PlanArg pl, const double2 *tw,
+                                                        int P)
 {
     extern __shared__ double2 sm[];
     const int N = pl.N, ld = N + 1;
@@ -240,13 +241,14 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
         double2 o;
         if (rr & 1) o = make_double2(0.5 * (z1.y + z2.y), -0.5 * (z1.x - z2.x));
         else o = make_double2(0.5 * (z1.x + z2.x), 0.5 * (z1.y - z2.y));
-        X[(size_t)row * Hx + k] = o;
+        X[(size_t)row * Hp + k] = o;
     }
 }
 
-// Inverse: rows of Hx complex half-spectra -> rows of U reals (unnormalised).
+// Inverse: rows of Hx complex half-spectra (pitch Hp) -> rows of U reals (unnormalised).
 __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restrict__ X, double *__restrict__ y,
-                                                        int nrows, int U, int Hx, PlanArg pl, const double2 *tw, int P)
+                                                        int nrows, int U, int Hx, int Hp, PlanArg pl, const double2 *tw,
+                                                        int P)
 {
     extern __shared__ double2 sm[];
     const int N = pl.N, ld = N + 1;
@@ -262,8 +264,8 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
             const int ra = row0 + 2 * p, rb = ra + 1;
             const int k = n <= N / 2 ? n : N - n;
             double2 xa = make_double2(0, 0), xb = make_double2(0, 0);
-            if (ra < nrows) xa = X[(size_t)ra * Hx + k];
-            if (rb < nrows) xb = X[(size_t)rb * Hx + k];
+            if (ra < nrows) xa = X[(size_t)ra * Hp + k];
+            if (rb < nrows) xb = X[(size_t)rb * Hp + k];
             return make_double4(xa.x, xa.y, xb.x, xb.y);
         },
         [&](int i, double4 v) {
@@ -401,11 +403,12 @@ void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz
     f.U = U; f.V = V; f.W = W;
     f.Nx = Nx; f.Ny = Ny; f.Nz = Nz;
     f.Hx = Nx / 2 + 1;
+    f.Hp = spectrum_pitch(f.Hx);
     f.ncomp = ncomp;
     fft_plan_init(f.px, Nx);
     fft_plan_init(f.py, Ny);
     fft_plan_init(f.pz, Nz);
-    size_t na = (size_t)ncomp * W * V * f.Hx, nb = (size_t)ncomp * W * Ny * f.Hx;
+    size_t na = (size_t)ncomp * W * V * f.Hp, nb = (size_t)ncomp * W * Ny * f.Hp;
     if (hipMalloc(&f.bufA, sizeof(double2) * na) != hipSuccess) throw MemError("FFT scratch A");
     if (hipMalloc(&f.bufB, sizeof(double2) * nb) != hipSuccess) throw MemError("FFT scratch B");
 }
@@ -433,13 +436,13 @@ static void launch_strided(const double2 *in, double2 *out, const StridedArg &g,
 
 void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t st)
 {
-    const int U = f.U, V = f.V, W = f.W, Hx = f.Hx, Ny = f.Ny, Nz = f.Nz;
+    const int U = f.U, V = f.V, W = f.W, Hx = f.Hx, Hp = f.Hp, Ny = f.Ny, Nz = f.Nz;
     // x pass: rows (c, w, v)
     {
         int nrows = ncomp * W * V;
         int P = pencils_per_block(f.Nx);
         dim3 grid((nrows + 2 * P - 1) / (2 * P));
-        hipLaunchKernelGGL(k_fft_x_fwd, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, x, f.bufA, nrows, U, Hx,
+        hipLaunchKernelGGL(k_fft_x_fwd, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, x, f.bufA, nrows, U, Hx, Hp,
                            plan_arg(f.px), f.px.tw, P);
         MJ_CHECK(hipGetLastError());
     }
@@ -447,8 +450,8 @@ void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t
     {
         StridedArg g{};
         g.nq = W; g.Hx = Hx;
-        g.cs_in = (long)W * V * Hx; g.qs_in = (long)V * Hx; g.es_in = Hx;
-        g.cs_out = (long)W * Ny * Hx; g.qs_out = (long)Ny * Hx; g.es_out = Hx;
+        g.cs_in = (long)W * V * Hp; g.qs_in = (long)V * Hp; g.es_in = Hp;
+        g.cs_out = (long)W * Ny * Hp; g.qs_out = (long)Ny * Hp; g.es_out = Hp;
         g.n_in = V; g.n_out = Ny;
         launch_strided(f.bufA, f.bufB, g, ncomp, f.py, false, st);
     }
@@ -456,8 +459,8 @@ void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t
     {
         StridedArg g{};
         g.nq = Ny; g.Hx = Hx;
-        g.cs_in = (long)W * Ny * Hx; g.qs_in = Hx; g.es_in = (long)Ny * Hx;
-        g.cs_out = (long)Nz * Ny * Hx; g.qs_out = Hx; g.es_out = (long)Ny * Hx;
+        g.cs_in = (long)W * Ny * Hp; g.qs_in = Hp; g.es_in = (long)Ny * Hp;
+        g.cs_out = (long)Nz * Ny * Hp; g.qs_out = Hp; g.es_out = (long)Ny * Hp;
         g.n_in = W; g.n_out = Nz;
         launch_strided(f.bufB, X, g, ncomp, f.pz, false, st);
     }
@@ -465,13 +468,13 @@ void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t
 
 void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t st)
 {
-    const int U = f.U, V = f.V, W = f.W, Hx = f.Hx, Ny = f.Ny, Nz = f.Nz;
+    const int U = f.U, V = f.V, W = f.W, Hx = f.Hx, Hp = f.Hp, Ny = f.Ny, Nz = f.Nz;
     // z pass: X[c][kz][ky][kx] -> B[c][w][ky][kx], w < W
     {
         StridedArg g{};
         g.nq = Ny; g.Hx = Hx;
-        g.cs_in = (long)Nz * Ny * Hx; g.qs_in = Hx; g.es_in = (long)Ny * Hx;
-        g.cs_out = (long)W * Ny * Hx; g.qs_out = Hx; g.es_out = (long)Ny * Hx;
+        g.cs_in = (long)Nz * Ny * Hp; g.qs_in = Hp; g.es_in = (long)Ny * Hp;
+        g.cs_out = (long)W * Ny * Hp; g.qs_out = Hp; g.es_out = (long)Ny * Hp;
         g.n_in = Nz; g.n_out = W;
         launch_strided(X, f.bufB, g, ncomp, f.pz, true, st);
     }
@@ -479,8 +482,8 @@ void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t
     {
         StridedArg g{};
         g.nq = W; g.Hx = Hx;
-        g.cs_in = (long)W * Ny * Hx; g.qs_in = (long)Ny * Hx; g.es_in = Hx;
-        g.cs_out = (long)W * V * Hx; g.qs_out = (long)V * Hx; g.es_out = Hx;
+        g.cs_in = (long)W * Ny * Hp; g.qs_in = (long)Ny * Hp; g.es_in = Hp;
+        g.cs_out = (long)W * V * Hp; g.qs_out = (long)V * Hp; g.es_out = Hp;
         g.n_in = Ny; g.n_out = V;
         launch_strided(f.bufB, f.bufA, g, ncomp, f.py, true, st);
     }
@@ -489,7 +492,7 @@ void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t
         int nrows = ncomp * W * V;
         int P = pencils_per_block(f.Nx);
         dim3 grid((nrows + 2 * P - 1) / (2 * P));
-        hipLaunchKernelGGL(k_fft_x_inv, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, f.bufA, y, nrows, U, Hx,
+        hipLaunchKernelGGL(k_fft_x_inv, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, f.bufA, y, nrows, U, Hx, Hp,
                            plan_arg(f.px), f.px.tw, P);
         MJ_CHECK(hipGetLastError());
     }

@@ -8,10 +8,10 @@ namespace mj {
 constexpr int kMaxLocal = 64;   // largest history depth kept in real space
 
 struct MacArg {
-    const double *Khat;      // [nk][Nz/2+1][Ny/2+1][Hx][6] real, lags 1..nk
-    const double2 *ring_base;// [ring][nrhs][3][Nz][Ny][Hx]
-    double2 *Shat;           // [nrhs][3][Nz][Ny][Hx]
-    int Hx, Ny, Nz;
+    const double *Khat;      // [nk][Nz/2+1][Ny/2+1][Hp][6] real, lags 1..nk
+    const double2 *ring_base;// [ring][nrhs][3][Nz][Ny][Hp]
+    double2 *Shat;           // [nrhs][3][Nz][Ny][Hp]
+    int Hx, Hp, Ny, Nz;      // Hx = Nx/2 + 1 frequencies in rows of pitch Hp
     int nk;                  // number of lags summed (1..nk)
     int ring;                // ring slots
     int slot_nm1;            // slot of Jhat_{n-1}
@@ -19,10 +19,10 @@ struct MacArg {
 };
 
 struct BlockMacArg {
-    const double *Khat;        // [ell][Nz/2+1][Ny/2+1][Hx][6]
-    const double2 *ring_base;  // [ring][nrhs][3][Nz][Ny][Hx]
-    double2 *far;              // [TB][nrhs][3][Nz][Ny][Hx]
-    int Hx, Ny, Nz;
+    const double *Khat;        // [ell][Nz/2+1][Ny/2+1][Hp][6]
+    const double2 *ring_base;  // [ring][nrhs][3][Nz][Ny][Hp]
+    double2 *far;              // [TB][nrhs][3][Nz][Ny][Hp]
+    int Hx, Hp, Ny, Nz;        // Hx = Nx/2 + 1 frequencies in rows of pitch Hp
     int nk;                    // ell (far: lags 1..nk)
     int ring;
     int nb;                    // first step of the block

@@ -18,25 +18,26 @@ namespace mj {
 template <int G>
 __global__ void __launch_bounds__(256) k_mac(MacArg a)
 {
-    const int Hx = a.Hx, Nyo = a.Ny / 2 + 1, Nzo = a.Nz / 2 + 1;
-    const long npt = (long)Hx * Nyo * Nzo;
+    const int Hp = a.Hp, Nyo = a.Ny / 2 + 1, Nzo = a.Nz / 2 + 1;
+    const long npt = (long)Hp * Nyo * Nzo;
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= npt) return;
-    const int kx = (int)(t % Hx);
-    const int qy = (int)((t / Hx) % Nyo);
-    const int qz = (int)(t / ((long)Hx * Nyo));
+    const int kx = (int)(t % Hp);
+    if (kx >= a.Hx) return;   // row padding
+    const int qy = (int)((t / Hp) % Nyo);
+    const int qz = (int)(t / ((long)Hp * Nyo));
     const int r0 = blockIdx.y * G;
     // mirror points
     int ys[2] = {qy, a.Ny - qy}, zs[2] = {qz, a.Nz - qz};
     const int ny_m = (qy == 0 || 2 * qy == a.Ny) ? 1 : 2;
     const int nz_m = (qz == 0 || 2 * qz == a.Nz) ? 1 : 2;
-    const long plane = (long)a.Nz * a.Ny * Hx;   // one component of one spectrum
+    const long plane = (long)a.Nz * a.Ny * Hp;   // one component of one spectrum
     long off[4];
     double sy_[4], sz_[4];
     int np = 0;
     for (int iz = 0; iz < nz_m; iz++)
         for (int iy = 0; iy < ny_m; iy++) {
-            off[np] = ((long)zs[iz] * a.Ny + ys[iy]) * Hx + kx;
+            off[np] = ((long)zs[iz] * a.Ny + ys[iy]) * Hp + kx;
             sy_[np] = iy ? -1.0 : 1.0;
             sz_[np] = iz ? -1.0 : 1.0;
             np++;
@@ -49,7 +50,7 @@ __global__ void __launch_bounds__(256) k_mac(MacArg a)
 #pragma unroll
             for (int c = 0; c < 3; c++) acc[g][p][c] = make_double2(0.0, 0.0);
 
-    const long koct = (long)Hx * Nyo * Nzo;
+    const long koct = (long)Hp * Nyo * Nzo;
     const double *Kp = a.Khat + 6 * t;
     for (int k = 1; k <= a.nk; k++) {
         const double *Kk = Kp + (long)(k - 1) * 6 * koct;
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(256) k_mac(MacArg a)
 
 void launch_mac(const MacArg &a, hipStream_t st)
 {
-    const long npt = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    const long npt = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     dim3 blk(256);
     if (a.nrhs == 1) {
         dim3 grd((unsigned)((npt + 255) / 256), 1);
@@ -120,26 +121,27 @@ void launch_mac(const MacArg &a, hipStream_t st)
 // of the 4 loads hit in cache.  Duplicate mirrors (ky = 0 or Ny/2, kz = 0 or Nz/2) idle.
 struct MirrorPoint {
     bool valid;
-    long off;      // offset in one spectrum component [Nz][Ny][Hx]
+    long off;      // offset in one spectrum component [Nz][Ny][Hp]
     long koff;     // octant point index (its Khat record starts at 6 koff)
     double sy, sz; // parity signs of the odd components
 };
 
-__device__ inline MirrorPoint mirror_point(int Hx, int Ny, int Nz)
+__device__ inline MirrorPoint mirror_point(int Hx, int Hp, int Ny, int Nz)
 {
     MirrorPoint mp;
     const int Nyo = Ny / 2 + 1, Nzo = Nz / 2 + 1;
-    const long nocts = (long)Hx * Nyo * Nzo;
+    const long nocts = (long)Hp * Nyo * Nzo;
     const long o = blockIdx.x * 64L + (threadIdx.x & 63);
     const int m = (threadIdx.x >> 6) & 3;
     mp.valid = o < nocts;
     if (!mp.valid) return mp;
-    const int kx = (int)(o % Hx), qy = (int)((o / Hx) % Nyo), qz = (int)(o / ((long)Hx * Nyo));
+    const int kx = (int)(o % Hp), qy = (int)((o / Hp) % Nyo), qz = (int)(o / ((long)Hp * Nyo));
     const int fy = m & 1, fz = m >> 1;
+    if (kx >= Hx) mp.valid = false;   // row padding
     if (fy && (qy == 0 || 2 * qy == Ny)) mp.valid = false;
     if (fz && (qz == 0 || 2 * qz == Nz)) mp.valid = false;
     const int ky = fy ? Ny - qy : qy, kz = fz ? Nz - qz : qz;
-    mp.off = ((long)kz * Ny + ky) * Hx + kx;
+    mp.off = ((long)kz * Ny + ky) * Hp + kx;
     mp.koff = o;
     mp.sy = fy ? -1.0 : 1.0;
     mp.sz = fz ? -1.0 : 1.0;
@@ -191,28 +193,29 @@ __device__ inline int ring_slot(int j, int ring)
 // written at lag k - tt.  A group's sources are those of group 0 TG lags earlier, so the
 // extra loads hit in cache; K_k is the same for every group.
 template <int TG, int G, int PD>
-__global__ void __launch_bounds__(256) k_mac_far(BlockMacArg a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mac_far(BlockMacArg a)
 {
     static_assert(64 % (2 * G) == 0, "lanes split evenly into groups");
     static_assert(TG % PD == 0, "the prefetch buffers rotate with the slot window");
     constexpr int kLanesPerGroup = 64 / G;
     constexpr int kPointsPerWave = kLanesPerGroup / 2;
     const int Nyo = a.Ny / 2 + 1, Nzo = a.Nz / 2 + 1;
-    const long nocts = (long)a.Hx * Nyo * Nzo;
+    const long nocts = (long)a.Hp * Nyo * Nzo;
     const int lane = threadIdx.x & 63;
     const int g = lane / kLanesPerGroup, li = lane % kLanesPerGroup;
     const long o = blockIdx.x * (long)kPointsPerWave + (li >> 1);
     const int part = li & 1;
     const int m = threadIdx.x >> 6;
     if (o >= nocts) return;
-    const int kx = (int)(o % a.Hx), qy = (int)((o / a.Hx) % Nyo), qz = (int)(o / ((long)a.Hx * Nyo));
+    const int kx = (int)(o % a.Hp), qy = (int)((o / a.Hp) % Nyo), qz = (int)(o / ((long)a.Hp * Nyo));
     const int fy = m & 1, fz = m >> 1;
+    if (kx >= a.Hx) return;   // row padding
     if ((fy && (qy == 0 || 2 * qy == a.Ny)) || (fz && (qz == 0 || 2 * qz == a.Nz))) return;
     const int ky = fy ? a.Ny - qy : qy, kz = fz ? a.Nz - qz : qz;
     const double sy = fy ? -1.0 : 1.0, sz = fz ? -1.0 : 1.0;
-    const long off2 = 2 * (((long)kz * a.Ny + ky) * a.Hx + kx) + part;   // in doubles
+    const long off2 = 2 * (((long)kz * a.Ny + ky) * a.Hp + kx) + part;   // in doubles
     const int r = blockIdx.y;
-    const long plane2 = 2L * a.Nz * a.Ny * a.Hx;                           // one component, in doubles
+    const long plane2 = 2L * a.Nz * a.Ny * a.Hp;                           // one component, in doubles
     const long koct = nocts;
     const int tg0 = g * TG;                                                // first target of the group
     constexpr int TB = TG * G;
@@ -320,11 +323,11 @@ __global__ void __launch_bounds__(256) k_mac_far(BlockMacArg a)
 // near part of step n = n_b + t, accumulated in place into F[t]
 __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 {
-    const MirrorPoint mp = mirror_point(a.Hx, a.Ny, a.Nz);
+    const MirrorPoint mp = mirror_point(a.Hx, a.Hp, a.Ny, a.Nz);
     if (!mp.valid) return;
     const int r = blockIdx.y;
-    const long plane = (long)a.Nz * a.Ny * a.Hx;
-    const long koct = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    const long plane = (long)a.Nz * a.Ny * a.Hp;
+    const long koct = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     const int t = a.t;
     double2 *F = a.far + ((long)t * a.nrhs + r) * 3 * plane + mp.off;
     double2 acc[3] = {F[0], F[plane], F[2 * plane]};
@@ -352,7 +355,7 @@ __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 
 void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
 {
-    const long nocts = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     // TB = TG * G targets per launch; points per block = 32 / G
     auto grid = [&](int G) { return dim3((unsigned)((nocts + 32 / G - 1) / (32 / G)), a.nrhs); };
     const dim3 blk(256);
@@ -368,7 +371,7 @@ void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
 
 void launch_mac_near(const BlockMacArg &a, hipStream_t st)
 {
-    const long nocts = (long)a.Hx * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     dim3 grd((unsigned)((nocts + 63) / 64), a.nrhs), blk(256);
     hipLaunchKernelGGL(k_mac_near, grd, blk, 0, st, a);
     MJ_CHECK(hipGetLastError());
