@@ -407,3 +407,125 @@ def test_probe_objective_autograd(torch_cuda, adjoint_oracle):
     assert abs(phi.item() - phi_ref) <= 1e-10 * abs(phi_ref)
     assert _rel(gr.numpy(), 3.0 * grad_ref) <= 1e-8
     s.close()
+
+
+# ----------------------------------------------------------------------------- full size
+def test_full_size_104_sampled(torch_cuda):
+    """The 104^3 workload in the configuration bench.py times (time block 8, 17 taps):
+    the history sum over all 182 lags for a history carried by 40 scatterer voxels, sampled at
+    16 voxels (8 of them sources, so the local and FIR terms are in play) against the oracle's
+    direct sum with kernels computed pair by pair; and sampled generated kernels at offsets up
+    to 103 and lags up to 182."""
+    from oracle import mot
+    torch = torch_cuda
+    prob = wl.config("C5")
+    U = prob.U
+    say("full size 104^3: create")
+    s = make_solver(prob, time_block=8)
+    ell = s.ell
+    rng = np.random.default_rng(104)
+    inside = np.argwhere(prob.eps > 1.0)                     # (w, v, u)
+    src = inside[rng.choice(len(inside), 40, replace=False)]
+    tgt = np.concatenate([src[:8], inside[rng.choice(len(inside), 8, replace=False)]])
+    Js = rng.standard_normal((ell, 3, len(src)))
+    Jh = torch.zeros((ell, 3, U, U, U), dtype=torch.float64, device="cuda")
+    idx = torch.tensor(src, device="cuda")
+    for k in range(ell):
+        for c in range(3):
+            Jh[k, c, idx[:, 0], idx[:, 1], idx[:, 2]] = torch.tensor(Js[k, c], dtype=torch.float64, device="cuda")
+    P = torch.zeros((3, U, U, U), dtype=torch.float64, device="cuda")
+    say("full size 104^3: history sum")
+    s.history_sum(Jh, P)
+    torch.cuda.synchronize()
+    Ph = P.cpu().numpy()
+    del Jh, P
+    conv = mot.conv_pairs(tgt[:, ::-1], src[:, ::-1], Js)            # [3][nt], sum_k K_k (*) J_{n-k}
+    cl = mot.local_coefficients(prob.eps, prob.fir, ell)
+    chi = mot.chi_of(prob.eps)
+    ref = np.zeros((3, len(tgt)))
+    for i, (w, v, u) in enumerate(tgt):
+        loc = np.zeros(3)
+        hit = np.where((src == (w, v, u)).all(axis=1))[0]
+        if len(hit):
+            for k in range(1, ell + 1):
+                loc += cl[k][w, v, u] * Js[k - 1, :, hit[0]]
+        ref[:, i] = loc - chi[w, v, u] * conv[:, i]
+    got = np.stack([Ph[:, w, v, u] for (w, v, u) in tgt], axis=1)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  history sum sampled rel", err)
+    assert err <= 1e-11
+    say("full size 104^3: kernels")
+    offs, lags = [], []
+    for _ in range(40):
+        D = rng.integers(-(U - 1), U, 3)
+        R = np.sqrt(((np.maximum(np.abs(D) - 1, 0)) ** 2).sum())
+        offs.append(D)
+        lags.append(int(min(ell, int(R) + rng.integers(0, 4))))
+    offs += [np.array([103, 103, 103]), np.array([-103, 0, 2])]
+    lags += [ell, 104]
+    got = s.kernel_values(lags, np.array(offs))
+    worst = 0.0
+    for i, (k, D) in enumerate(zip(lags, offs)):
+        ref = mot.kernel_entry(k, D)
+        R = np.sqrt(((np.maximum(np.abs(D) - 1, 0)) ** 2).sum())
+        scale = max(np.abs(ref).max(), 0.03 / (1.0 + R))
+        worst = max(worst, np.abs(got[i] - ref).max() / scale)
+    say("  kernels worst", worst)
+    assert worst <= 3e-12
+    s.close()
+
+
+# ----------------------------------------------------------------------------- degenerate cases
+@pytest.mark.parametrize("UVW", [(1, 1, 1), (7, 1, 1), (1, 5, 2), (3, 3, 1)])
+def test_march_degenerate_grids(torch_cuda, UVW):
+    """One voxel, a line, thin slabs: padded sizes of 2, ell as small as 3, every time block
+    larger than the history; against the oracle's march."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W = UVW
+    n = 30
+    say("degenerate grid", UVW)
+    eps = wl.random_eps(U, V, W, 5, 2.0, 9.0)
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("deg", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1))
+    ref = mot.Oracle(prob).run(n)
+    s = make_solver(prob, time_block=8)
+    Jt = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    s.run(n, Jt)
+    torch.cuda.synchronize()
+    err = _rel(Jt.cpu().numpy()[:, 0], ref)
+    say("  ell", s.ell, "rel L2", err)
+    assert err <= 1e-8
+    s.close()
+
+
+def test_vacuum_and_restart(torch_cuda):
+    """eps_r = 1 everywhere: no contrast, J and the probe field stay exactly zero.  Then a
+    dielectric block: zero steps change nothing, and a march after mj_reset repeats the first
+    one bit for bit."""
+    torch = torch_cuda
+    U, V, W, n = 5, 4, 3, 25
+    k, p = wl.XPOL_PLUS_Z
+    wave = wl.gaussian_wave(U, V, W, k, p, 2.0)
+    vac = wl.Problem("vac", U, V, W, np.ones((W, V, U)), [wave], n, fir=wl.binomial_highpass(3, 0.1))
+    s = make_solver(vac, time_block=8)
+    s.set_probes(wl.fibonacci_sphere(3, 4.0, (2.5, 2.0, 1.5)))
+    Jt = torch.ones((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    Pt = torch.ones((n, 1, 3, 3), dtype=torch.float64, device="cuda")
+    s.run(n, Jt, Pt)
+    torch.cuda.synchronize()
+    assert float(Jt.abs().max()) == 0.0 and float(Pt.abs().max()) == 0.0
+    s.close()
+    diel = wl.Problem("diel", U, V, W, wl.random_eps(U, V, W, 9, 2.0, 9.0), [wave], n,
+                      fir=wl.binomial_highpass(3, 0.1))
+    s = make_solver(diel, time_block=8)
+    s.run(0)
+    J1 = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    J2 = torch.zeros_like(J1)
+    s.run(n, J1)
+    s.reset()
+    s.run(n, J2)
+    torch.cuda.synchronize()
+    assert torch.equal(J1, J2)
+    s.close()
