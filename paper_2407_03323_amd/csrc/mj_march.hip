@@ -192,8 +192,8 @@ __device__ inline int ring_slot(int j, int ring)
 // k' (J at n_b - k') goes to slot (k - 1) mod TG and local target tt at lag k reads the slot
 // written at lag k - tt.  A group's sources are those of group 0 TG lags earlier, so the
 // extra loads hit in cache; K_k is the same for every group.
-template <int TG, int G, int PD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mac_far(BlockMacArg a)
+template <int TG, int G, int PD, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_mac_far(BlockMacArg a)
 {
     static_assert(64 % (2 * G) == 0, "lanes split evenly into groups");
     static_assert(TG % PD == 0, "the prefetch buffers rotate with the slot window");
@@ -360,10 +360,12 @@ void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
     auto grid = [&](int G) { return dim3((unsigned)((nocts + 32 / G - 1) / (32 / G)), a.nrhs); };
     const dim3 blk(256);
     switch (tb) {
-    case 4: hipLaunchKernelGGL((k_mac_far<4, 1, 2>), grid(1), blk, 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_mac_far<8, 1, 2>), grid(1), blk, 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_mac_far<8, 2, 2>), grid(2), blk, 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_mac_far<8, 4, 2>), grid(4), blk, 0, st, a); break;
+    // last argument: waves per SIMD the register budget is held to.  At TB = 8, three waves
+    // (168 VGPRs, one lag in flight) measured slower than two waves with two lags in flight.
+    case 4: hipLaunchKernelGGL((k_mac_far<4, 1, 2, 3>), grid(1), blk, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_mac_far<8, 1, 2, 2>), grid(1), blk, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_mac_far<8, 2, 2, 2>), grid(2), blk, 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_mac_far<8, 4, 2, 2>), grid(4), blk, 0, st, a); break;
     default: throw ArgError("unsupported time block (4, 8, 16 or 32)");
     }
     MJ_CHECK(hipGetLastError());
@@ -416,36 +418,39 @@ __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
     if (i >= M) return;
     const double chi = e.chi[i], sc = e.schi[i];
     const int u = (int)(i % e.U), v = (int)((i / e.U) % e.V), z = (int)(i / ((long)e.U * e.V));
-    double avg = 0.0;
+    const long Mp = (long)(e.U + 2) * (e.V + 2) * (e.W + 2);
+    const long ip = ((long)(z + 1) * (e.V + 2) + (v + 1)) * (e.U + 2) + (u + 1);
+    if (sc == 0.0) {
+        // vacuum voxel: its current and every term of its row vanish
+        for (int c = 0; c < 3; c++) {
+            const long o = ((long)r * 3 + c) * M + i;
+            e.rhs[o] = 0.0;
+            e.y[o] = 0.0;
+            e.uy[((long)r * 3 + c) * Mp + ip] = 0.0;
+        }
+        return;
+    }
     const WaveArg w = e.waves[r];
-    if (chi != 0.0) avg = wave_average(w, e, u, v, z, e.n * e.c_dt);
+    const double avg = wave_average(w, e, u, v, z, e.n * e.c_dt);
     const double c1 = 0.5 * e.inv_eps[i] + (e.nfir > 1 ? e.fir[1] : 0.0);
+    const int kmax = min(e.nloc, e.n - 1);   // lags with a past current
+    // initial guess of the Z_0 solve: the quartic through the last five solutions (the
+    // current is smooth in time, so this lands close to y_n)
+    constexpr double cx[5] = {5.0, -10.0, 10.0, -5.0, 1.0};
     for (int c = 0; c < 3; c++) {
-        double b = chi * (avg * w.pol[c] + (e.S ? e.S[((long)r * 3 + c) * M + i] : 0.0));
-        for (int k = 1; k <= e.nloc; k++) {
-            if (e.n - k < 1) break;
-            const double ck = (k == 1) ? c1 : (k < e.nfir ? e.fir[k] : 0.0);
-            if (ck == 0.0) continue;
-            const double *Jk = e.Jring + (((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M;
-            b -= ck * Jk[i];
-        }
-        double rhs = sc > 0.0 ? b / sc : 0.0;
-        double y0 = 0.0;
-        if (sc > 0.0) {
-            // initial guess of the Z_0 solve: the quartic through the last five solutions
-            // (the current is smooth in time, so this lands close to y_n)
-            constexpr double cx[5] = {5.0, -10.0, 10.0, -5.0, 1.0};
-            double g = 0.0;
-#pragma unroll
-            for (int k = 1; k <= 5; k++)
-                if (e.n - k >= 1) g += cx[k - 1] * e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
-            y0 = g / sc;
-        }
         const long o = ((long)r * 3 + c) * M + i;
-        e.rhs[o] = rhs;
+        double b = chi * (avg * w.pol[c] + (e.S ? e.S[o] : 0.0));
+        double g = 0.0;
+#pragma unroll 4
+        for (int k = 1; k <= kmax; k++) {
+            const double jv = e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
+            const double ck = (k == 1) ? c1 : (k < e.nfir ? e.fir[k] : 0.0);
+            b -= ck * jv;
+            if (k <= 5) g += cx[k - 1] * jv;
+        }
+        const double y0 = g / sc;
+        e.rhs[o] = b / sc;
         e.y[o] = y0;
-        const long Mp = (long)(e.U + 2) * (e.V + 2) * (e.W + 2);
-        const long ip = ((long)(z + 1) * (e.V + 2) + (v + 1)) * (e.U + 2) + (u + 1);
         e.uy[((long)r * 3 + c) * Mp + ip] = sc * y0;
     }
 }
