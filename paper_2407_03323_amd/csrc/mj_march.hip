@@ -126,12 +126,12 @@ struct MirrorPoint {
     double sy, sz; // parity signs of the odd components
 };
 
-__device__ inline MirrorPoint mirror_point(int Hx, int Hp, int Ny, int Nz)
+__device__ inline MirrorPoint mirror_point(int Hx, int Hp, int Ny, int Nz, long group)
 {
     MirrorPoint mp;
     const int Nyo = Ny / 2 + 1, Nzo = Nz / 2 + 1;
     const long nocts = (long)Hp * Nyo * Nzo;
-    const long o = blockIdx.x * 64L + (threadIdx.x & 63);
+    const long o = group * 64L + (threadIdx.x & 63);
     const int m = (threadIdx.x >> 6) & 3;
     mp.valid = o < nocts;
     if (!mp.valid) return mp;
@@ -203,7 +203,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     const long nocts = (long)a.Hp * Nyo * Nzo;
     const int lane = threadIdx.x & 63;
     const int g = lane / kLanesPerGroup, li = lane % kLanesPerGroup;
-    const long o = blockIdx.x * (long)kPointsPerWave + (li >> 1);
+    // the right-hand sides of one point group are adjacent blocks, so the kernel values they
+    // share are read from HBM once and hit in cache for the others
+    const int r = blockIdx.x % a.nrhs;
+    const long o = (blockIdx.x / a.nrhs) * (long)kPointsPerWave + (li >> 1);
     const int part = li & 1;
     const int m = threadIdx.x >> 6;
     if (o >= nocts) return;
@@ -214,7 +217,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int ky = fy ? a.Ny - qy : qy, kz = fz ? a.Nz - qz : qz;
     const double sy = fy ? -1.0 : 1.0, sz = fz ? -1.0 : 1.0;
     const long off2 = 2 * (((long)kz * a.Ny + ky) * a.Hp + kx) + part;   // in doubles
-    const int r = blockIdx.y;
     const long plane2 = 2L * a.Nz * a.Ny * a.Hp;                           // one component, in doubles
     const long koct = nocts;
     const int tg0 = g * TG;                                                // first target of the group
@@ -323,9 +325,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 // near part of step n = n_b + t, accumulated in place into F[t]
 __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 {
-    const MirrorPoint mp = mirror_point(a.Hx, a.Hp, a.Ny, a.Nz);
+    const MirrorPoint mp = mirror_point(a.Hx, a.Hp, a.Ny, a.Nz, blockIdx.x / a.nrhs);
     if (!mp.valid) return;
-    const int r = blockIdx.y;
+    const int r = blockIdx.x % a.nrhs;
     const long plane = (long)a.Nz * a.Ny * a.Hp;
     const long koct = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     const int t = a.t;
@@ -357,7 +359,7 @@ void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
 {
     const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     // TB = TG * G targets per launch; points per block = 32 / G
-    auto grid = [&](int G) { return dim3((unsigned)((nocts + 32 / G - 1) / (32 / G)), a.nrhs); };
+    auto grid = [&](int G) { return dim3((unsigned)((nocts + 32 / G - 1) / (32 / G) * a.nrhs)); };
     const dim3 blk(256);
     switch (tb) {
     // last argument: waves per SIMD the register budget is held to.  At TB = 8, three waves
@@ -374,7 +376,7 @@ void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
 void launch_mac_near(const BlockMacArg &a, hipStream_t st)
 {
     const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
-    dim3 grd((unsigned)((nocts + 63) / 64), a.nrhs), blk(256);
+    dim3 grd((unsigned)((nocts + 63) / 64 * a.nrhs)), blk(256);
     hipLaunchKernelGGL(k_mac_near, grd, blk, 0, st, a);
     MJ_CHECK(hipGetLastError());
 }
