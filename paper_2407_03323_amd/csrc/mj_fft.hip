@@ -151,21 +151,37 @@ struct PlanArg {
     int radix[kMaxStages];
 };
 
+// Radix sets: a kernel instantiated for set MASK holds code (and registers) only for the
+// radices in it.  The generic instance kAll serves every plan.
+constexpr int kR2 = 1, kR3 = 2, kR4 = 4, kR5 = 8, kR7 = 16, kR11 = 32, kR13 = 64, kAll = 127;
+
+// Stage of radix R for a plan whose radices lie in MASK: tests the radices of MASK in turn;
+// the last one is taken without a test (the plan guarantees R is in MASK).
+constexpr int kRadixOfBit[7] = {2, 3, 4, 5, 7, 11, 13};
+constexpr int lowest_bit(int m) { return (m & 1) ? 0 : 1 + lowest_bit(m >> 1); }
+
+template <int MASK>
+__device__ inline void stage_of(int R, double2 *buf, int N, int Ns, int P, int ld, const double2 *tw, bool inv)
+{
+    constexpr int b = lowest_bit(MASK);
+    constexpr int RB = kRadixOfBit[b];
+    constexpr int REST = MASK & ~(1 << b);
+    if constexpr (REST == 0) {
+        stage<RB>(buf, N, Ns, P, ld, tw, inv);
+    } else {
+        if (R == RB) stage<RB>(buf, N, Ns, P, ld, tw, inv);
+        else stage_of<REST>(R, buf, N, Ns, P, ld, tw, inv);
+    }
+}
+
 // Runs all stages in place on the tile in buf.
+template <int MASK>
 __device__ void lds_fft(double2 *buf, int P, int ld, const PlanArg &pl, const double2 *tw, bool inv)
 {
     int Ns = 1;
     for (int s = 0; s < pl.nst; s++) {
-        int R = pl.radix[s];
-        switch (R) {
-        case 2: stage<2>(buf, pl.N, Ns, P, ld, tw, inv); break;
-        case 3: stage<3>(buf, pl.N, Ns, P, ld, tw, inv); break;
-        case 4: stage<4>(buf, pl.N, Ns, P, ld, tw, inv); break;
-        case 5: stage<5>(buf, pl.N, Ns, P, ld, tw, inv); break;
-        case 7: stage<7>(buf, pl.N, Ns, P, ld, tw, inv); break;
-        case 11: stage<11>(buf, pl.N, Ns, P, ld, tw, inv); break;
-        default: stage<13>(buf, pl.N, Ns, P, ld, tw, inv); break;   // the plan holds only 2, 3, 4, 5, 7, 11, 13
-        }
+        const int R = pl.radix[s];
+        stage_of<MASK>(R, buf, pl.N, Ns, P, ld, tw, inv);
         __syncthreads();
         Ns *= R;
     }
@@ -201,6 +217,7 @@ __device__ inline void gather_tile(int total, Get get, Put put)
 // ---------------------------------------------------------------------------- x pass
 // Forward: rows of U reals (row r at x + r*U), nrows rows; two rows per pencil.
 // Output: rows of Hx complex at X + r*Hp.
+template <int MASK>
 __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict__ x, double2 *__restrict__ X,
                                                         int nrows, int U, int Hx, int Hp, PlanArg pl, const double2 *tw,
                                                         int P)
@@ -229,7 +246,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
             if (rr & 1) slot->y = v; else slot->x = v;
         });
     __syncthreads();
-    lds_fft(a, P, ld, pl, tw_s, false);
+    lds_fft<MASK>(a, P, ld, pl, tw_s, false);
     const double2 *res = a;
     // separate: Xa[k] = (Z[k] + conj Z[N-k]) / 2, Xb[k] = (Z[k] - conj Z[N-k]) / (2i)
     for (int i = threadIdx.x; i < 2 * P * Hx; i += blockDim.x) {
@@ -246,6 +263,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
 }
 
 // Inverse: rows of Hx complex half-spectra (pitch Hp) -> rows of U reals (unnormalised).
+template <int MASK>
 __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restrict__ X, double *__restrict__ y,
                                                         int nrows, int U, int Hx, int Hp, PlanArg pl, const double2 *tw,
                                                         int P)
@@ -278,7 +296,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
             a[p * ld + n] = make_double2(xa.x - xb.y, xa.y + xb.x);
         });
     __syncthreads();
-    lds_fft(a, P, ld, pl, tw_s, true);
+    lds_fft<MASK>(a, P, ld, pl, tw_s, true);
     const double2 *res = a;
     for (int i = threadIdx.x; i < 2 * P * U; i += blockDim.x) {
         int rr = i / U, u = i - rr * U;
@@ -299,6 +317,7 @@ struct StridedArg {
     int n_in, n_out;
 };
 
+template <int MASK>
 __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restrict__ in, double2 *__restrict__ out,
                                                           StridedArg g, PlanArg pl, const double2 *tw, int P,
                                                           int inv)
@@ -326,7 +345,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restr
             a[p * ld + n] = v;
         });
     __syncthreads();
-    lds_fft(a, P, ld, pl, tw_s, inv != 0);
+    lds_fft<MASK>(a, P, ld, pl, tw_s, inv != 0);
     const double2 *res = a;
     double2 *dst = out + c * g.cs_out + q * g.qs_out + kx0;
     for (int i = threadIdx.x; i < P * g.n_out; i += blockDim.x) {
@@ -423,14 +442,46 @@ void fft3d_free(Fft3D &f)
     f.bufA = f.bufB = nullptr;
 }
 
+// Radix set of a plan, and the kernel instance that serves it: the sets of the usual padded
+// sizes (208 = 4 4 13; powers of two; 2^k 3) have their own instances, any other plan the
+// generic one.
+static int plan_mask(const FftPlan1D &p)
+{
+    int m = 0;
+    for (int i = 0; i < p.nst; i++) {
+        switch (p.radix[i]) {
+        case 2: m |= kR2; break;
+        case 3: m |= kR3; break;
+        case 4: m |= kR4; break;
+        case 5: m |= kR5; break;
+        case 7: m |= kR7; break;
+        case 11: m |= kR11; break;
+        default: m |= kR13; break;
+        }
+    }
+    return m;
+}
+
+#define MJ_FFT_DISPATCH(mask, KERNEL, ...)                                                        \
+    do {                                                                                          \
+        switch (mask) {                                                                           \
+        case kR4 | kR13: hipLaunchKernelGGL(KERNEL<kR4 | kR13>, __VA_ARGS__); break;              \
+        case kR4: hipLaunchKernelGGL(KERNEL<kR4>, __VA_ARGS__); break;                            \
+        case kR2 | kR4: hipLaunchKernelGGL(KERNEL<kR2 | kR4>, __VA_ARGS__); break;                \
+        case kR3 | kR4: hipLaunchKernelGGL(KERNEL<kR3 | kR4>, __VA_ARGS__); break;                \
+        case kR2 | kR3 | kR4: hipLaunchKernelGGL(KERNEL<kR2 | kR3 | kR4>, __VA_ARGS__); break;    \
+        default: hipLaunchKernelGGL(KERNEL<kAll>, __VA_ARGS__); break;                            \
+        }                                                                                         \
+    } while (0)
+
 static void launch_strided(const double2 *in, double2 *out, const StridedArg &g, int ncomp, const FftPlan1D &p,
                            bool inv, hipStream_t st)
 {
     int P = pencils_per_block(p.N);
     int ntile = (g.Hx + P - 1) / P;
     dim3 grid(ncomp * g.nq * ntile);
-    hipLaunchKernelGGL(k_fft_strided, grid, dim3(kThreads), lds_bytes(p.N, P), st, in, out, g, plan_arg(p), p.tw, P,
-                       inv ? 1 : 0);
+    MJ_FFT_DISPATCH(plan_mask(p), k_fft_strided, grid, dim3(kThreads), lds_bytes(p.N, P), st, in, out, g,
+                    plan_arg(p), p.tw, P, inv ? 1 : 0);
     MJ_CHECK(hipGetLastError());
 }
 
@@ -442,8 +493,8 @@ void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t
         int nrows = ncomp * W * V;
         int P = pencils_per_block(f.Nx);
         dim3 grid((nrows + 2 * P - 1) / (2 * P));
-        hipLaunchKernelGGL(k_fft_x_fwd, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, x, f.bufA, nrows, U, Hx, Hp,
-                           plan_arg(f.px), f.px.tw, P);
+        MJ_FFT_DISPATCH(plan_mask(f.px), k_fft_x_fwd, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, x, f.bufA, nrows,
+                        U, Hx, Hp, plan_arg(f.px), f.px.tw, P);
         MJ_CHECK(hipGetLastError());
     }
     // y pass: groups (c, w); A[c][w][v][kx] -> B[c][w][ky][kx]
@@ -492,8 +543,8 @@ void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t
         int nrows = ncomp * W * V;
         int P = pencils_per_block(f.Nx);
         dim3 grid((nrows + 2 * P - 1) / (2 * P));
-        hipLaunchKernelGGL(k_fft_x_inv, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, f.bufA, y, nrows, U, Hx, Hp,
-                           plan_arg(f.px), f.px.tw, P);
+        MJ_FFT_DISPATCH(plan_mask(f.px), k_fft_x_inv, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, f.bufA, y, nrows,
+                        U, Hx, Hp, plan_arg(f.px), f.px.tw, P);
         MJ_CHECK(hipGetLastError());
     }
 }
