@@ -234,6 +234,21 @@ def main():
         kname = "k_mac (history MAC, all lags every step)"
     achieved = bytes_launch / (launch_ms / 1e3) / 1e9
     traffic = mac_traffic(args.workload)
+    # the whole FFT convolution of a step (forward FFT, far + near MAC, inverse FFT): algorithmic
+    # bytes per step over the measured time of those three phases
+    U, V, W = prob.U, prob.V, prob.W
+    Hx_ = Nx // 2 + 1
+    fft_bytes = 8.0 * 3 * M + 16.0 * 3 * (Hx_ * V * W + Hx_ * V * W + Hx_ * Ny * W + Hx_ * Ny * W + half)
+    if B > 1:
+        near_bytes = sum(2 * 48.0 * half + t * (48.0 * half + 48.0 * octant) for t in range(1, B)) / B
+        mac_step = bytes_launch / B + near_bytes
+    else:
+        mac_step = bytes_launch
+    conv_bytes = 2 * fft_bytes + mac_step
+    conv_ms = st["fft_fwd_ms"] + st["mac_ms"] + st["fft_inv_ms"]
+    conv = {"bytes_per_step": conv_bytes, "ms_per_step": conv_ms,
+            "achieved": conv_bytes / (conv_ms / 1e3) / 1e9, "unit": "GB/s",
+            "frac": conv_bytes / (conv_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
     line = {
         "metric": METRIC,
         "value": value,
@@ -257,7 +272,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "bytes_per_launch": bytes_launch,
-                     "avg_launch_ms": launch_ms},
+                     "avg_launch_ms": launch_ms, "convolution": conv},
     }
     solver.close()
     del solver

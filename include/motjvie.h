@@ -49,7 +49,7 @@ enum {
     MJ_ENOMEM = -2,      /* device allocation failed */
     MJ_EHIP = -3,        /* HIP runtime error */
     MJ_ENOCONV = -4,     /* Z_0 solve did not reach cg_rtol within cg_maxit */
-    MJ_EUNSTABLE = -5,   /* current grew beyond the instability threshold */
+    MJ_EUNSTABLE = -5,   /* the march grows without bound (right-hand side norm > 1e100 or not finite) */
     MJ_ESTATE = -6       /* call not valid in the current state */
 };
 
@@ -111,7 +111,9 @@ int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, cons
  * mj_run -- march n_steps steps (eq:MOTInversion for n = n_cur+1 .. n_cur+n_steps).
  *   J_hist: device, nullable, [n_steps][n_rhs][3][W][V][U]; receives J_n of every step.
  *   Returns MJ_ENOCONV if a Z_0 solve missed cg_rtol (the march state stays consistent:
- *   J_n holds the last iterate).
+ *   J_n holds the last iterate).  Returns MJ_EUNSTABLE, and stops after that step, once the
+ *   right-hand side of a Z_0 solve exceeds 1e100 in norm or is not finite: the unbounded
+ *   growth of Sec. 5 (the alternating mode at f = 1/(2 dt)); mj_info entry 7 gives the step.
  */
 int mj_run(mj_solver *s, int32_t n_steps, double *J_hist);
 

@@ -12,6 +12,7 @@
 using mj::ArgError;
 using mj::HipError;
 using mj::MemError;
+using mj::UnstableError;
 
 namespace {
 
@@ -73,7 +74,6 @@ struct mj_solver {
     double *rhs = nullptr, *y = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     double *u = nullptr, *uy = nullptr;
     double *parts = nullptr;
-    unsigned *counters = nullptr;
     mj::CgScalars *scal = nullptr;
     int cg_guess = 8;
     mj::CgStatus *cgstat = nullptr, *cgstat_h = nullptr;
@@ -158,6 +158,7 @@ struct mj_solver {
     mj::EpiArg epi_arg() const;
     mj::AdjArg adj_arg() const;
     void step(const StepIO &io);
+    void check_growth() const;
     void run(int n_steps, double *Jout, double *Pout);
     void adjoint_gradient(int n_steps, int ckpt_every, double *phi, double *grad_dev, double *probe_hist);
     void set_probes(int n_probes, const double *pos);
@@ -242,8 +243,6 @@ void mj_solver::create(const mj_config &c)
     MJ_CHECK(hipMemset(uy, 0, sizeof(double) * nrhs * 3 * Mp));
     nblk = (int)((M + 255) / 256);
     parts = dalloc<double>((size_t)3 * nrhs * nblk, "cg partials");
-    counters = dalloc<unsigned>(nrhs, "cg counters");
-    MJ_CHECK(hipMemset(counters, 0, sizeof(unsigned) * nrhs));
     scal = dalloc<mj::CgScalars>(nrhs, "cg scalars");
     cgstat = dalloc<mj::CgStatus>(nrhs, "cg status");
     waves_d = dalloc<mj::WaveArg>(nrhs, "waves");
@@ -573,6 +572,18 @@ void mj_solver::step(const StepIO &io)
     if (ev) MJ_CHECK(hipEventRecord(ev[6], st));
 }
 
+// The march grows without bound (Sec. 5: the alternating mode at f = 1/(2 dt)): stop once the
+// right-hand side of a Z_0 solve leaves the finite range or passes 1e100 in norm.
+void mj_solver::check_growth() const
+{
+    for (int i = 0; i < nrhs; i++) {
+        const double bb = cgstat_h[i].bb;
+        if (!std::isfinite(bb) || bb > 1e200 || !std::isfinite(cgstat_h[i].res))
+            throw UnstableError("the march is unstable: the Z_0 right-hand side of step " + std::to_string(n) +
+                                " exceeds 1e100 in norm or is not finite");
+    }
+}
+
 mj::AdjArg mj_solver::adj_arg() const
 {
     mj::AdjArg a{};
@@ -607,6 +618,7 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout)
         io.Pout = Pout ? Pout + (size_t)s * nrhs * np * 3 : nullptr;
         io.far_kind = &step_far[s];
         step(io);
+        check_growth();
         for (int i = 0; i < nrhs; i++) {
             cg_iter_sum += cgstat_h[i].iters;
             cg_iter_max = std::max(cg_iter_max, (double)cgstat_h[i].iters);
@@ -918,6 +930,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             io.Pout = Ehist + (size_t)(t - 1) * nrhs * np * 3;
             io.Bout = t >= last0 ? Bbuf + (size_t)(t - last0) * vec : nullptr;
             step(io);
+            check_growth();
             check_cg();
             if (next_ck < C && t + 1 == starts[next_ck]) {
                 // J_j for j = t - ell .. t (those with j >= 1) from the real-space ring
@@ -1039,6 +1052,8 @@ int guarded(mj_solver *s, F &&f)
         return fail(s, MJ_ENOMEM, e.what());
     } catch (const HipError &e) {
         return fail(s, MJ_EHIP, e.what());
+    } catch (const UnstableError &e) {
+        return fail(s, MJ_EUNSTABLE, e.what());
     } catch (const std::range_error &e) {
         return fail(s, MJ_ENOCONV, e.what());
     } catch (const std::logic_error &e) {

@@ -23,6 +23,9 @@ struct HipError : std::runtime_error {
 struct ArgError : std::runtime_error {
     using std::runtime_error::runtime_error;
 };
+struct UnstableError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
 struct MemError : std::runtime_error {
     using std::runtime_error::runtime_error;
 };

@@ -90,6 +90,7 @@ struct CgStatus {
     int done;                // converged (set by the first iteration whose test passes)
     int iters;               // iterations taken
     double res;              // relative residual |r| / |b| at the last test
+    double bb;               // |b|^2 of the solve's right-hand side (growth detector)
 };
 
 struct CgArg {

@@ -590,7 +590,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
     const long M = a.M, base = (long)r * 3 * M;
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};   // rz, rr, bb
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[r] = CgStatus{0, 0, 0.0};
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[r] = CgStatus{0, 0, 0.0, 0.0};
     if (i < M) {
         const double s = a.schi[i];
         const double md = a.inv_diag[i];
@@ -631,12 +631,14 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
             a.stat[r].done = 1;
             a.stat[r].iters = it;
             a.stat[r].res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            a.stat[r].bb = bb;
         }
         return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.stat[r].iters = it;
         a.stat[r].res = sqrt(rr / bb);
+        a.stat[r].bb = bb;
     }
     const double beta = it > 0 ? sc->rz[it & 1] / sc->rz[(it + 1) & 1] : 0.0;
     const long M = a.M, base = (long)r * 3 * M;

@@ -529,3 +529,27 @@ def test_vacuum_and_restart(torch_cuda):
     torch.cuda.synchronize()
     assert torch.equal(J1, J2)
     s.close()
+
+
+def test_unbounded_growth_is_reported(torch_cuda):
+    """A FIR tap that makes the march grow (delta_1 = 5 on a 3^3 block) ends the run with
+    MJ_EUNSTABLE well before the requested 300 steps; a stable march of the same block does
+    not."""
+    from paper_2407_03323_amd.motjvie import MJ_EUNSTABLE, MotJvieError
+    U = 3
+    k, p = wl.XPOL_PLUS_Z
+    wave = wl.gaussian_wave(U, U, U, k, p, 2.0)
+    bad = wl.Problem("grow", U, U, U, np.full((U, U, U), 4.0), [wave], 300, fir=np.array([0.0, 5.0]))
+    s = make_solver(bad, time_block=8)
+    with pytest.raises(MotJvieError) as ei:
+        s.run(300)
+    assert ei.value.code == MJ_EUNSTABLE
+    stopped = s.info()["n"]
+    say("  unstable march stopped at step", stopped)
+    assert 12 < stopped < 300
+    s.close()
+    ok = wl.Problem("stable", U, U, U, np.full((U, U, U), 4.0), [wave], 300, fir=wl.binomial_highpass(3, 0.1))
+    s = make_solver(ok, time_block=8)
+    s.run(300)
+    assert s.info()["n"] == 300
+    s.close()
