@@ -71,7 +71,7 @@ struct mj_solver {
     double *Khat = nullptr;
     double2 *ring = nullptr, *Shat = nullptr, *farbuf = nullptr;
     double *S = nullptr, *Jr = nullptr;
-    double *rhs = nullptr, *y = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+    double *rhs = nullptr, *y = nullptr, *p = nullptr, *q = nullptr;
     double *u = nullptr, *uy = nullptr;
     double *parts = nullptr;
     mj::CgScalars *scal = nullptr;
@@ -229,7 +229,6 @@ void mj_solver::create(const mj_config &c)
     Jr = dalloc<double>((size_t)rdepth * nrhs * 3 * M, "current history");
     rhs = dalloc<double>((size_t)nrhs * 3 * M, "cg rhs");
     y = dalloc<double>((size_t)nrhs * 3 * M, "cg y");
-    r = dalloc<double>((size_t)nrhs * 3 * M, "cg r");
     p = dalloc<double>((size_t)nrhs * 3 * M, "cg p");
     q = dalloc<double>((size_t)nrhs * 3 * M, "cg q");
     // the first iteration of every solve scales p and q by beta = 0: they must be finite
@@ -371,7 +370,6 @@ void mj_solver::solve_z0()
     a.rhs = rhs;
     a.uy = uy;
     a.y = y;
-    a.r = r;
     a.p = p;
     a.q = q;
     a.u = u;
@@ -396,13 +394,8 @@ void mj_solver::solve_z0()
         for (int i = 0; i < nrhs; i++) all_done = all_done && cgstat_h[i].done;
         batch = 2;
     }
-    if (!all_done) {
-        // out of iterations: one more test records the final residual (and the flag, if the
-        // last update converged)
-        mj::launch_cg_a(a, it, st);
-        MJ_CHECK(hipMemcpyAsync(cgstat_h, cgstat, sizeof(mj::CgStatus) * nrhs, hipMemcpyDeviceToHost, st));
-        MJ_CHECK(hipStreamSynchronize(st));
-    }
+    // the last update of y (a no-op for the right-hand sides whose solve already ended)
+    mj::launch_cg_end(a, it, st);
     int mx = 0;
     for (int i = 0; i < nrhs; i++) mx = std::max(mx, cgstat_h[i].iters);
     cg_guess = mx + 1;

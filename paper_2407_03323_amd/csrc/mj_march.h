@@ -83,6 +83,7 @@ struct AdjArg {
 struct CgScalars {
     double rz[2];            // r.z of the current and the previous iteration (alternating slots)
     double pq, rr, bb;
+    int conv;                // iteration whose convergence test passed (INT_MAX: none yet)
 };
 
 // per right-hand side, read back by the host in one copy
@@ -101,7 +102,7 @@ struct CgArg {
     double tol2;
     const double *schi, *c0, *inv_diag;
     const double *rhs, *uy;  // uy, u: haloed layout [nrhs][3][Mp]
-    double *y, *r, *p, *q, *u;
+    double *y, *p, *q, *u;   // u = sqrt(chi) M^-1 r stands for the residual r
     double *part;            // [nrhs][3][nblk]
     CgScalars *scal;         // [nrhs]
     CgStatus *stat;          // [nrhs]
@@ -141,6 +142,7 @@ void upload_stencil(const double *K0_27x6);
 void launch_cg_init(const CgArg &a, hipStream_t st);
 void launch_cg_a(const CgArg &a, int it, hipStream_t st);
 void launch_cg_b(const CgArg &a, int it, hipStream_t st);
+void launch_cg_end(const CgArg &a, int it, hipStream_t st);
 void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, double *J, double *Jout,
                       hipStream_t st);
 

@@ -3,6 +3,7 @@
 // conjugate-gradient solve with Z_0.
 #include "mj_march.h"
 
+#include <climits>
 #include <cmath>
 
 namespace mj {
@@ -493,10 +494,17 @@ void launch_history_local(const double *Jh, int depth, const double *S, const do
 // Symmetrised Z_0:  J = D y with D = diag(sqrt(chi)),  A = C_0 - D K_0 D,
 // (A z)_b(m) = c_0(m) z_b(m) - s(m) sum_{D in 27} sum_a K_0^{ba}(D) u_a(m-D),   u = s z.
 // K_0(D) = K_0(-D) for every component, so the 26 neighbours are summed in 13 pairs.
-// A is symmetric positive definite; Jacobi preconditioning with diag(A).
+// A is symmetric positive definite; Jacobi preconditioning with diag(A), z = M^-1 r = md r.
+//
+// Stored vectors: y, p, q = A p (kept by recurrence) and u = s z in the zero-haloed layout the
+// stencil reads.  The residual is not stored: where s != 0, r = u / (s md) and z = u / s.
+// The update y += alpha_it p_it is applied by the next iteration's first kernel, which reads
+// p_it anyway; the solve ends with one more such pass.
 //
 // Reductions: every block writes its partial sums; a one-block kernel per right-hand side adds
-// them in block order and stores the scalars, so the results do not depend on scheduling.
+// them in block order and stores the scalars, so the results do not depend on scheduling.  The
+// same kernel takes the convergence test and keeps the status record, and the iteration kernels
+// read its outcome (CgScalars::conv) from the previous launch.
 __constant__ double c_K0[27 * 6];
 
 void upload_stencil(const double *K0_27x6)
@@ -504,8 +512,10 @@ void upload_stencil(const double *K0_27x6)
     MJ_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_K0), K0_27x6, sizeof(double) * 27 * 6));
 }
 
-// sum_{D} K_0(D) u(m - D) at haloed index ip (the halo of u is zero, so no bounds tests)
-__device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ u, long ip, double out[3])
+// sum_{D} K_0(D) u(m - D) at haloed index ip (the halo of u is zero, so no bounds tests);
+// ctr receives u(m) itself
+__device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ u, long ip, double out[3],
+                                     double ctr[3])
 {
     const long Mp = a.Mp;
     const long sy = a.U + 2, sz = (long)(a.U + 2) * (a.V + 2);
@@ -513,6 +523,9 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
     {
         const double *k = &c_K0[13 * 6];
         const double u0 = u[ip], u1 = u[Mp + ip], u2 = u[2 * Mp + ip];
+        ctr[0] = u0;
+        ctr[1] = u1;
+        ctr[2] = u2;
         acc0 = k[0] * u0 + k[3] * u1 + k[4] * u2;
         acc1 = k[3] * u0 + k[1] * u1 + k[5] * u2;
         acc2 = k[4] * u0 + k[5] * u1 + k[2] * u2;
@@ -566,39 +579,78 @@ __device__ inline void block_partials(const double (&v)[NV], double *part, int n
     }
 }
 
-// One block per right-hand side: dst[q] = sum_b part[q][b] in block order.
-__global__ void __launch_bounds__(1024) k_cg_reduce(const double *__restrict__ part, int nb, int nv,
-                                                    CgScalars *scal, int slot0, int slot1, int slot2)
+// One block per right-hand side adds the partials of one CG kernel in block order; the number
+// of sums tells which kernel wrote them:
+//   NV = 3 (k_cg_init): rz_0, r.r, b.b and the test at iteration 0
+//   NV = 1 (k_cg_a):    p.q
+//   NV = 2 (k_cg_b):    rz_{it+1}, r.r and the test at iteration it + 1
+// The test |r|^2 <= tol^2 |b|^2 (or b = 0) sets conv to the iteration that passed it.  The
+// host enqueues iterations in batches, so launches past the end of a solve are routine.
+template <int NV>
+__global__ void __launch_bounds__(1024) k_cg_reduce(CgArg a, int it)
 {
+    constexpr int kUnroll = 8;
     __shared__ double sm[16];
-    const int r = blockIdx.x;
-    const double *pr = part + (size_t)r * 3 * nb;
-    double *base = (double *)(scal + r);
-    const int slots[3] = {slot0, slot1, slot2};
-    for (int q = 0; q < nv; q++) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += pr[(size_t)q * nb + b];
-        acc = block_sum(acc, sm);
-        if (threadIdx.x == 0) base[slots[q]] = acc;
+    const int r = blockIdx.x, nb = a.nblk;
+    // k_cg_a and k_cg_b of iteration it wrote no partials once the solve ended at conv <= it;
+    // the scalars and the status stay as the end left them
+    if (NV != 3 && a.scal[r].conv <= it) return;
+    const double *pr = a.part + (size_t)r * 3 * nb;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) acc[q] = 0.0;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += kUnroll * 1024) {
+        double v[kUnroll][NV];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            const int b = b0 + j * 1024;
+#pragma unroll
+            for (int q = 0; q < NV; q++) v[j][q] = b < nb ? pr[(size_t)q * nb + b] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++)
+#pragma unroll
+            for (int q = 0; q < NV; q++) acc[q] += v[j][q];
     }
+#pragma unroll
+    for (int q = 0; q < NV; q++) acc[q] = block_sum(acc[q], sm);
+    if (threadIdx.x != 0) return;
+    CgScalars *sc = a.scal + r;
+    int iter;
+    if constexpr (NV == 1) {
+        sc->pq = acc[0];
+        return;
+    } else if constexpr (NV == 3) {
+        iter = 0;
+        sc->rz[0] = acc[0];
+        sc->rr = acc[1];
+        sc->bb = acc[2];
+    } else {
+        iter = it + 1;
+        sc->rz[iter & 1] = acc[0];
+        sc->rr = acc[1];
+    }
+    const double rr = sc->rr, bb = sc->bb;
+    const bool pass = rr <= a.tol2 * bb || bb == 0.0;
+    sc->conv = pass ? iter : INT_MAX;
+    a.stat[r] = CgStatus{pass ? 1 : 0, iter, bb > 0.0 ? sqrt(rr / bb) : 0.0, bb};
 }
 
-// r = rhs - A y0 (uy = s y0), u = s M^-1 r; scalars rz[0], rr, bb (z = M^-1 r is never stored)
+// r = rhs - A y0 (uy = s y0), u = s M^-1 r; partials rz, rr, bb
 __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
 {
     const int r = blockIdx.y;
     const long M = a.M, base = (long)r * 3 * M;
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};   // rz, rr, bb
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[r] = CgStatus{0, 0, 0.0, 0.0};
     if (i < M) {
         const double s = a.schi[i];
         const double md = a.inv_diag[i];
         double Ay[3] = {0.0, 0.0, 0.0};
         const long ip = haloed(a, i), bp = (long)r * 3 * a.Mp;
         if (s != 0.0) {
-            double Ku[3];
-            stencil_apply(a, a.uy + bp, ip, Ku);
+            double Ku[3], ctr[3];
+            stencil_apply(a, a.uy + bp, ip, Ku, ctr);
             const double c0 = a.c0[i];
             for (int c = 0; c < 3; c++) Ay[c] = c0 * a.y[base + c * M + i] - s * Ku[c];
         }
@@ -607,7 +659,6 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
             const double b = a.rhs[o];
             const double rv = s != 0.0 ? b - Ay[c] : 0.0;
             const double zv = md * rv;
-            a.r[o] = rv;
             a.u[bp + c * a.Mp + ip] = s * zv;
             v[0] += rv * zv;
             v[1] += rv * rv;
@@ -617,44 +668,44 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
     block_partials<3>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
 }
 
-// iteration it, first half: convergence test on r.r; beta = rz_it / rz_{it-1} (0 at it = 0);
-// w = A z;  p = z + beta p;  q = w + beta q;  scalar p.q
-__global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
+// Iteration it, first half: y += alpha_{it-1} p_{it-1};  then, unless the solve ends here,
+// beta = rz_it / rz_{it-1} (0 at it = 0);  w = A z;  p = z + beta p;  q = w + beta q;  partial p.q.
+// The solve ends here when the test passed at iteration it, or when finish is set (the host's
+// last pass); launches after that return at once.
+__global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it, int finish)
 {
     const int r = blockIdx.y;
-    CgScalars *sc = a.scal + r;
-    if (a.stat[r].done) return;
-    const double rr = sc->rr, bb = sc->bb;
-    if (rr <= a.tol2 * bb || bb == 0.0) {
-        // every block takes the same decision; block 0 records it
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.stat[r].done = 1;
-            a.stat[r].iters = it;
-            a.stat[r].res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-            a.stat[r].bb = bb;
-        }
-        return;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.stat[r].iters = it;
-        a.stat[r].res = sqrt(rr / bb);
-        a.stat[r].bb = bb;
-    }
+    const CgScalars *sc = a.scal + r;
+    const int conv = sc->conv;
+    if (conv < it) return;
+    const bool last = conv == it || finish;
+    if (last && it == 0) return;
+    // at it > 0: slot (it + 1) & 1 holds rz_{it-1}, pq holds p_{it-1}.q_{it-1}
+    const double alpha = it > 0 ? sc->rz[(it + 1) & 1] / sc->pq : 0.0;
     const double beta = it > 0 ? sc->rz[it & 1] / sc->rz[(it + 1) & 1] : 0.0;
     const long M = a.M, base = (long)r * 3 * M;
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (last) {
+        if (i < M && a.schi[i] != 0.0)
+            for (int c = 0; c < 3; c++) a.y[base + c * M + i] += alpha * a.p[base + c * M + i];
+        return;
+    }
     double v[1] = {0.0};
     if (i < M) {
         const double s = a.schi[i];
         if (s != 0.0) {
-            double Ku[3];
-            stencil_apply(a, a.u + (long)r * 3 * a.Mp, haloed(a, i), Ku);
-            const double c0 = a.c0[i], md = a.inv_diag[i];
+            double Ku[3], uc[3];
+            stencil_apply(a, a.u + (long)r * 3 * a.Mp, haloed(a, i), Ku, uc);
+            const double c0 = a.c0[i], inv_s = 1.0 / s;
             for (int c = 0; c < 3; c++) {
                 const long o = base + c * M + i;
-                const double zv = md * a.r[o];
-                // at it = 0, beta = 0 and p, q hold finite values of the previous solve
-                const double pv = zv + beta * a.p[o];
+                const double zv = uc[c] * inv_s;
+                // at it = 0, alpha = beta = 0 and p, q hold finite values of the previous solve
+                // (the update stays unconditional: a branch here makes the compiler duplicate
+                // the loop body)
+                const double po = a.p[o];
+                a.y[o] += alpha * po;
+                const double pv = zv + beta * po;
                 const double qv = (c0 * zv - s * Ku[c]) + beta * a.q[o];
                 a.p[o] = pv;
                 a.q[o] = qv;
@@ -665,13 +716,13 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it)
     block_partials<1>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
 }
 
-// second half: alpha = rz_it / p.q;  y += alpha p;  r -= alpha q;  u = s M^-1 r;
-// scalars rz_{it+1} (other slot) and r.r
+// second half: alpha = rz_it / p.q;  r -= alpha q, kept as u -= alpha s md q;  partials
+// rz_{it+1} and r.r
 __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
 {
     const int r = blockIdx.y;
-    CgScalars *sc = a.scal + r;
-    if (a.stat[r].done) return;
+    const CgScalars *sc = a.scal + r;
+    if (sc->conv <= it) return;
     const double alpha = sc->rz[it & 1] / sc->pq;
     const long M = a.M, base = (long)r * 3 * M;
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -680,15 +731,13 @@ __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
         const double s = a.schi[i];
         if (s != 0.0) {
             const double md = a.inv_diag[i];
+            const double f = s * md, inv_f = 1.0 / f;
             const long up = (long)r * 3 * a.Mp + haloed(a, i);
             for (int c = 0; c < 3; c++) {
-                const long o = base + c * M + i;
-                a.y[o] += alpha * a.p[o];
-                const double rv = a.r[o] - alpha * a.q[o];
-                const double zv = md * rv;
-                a.r[o] = rv;
-                a.u[up + c * a.Mp] = s * zv;
-                v[0] += rv * zv;
+                const double un = a.u[up + c * a.Mp] - alpha * f * a.q[base + c * M + i];
+                a.u[up + c * a.Mp] = un;
+                const double rv = un * inv_f;
+                v[0] += md * rv * rv;
                 v[1] += rv * rv;
             }
         }
@@ -712,29 +761,34 @@ __global__ void k_cg_finish(const double *__restrict__ y, const double *__restri
         }
 }
 
-// slot indices of CgScalars viewed as double[5]: rz[0], rz[1], pq, rr, bb
-static void launch_reduce(const CgArg &a, int nv, int s0, int s1, int s2, hipStream_t st)
+template <int NV>
+static void launch_reduce(const CgArg &a, int it, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_reduce, dim3(a.nrhs), dim3(1024), 0, st, a.part, a.nblk, nv, a.scal, s0, s1, s2);
+    hipLaunchKernelGGL(k_cg_reduce<NV>, dim3(a.nrhs), dim3(1024), 0, st, a, it);
     MJ_CHECK(hipGetLastError());
 }
 void launch_cg_init(const CgArg &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_init, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a);
     MJ_CHECK(hipGetLastError());
-    launch_reduce(a, 3, 0, 3, 4, st);            // rz[0], rr, bb
+    launch_reduce<3>(a, 0, st);
 }
 void launch_cg_a(const CgArg &a, int it, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_a, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a, it);
+    hipLaunchKernelGGL(k_cg_a, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a, it, 0);
     MJ_CHECK(hipGetLastError());
-    launch_reduce(a, 1, 2, 2, 2, st);            // pq
+    launch_reduce<1>(a, it, st);
 }
 void launch_cg_b(const CgArg &a, int it, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_b, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a, it);
     MJ_CHECK(hipGetLastError());
-    launch_reduce(a, 2, (it + 1) & 1, 3, 3, st); // rz[(it+1)&1], rr
+    launch_reduce<2>(a, it, st);
+}
+void launch_cg_end(const CgArg &a, int it, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_a, dim3(a.nblk, a.nrhs), dim3(256), 0, st, a, it, 1);
+    MJ_CHECK(hipGetLastError());
 }
 void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, double *J, double *Jout,
                       hipStream_t st)

@@ -236,6 +236,34 @@ def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb):
         assert e_oracle <= 1e-8
 
 
+def test_batched_rhs_with_a_zero_column(torch_cuda):
+    """A batch whose first right-hand side is identically zero: its Z_0 solve ends at the
+    initial test in every step while the second one iterates, so the batched iterations run
+    past the end of the first solve.  The zero column stays exactly zero (no update may
+    follow the end of a solve) and the other one matches the oracle."""
+    import dataclasses
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n = 6, 5, 4, 40
+    say("batched rhs with a zero column 6x5x4")
+    eps = wl.random_eps(U, V, W, 7, 1.0, 8.0)
+    w1 = _three_waves(U, V, W)[0]
+    waves = [dataclasses.replace(w1, amp=0.0), w1]
+    fir = wl.binomial_highpass(5, 0.1)
+    s = make_solver(wl.Problem("zero column", U, V, W, eps, waves, n, fir=fir), time_block=8)
+    J = torch.zeros((n, 2, 3, W, V, U), dtype=torch.float64, device="cuda")
+    s.run(n, J)
+    torch.cuda.synchronize()
+    J = J.cpu().numpy()
+    s.close()
+    assert np.all(J[:, 0] == 0.0)
+    p1 = wl.Problem("single", U, V, W, eps, [w1], n, fir=fir)
+    ref = mot.Oracle(p1, K=oracle_kernel_table(U, V, W, mot.ell(U, V, W))).run(n)
+    e = _rel(J[:, 1], ref)
+    say("  nonzero column vs oracle", e)
+    assert e <= 1e-8
+
+
 # ----------------------------------------------------------------------------- probes
 def test_probes_match_oracle(torch_cuda):
     """Scattered field at probe points (a Fibonacci sphere around the block, plus two points
