@@ -66,7 +66,7 @@ struct mj_solver {
     // device state
     size_t bytes = 0;
     std::vector<void *> allocs;
-    double *chi = nullptr, *schi = nullptr, *inv_eps = nullptr, *c0 = nullptr, *inv_diag = nullptr;
+    double *chi = nullptr, *schi = nullptr, *inv_eps = nullptr, *c0 = nullptr;
     double *fir_d = nullptr;
     double *Khat = nullptr;
     double2 *ring = nullptr, *Shat = nullptr, *farbuf = nullptr;
@@ -213,7 +213,6 @@ void mj_solver::create(const mj_config &c)
     schi = dalloc<double>(M, "sqrt chi");
     inv_eps = dalloc<double>(M, "1/eps");
     c0 = dalloc<double>(M, "c0");
-    inv_diag = dalloc<double>(M, "Jacobi");
     fir_d = dalloc<double>(std::max<size_t>(fir.size(), 1), "fir");
     if (!fir.empty()) MJ_CHECK(hipMemcpy(fir_d, fir.data(), fir.size() * 8, hipMemcpyHostToDevice));
 
@@ -259,22 +258,18 @@ void mj_solver::set_material(const double *eps)
     for (long i = 0; i < M; i++)
         if (!(eps[i] >= 1.0) || !std::isfinite(eps[i])) throw ArgError("eps_r must be finite and >= 1");
     eps_h.assign(eps, eps + M);
-    std::vector<double> chi_h(M), schi_h(M), ie_h(M), c0_h(M), idg(M);
+    std::vector<double> chi_h(M), schi_h(M), ie_h(M), c0_h(M);
     const double d0 = fir.empty() ? 0.0 : fir[0];
-    const double k0self = K0_27[13 * 6 + 0];
     for (long i = 0; i < M; i++) {
         chi_h[i] = (eps[i] - 1.0) / eps[i];
         schi_h[i] = std::sqrt(chi_h[i]);
         ie_h[i] = 1.0 / eps[i];
         c0_h[i] = 0.5 * ie_h[i] + d0;   // T(0)/eps + delta_0
-        const double d = c0_h[i] - chi_h[i] * k0self;
-        idg[i] = chi_h[i] > 0.0 ? 1.0 / d : 0.0;
     }
     MJ_CHECK(hipMemcpy(chi, chi_h.data(), M * 8, hipMemcpyHostToDevice));
     MJ_CHECK(hipMemcpy(schi, schi_h.data(), M * 8, hipMemcpyHostToDevice));
     MJ_CHECK(hipMemcpy(inv_eps, ie_h.data(), M * 8, hipMemcpyHostToDevice));
     MJ_CHECK(hipMemcpy(c0, c0_h.data(), M * 8, hipMemcpyHostToDevice));
-    MJ_CHECK(hipMemcpy(inv_diag, idg.data(), M * 8, hipMemcpyHostToDevice));
 }
 
 void mj_solver::build_spectra()
@@ -365,8 +360,8 @@ void mj_solver::solve_z0()
     a.nblk = nblk;
     a.tol2 = cg_rtol * cg_rtol;
     a.schi = schi;
-    a.c0 = c0;
-    a.inv_diag = inv_diag;
+    a.d0 = fir.empty() ? 0.0 : fir[0];
+    a.k0c = K0_27[13 * 6 + 0];
     a.rhs = rhs;
     a.uy = uy;
     a.y = y;

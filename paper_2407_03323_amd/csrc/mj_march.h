@@ -100,7 +100,8 @@ struct CgArg {
     long Mp;                 // (U+2)(V+2)(W+2): vectors read by the stencil carry a zero halo
     int nrhs, nblk;          // nblk = ceil(M / 256): one voxel per thread
     double tol2;
-    const double *schi, *c0, *inv_diag;
+    double d0, k0c;          // delta_0 and K_0^{xx}(0): c_0 and diag(A) follow from sqrt(chi)
+    const double *schi;
     const double *rhs, *uy;  // uy, u: haloed layout [nrhs][3][Mp]
     double *y, *p, *q, *u;   // u = sqrt(chi) M^-1 r stands for the residual r
     double *part;            // [nrhs][3][nblk]

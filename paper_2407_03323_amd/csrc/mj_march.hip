@@ -548,6 +548,12 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
     out[2] = acc2;
 }
 
+// c_0 = T(0)/eps + delta_0 with T(0) = 1/2 and 1/eps = 1 - chi, and the Jacobi weight
+// 1 / (c_0 - chi K_0^{xx}(0)), both from s = sqrt(chi) (the diagonal of K_0 at D = 0 is
+// isotropic for a cube): two coefficient streams fewer per pass
+__device__ inline double cg_c0(const CgArg &a, double s) { return 0.5 * (1.0 - s * s) + a.d0; }
+__device__ inline double cg_md(const CgArg &a, double s, double c0) { return 1.0 / (c0 - s * s * a.k0c); }
+
 __device__ inline long haloed(const CgArg &a, long i)
 {
     const int x = (int)(i % a.U), y = (int)((i / a.U) % a.V), z = (int)(i / ((long)a.U * a.V));
@@ -645,13 +651,13 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
     double v[3] = {0.0, 0.0, 0.0};   // rz, rr, bb
     if (i < M) {
         const double s = a.schi[i];
-        const double md = a.inv_diag[i];
+        const double c0 = cg_c0(a, s);
+        const double md = s != 0.0 ? cg_md(a, s, c0) : 0.0;
         double Ay[3] = {0.0, 0.0, 0.0};
         const long ip = haloed(a, i), bp = (long)r * 3 * a.Mp;
         if (s != 0.0) {
             double Ku[3], ctr[3];
             stencil_apply(a, a.uy + bp, ip, Ku, ctr);
-            const double c0 = a.c0[i];
             for (int c = 0; c < 3; c++) Ay[c] = c0 * a.y[base + c * M + i] - s * Ku[c];
         }
         for (int c = 0; c < 3; c++) {
@@ -696,7 +702,7 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it, int finish)
         if (s != 0.0) {
             double Ku[3], uc[3];
             stencil_apply(a, a.u + (long)r * 3 * a.Mp, haloed(a, i), Ku, uc);
-            const double c0 = a.c0[i], inv_s = 1.0 / s;
+            const double c0 = cg_c0(a, s), inv_s = 1.0 / s;
             for (int c = 0; c < 3; c++) {
                 const long o = base + c * M + i;
                 const double zv = uc[c] * inv_s;
@@ -730,7 +736,7 @@ __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
     if (i < M) {
         const double s = a.schi[i];
         if (s != 0.0) {
-            const double md = a.inv_diag[i];
+            const double md = cg_md(a, s, cg_c0(a, s));
             const double f = s * md, inv_f = 1.0 / f;
             const long up = (long)r * 3 * a.Mp + haloed(a, i);
             for (int c = 0; c < 3; c++) {
