@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
     double2 *tw_s = sm;
     double2 *a = sm + N;
     load_twiddles(tw_s, tw, N);
-    const int row0 = blockIdx.x * (2 * P);
+    const int row0 = (int)xcd_block(blockIdx.x, gridDim.x) * (2 * P);
     // load: pencil p takes rows row0 + 2p (real part) and row0 + 2p + 1 (imaginary part)
     for (int i = threadIdx.x; i < P * N; i += blockDim.x) {
         int p = i / N, n = i - p * N;
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
     double2 *tw_s = sm;
     double2 *a = sm + N;
     load_twiddles(tw_s, tw, N);
-    const int row0 = blockIdx.x * (2 * P);
+    const int row0 = (int)xcd_block(blockIdx.x, gridDim.x) * (2 * P);
     // Z[k] = Xa[k] + i Xb[k] for k <= N/2, Z[N-k] = conj(Xa[k]) + i conj(Xb[k]) for 0 < k < N/2
     gather_tile<double4>(
         P * N,
@@ -328,8 +328,9 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restr
     double2 *a = sm + N;
     load_twiddles(tw_s, tw, N);
     const int ntile = (g.Hx + P - 1) / P;
-    const int tile = blockIdx.x % ntile;
-    const int grp = blockIdx.x / ntile;
+    const int lb = (int)xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles share row ends
+    const int tile = lb % ntile;
+    const int grp = lb / ntile;
     const int c = grp / g.nq, q = grp - c * g.nq;
     const int kx0 = tile * P;
     const int np = min(P, g.Hx - kx0);

@@ -39,6 +39,19 @@ __host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_doub
 __host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// ---------------------------------------------------------------------------- XCD order
+// The chip hands workgroups to its 8 XCDs in turn (dispatch index b to XCD b mod 8), and every
+// XCD has its own L2.  Tiles that share cache lines (the ends of unaligned rows, the planes a
+// stencil reads) should meet in one L2, so kernels take their tile from
+// xcd_block(b, n): XCD x works on the contiguous range of logical indices that starts at
+// x q + min(x, n mod 8) (q = n / 8), in dispatch order.  A bijection of [0, n).
+constexpr unsigned kXcds = 8;
+__device__ inline unsigned xcd_block(unsigned b, unsigned n)
+{
+    const unsigned q = n / kXcds, rem = n % kXcds, x = b % kXcds, j = b / kXcds;
+    return x * q + (x < rem ? x : rem) + j;
+}
+
 // ---------------------------------------------------------------------------- FFT plan
 constexpr int kMaxStages = 12;
 constexpr int kMaxFftN = 512;

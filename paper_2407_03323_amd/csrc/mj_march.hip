@@ -206,8 +206,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int g = lane / kLanesPerGroup, li = lane % kLanesPerGroup;
     // the right-hand sides of one point group are adjacent blocks, so the kernel values they
     // share are read from HBM once and hit in cache for the others
-    const int r = blockIdx.x % a.nrhs;
-    const long o = (blockIdx.x / a.nrhs) * (long)kPointsPerWave + (li >> 1);
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int r = lb % a.nrhs;
+    const long o = (lb / a.nrhs) * (long)kPointsPerWave + (li >> 1);
     const int part = li & 1;
     const int m = threadIdx.x >> 6;
     if (o >= nocts) return;
@@ -326,9 +327,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 // near part of step n = n_b + t, accumulated in place into F[t]
 __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 {
-    const MirrorPoint mp = mirror_point(a.Hx, a.Hp, a.Ny, a.Nz, blockIdx.x / a.nrhs);
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const MirrorPoint mp = mirror_point(a.Hx, a.Hp, a.Ny, a.Nz, lb / a.nrhs);
     if (!mp.valid) return;
-    const int r = blockIdx.x % a.nrhs;
+    const int r = lb % a.nrhs;
     const long plane = (long)a.Nz * a.Ny * a.Hp;
     const long koct = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     const int t = a.t;
@@ -573,16 +575,28 @@ __device__ inline double block_sum(double v, double *sm)
     return t;   // valid in thread 0
 }
 
-// Stores this block's NV partial sums (every thread calls it).
+// Stores the NV partial sums of logical block bx (every thread calls it).
 template <int NV>
-__device__ inline void block_partials(const double (&v)[NV], double *part, int nb)
+__device__ inline void block_partials(const double (&v)[NV], double *part, int nb, int bx)
 {
     __shared__ double sm[8];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
         const double t = block_sum(v[q], sm);
-        if (threadIdx.x == 0) part[(size_t)q * nb + blockIdx.x] = t;
+        if (threadIdx.x == 0) part[(size_t)q * nb + bx] = t;
     }
+}
+
+// Logical (block, right-hand side) of a CG kernel on the grid (nblk, nrhs), in XCD order over
+// the linear dispatch index, so that the blocks holding neighbouring planes of the stencil
+// input share an L2.
+struct CgBlock {
+    int bx, r;
+};
+__device__ inline CgBlock cg_block()
+{
+    const unsigned lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    return CgBlock{(int)(lb % gridDim.x), (int)(lb / gridDim.x)};
 }
 
 // One block per right-hand side adds the partials of one CG kernel in block order; the number
@@ -645,9 +659,10 @@ __global__ void __launch_bounds__(1024) k_cg_reduce(CgArg a, int it)
 // r = rhs - A y0 (uy = s y0), u = s M^-1 r; partials rz, rr, bb
 __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
 {
-    const int r = blockIdx.y;
+    const CgBlock cb = cg_block();
+    const int r = cb.r;
     const long M = a.M, base = (long)r * 3 * M;
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long i = cb.bx * (long)blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};   // rz, rr, bb
     if (i < M) {
         const double s = a.schi[i];
@@ -671,7 +686,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
             v[2] += b * b;
         }
     }
-    block_partials<3>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
+    block_partials<3>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x, cb.bx);
 }
 
 // Iteration it, first half: y += alpha_{it-1} p_{it-1};  then, unless the solve ends here,
@@ -680,7 +695,8 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArg a)
 // last pass); launches after that return at once.
 __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it, int finish)
 {
-    const int r = blockIdx.y;
+    const CgBlock cb = cg_block();
+    const int r = cb.r;
     const CgScalars *sc = a.scal + r;
     const int conv = sc->conv;
     if (conv < it) return;
@@ -690,7 +706,7 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it, int finish)
     const double alpha = it > 0 ? sc->rz[(it + 1) & 1] / sc->pq : 0.0;
     const double beta = it > 0 ? sc->rz[it & 1] / sc->rz[(it + 1) & 1] : 0.0;
     const long M = a.M, base = (long)r * 3 * M;
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long i = cb.bx * (long)blockDim.x + threadIdx.x;
     if (last) {
         if (i < M && a.schi[i] != 0.0)
             for (int c = 0; c < 3; c++) a.y[base + c * M + i] += alpha * a.p[base + c * M + i];
@@ -719,19 +735,20 @@ __global__ void __launch_bounds__(256) k_cg_a(CgArg a, int it, int finish)
             }
         }
     }
-    block_partials<1>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
+    block_partials<1>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x, cb.bx);
 }
 
 // second half: alpha = rz_it / p.q;  r -= alpha q, kept as u -= alpha s md q;  partials
 // rz_{it+1} and r.r
 __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
 {
-    const int r = blockIdx.y;
+    const CgBlock cb = cg_block();
+    const int r = cb.r;
     const CgScalars *sc = a.scal + r;
     if (sc->conv <= it) return;
     const double alpha = sc->rz[it & 1] / sc->pq;
     const long M = a.M, base = (long)r * 3 * M;
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long i = cb.bx * (long)blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (i < M) {
         const double s = a.schi[i];
@@ -748,7 +765,7 @@ __global__ void __launch_bounds__(256) k_cg_b(CgArg a, int it)
             }
         }
     }
-    block_partials<2>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x);
+    block_partials<2>(v, a.part + (size_t)r * 3 * gridDim.x, gridDim.x, cb.bx);
 }
 
 // J_n = sqrt(chi) y into the real-space ring (and optionally the caller's output)
