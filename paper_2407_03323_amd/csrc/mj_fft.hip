@@ -37,6 +37,12 @@ __device__ inline double2 tw_at(const double2 *tw, int m, bool inv)
     return inv ? make_double2(w.x, -w.y) : w;
 }
 
+// cos(2 pi m / R) and sin(2 pi m / R), m = 1 .. (R-1)/2, of the odd radices, interleaved, from
+// offset odd_base(R).  They are the same for every N, so they sit in constant memory, where the
+// compiler keeps them in scalar registers.
+__constant__ double c_odd_cs[2 * (1 + 2 + 3 + 5 + 6)];
+constexpr int odd_base(int R) { return R == 3 ? 0 : R == 5 ? 2 : R == 7 ? 6 : R == 11 ? 12 : 22; }
+
 // In-register R-point DFT, v[q] <- sum_t v[t] W_R^{q t} (W_R = exp(-+2 pi i / R)).
 template <int R>
 __device__ inline void dft_small(double2 *v, const double2 *tw, int N, bool inv)
@@ -62,13 +68,11 @@ __device__ inline void dft_small(double2 *v, const double2 *tw, int N, bool inv)
         //   out_{R-q} = v_0 + sum_t a_t c_{qt} - i sg sum_t b_t s_{qt}     (q, t = 1 .. (R-1)/2)
         static_assert(R % 2 == 1, "even radices other than 2 and 4 are not used");
         constexpr int H = (R - 1) / 2;
-        const int st = N / R;
         double cm[H + 1], sm[H + 1];
 #pragma unroll
         for (int m = 1; m <= H; m++) {
-            const double2 w = tw[m * st];   // exp(-2 pi i m / R)
-            cm[m] = w.x;
-            sm[m] = -w.y;
+            cm[m] = c_odd_cs[odd_base(R) + 2 * (m - 1)];
+            sm[m] = c_odd_cs[odd_base(R) + 2 * (m - 1) + 1];
         }
         double2 a[H + 1], b[H + 1];
         double2 sum = v[0];
@@ -104,7 +108,7 @@ __device__ inline void dft_small(double2 *v, const double2 *tw, int N, bool inv)
 }
 
 // A tile holds at most kTileElems complex values (P pencils of length N, P * N <= kTileElems).
-constexpr int kTileElems = 2048;
+constexpr int kTileElems = 3072;
 static_assert(kMaxFftN <= kTileElems, "one pencil must fit a tile");
 
 // One Stockham stage, in place, on P pencils of length N stored with leading dimension ld.
@@ -410,6 +414,16 @@ void fft_plan_init(FftPlan1D &p, int N)
     }
     MJ_CHECK(hipMalloc(&p.tw, sizeof(double2) * N));
     MJ_CHECK(hipMemcpy(p.tw, h.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
+    // the odd-radix constants, rounded the same way (cheap; repeated for every plan so that
+    // the device current at plan creation has them)
+    double cs[2 * (1 + 2 + 3 + 5 + 6)];
+    for (int R : {3, 5, 7, 11, 13})
+        for (int m = 1; m <= (R - 1) / 2; m++) {
+            long double ang = 2.0L * pi * (long double)m / (long double)R;
+            cs[odd_base(R) + 2 * (m - 1)] = (double)cosl(ang);
+            cs[odd_base(R) + 2 * (m - 1) + 1] = (double)sinl(ang);
+        }
+    MJ_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_odd_cs), cs, sizeof(cs)));
 }
 
 void fft_plan_free(FftPlan1D &p)
