@@ -268,6 +268,7 @@ def main():
                    "phase_ms": {k: round(st[k], 4) for k in ("fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms",
                                                               "z0_ms")},
                    "cg_iters": round(st["cg_iters"], 2), "time_block": B,
+                   "fft_pencils": [info["fft_pencils_x"], info["fft_pencils_y"], info["fft_pencils_z"]],
                    "far_launch_ms": round(st["far_launch_ms"], 4), "near_launch_ms": round(st["near_launch_ms"], 4)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

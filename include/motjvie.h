@@ -68,6 +68,9 @@ typedef struct {
     int32_t time_block;       /* steps per time block of the history MAC: 1 (none), 4, 8, 16 or 32; 0 selects the default */
     void *stream;             /* hipStream_t to enqueue on; NULL = the null stream */
     int32_t quad_order;       /* Gauss-Legendre points per cell of the kernel quadrature; 0 selects 16 */
+    int32_t fft_pencils;      /* pencils per block of the FFT passes: 0 = pick per pass by timing at
+                                 mj_create; > 0 = at most this many (capped by what one LDS tile holds).
+                                 The transforms are bit-identical for every choice. < 0: MJ_EINVAL */
 } mj_config;
 
 /*
@@ -87,12 +90,13 @@ void mj_destroy(mj_solver *s);
 const char *mj_last_error(const mj_solver *s);
 
 /*
- * mj_info -- sizes of the solver.  out (host, n entries used, n <= 16):
+ * mj_info -- sizes of the solver.  out (host, n entries used, n <= 19):
  *   [0] ell  [1] Nx [2] Ny [3] Nz (padded FFT sizes)  [4] time block B
  *   [5] history depth kept in real space  [6] n_rhs  [7] current step n
  *   [8] device bytes allocated  [9] kernel generation time (ms)  [10] spectra time (ms)
  *   [11] number of FIR taps  [12] probes  [13] lag window per probe pair
  *   [14] probe pairs  [15] probe kernel generation time (ms)
+ *   [16] [17] [18] pencils per block of the x, y and z FFT passes
  */
 int mj_info(const mj_solver *s, double *out, int32_t n);
 

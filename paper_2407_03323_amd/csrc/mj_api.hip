@@ -176,6 +176,7 @@ void mj_solver::create(const mj_config &c)
     if (c.n_fir < 0 || (c.n_fir > 0 && !c.fir)) throw ArgError("bad FIR taps");
     if (c.n_fir > mj::kMaxLocal) throw ArgError("at most 64 FIR taps");
     if (c.n_rhs < 1 || c.n_rhs > 64) throw ArgError("n_rhs must be in [1, 64]");
+    if (c.fft_pencils < 0) throw ArgError("fft_pencils must be >= 0 (0: autotune)");
     U = c.U;
     V = c.V;
     W = c.W;
@@ -247,6 +248,8 @@ void mj_solver::create(const mj_config &c)
     MJ_CHECK(hipHostMalloc((void **)&cgstat_h, sizeof(mj::CgStatus) * nrhs, hipHostMallocDefault));
     mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz);
     bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hp + (size_t)3 * nrhs * W * Ny * Hp);
+    if (c.fft_pencils > 0) mj::fft3d_set_pencils(fft, c.fft_pencils);
+    else mj::fft3d_autotune(fft, st);
     n = 0;
     MJ_CHECK(hipStreamSynchronize(st));
 }
@@ -1078,11 +1081,11 @@ const char *mj_last_error(const mj_solver *s) { return s ? s->err.c_str() : g_er
 int mj_info(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    double v[16] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
+    double v[19] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
                     (double)s->rdepth, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
                     s->t_spec_ms, (double)s->fir.size(), (double)s->np, (double)s->nw, (double)s->npairs,
-                    s->t_probe_ms};
-    for (int i = 0; i < n && i < 16; i++) out[i] = v[i];
+                    s->t_probe_ms, (double)s->fft.Px, (double)s->fft.Py, (double)s->fft.Pz};
+    for (int i = 0; i < n && i < 19; i++) out[i] = v[i];
     return MJ_OK;
 }
 

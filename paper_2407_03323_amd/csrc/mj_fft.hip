@@ -442,6 +442,7 @@ void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz
     fft_plan_init(f.px, Nx);
     fft_plan_init(f.py, Ny);
     fft_plan_init(f.pz, Nz);
+    fft3d_set_pencils(f, 1 << 30);
     size_t na = (size_t)ncomp * W * V * f.Hp, nb = (size_t)ncomp * W * Ny * f.Hp;
     if (hipMalloc(&f.bufA, sizeof(double2) * na) != hipSuccess) throw MemError("FFT scratch A");
     if (hipMalloc(&f.bufB, sizeof(double2) * nb) != hipSuccess) throw MemError("FFT scratch B");
@@ -490,9 +491,8 @@ static int plan_mask(const FftPlan1D &p)
     } while (0)
 
 static void launch_strided(const double2 *in, double2 *out, const StridedArg &g, int ncomp, const FftPlan1D &p,
-                           bool inv, hipStream_t st)
+                           int P, bool inv, hipStream_t st)
 {
-    int P = pencils_per_block(p.N);
     int ntile = (g.Hx + P - 1) / P;
     dim3 grid(ncomp * g.nq * ntile);
     MJ_FFT_DISPATCH(plan_mask(p), k_fft_strided, grid, dim3(kThreads), lds_bytes(p.N, P), st, in, out, g,
@@ -500,68 +500,163 @@ static void launch_strided(const double2 *in, double2 *out, const StridedArg &g,
     MJ_CHECK(hipGetLastError());
 }
 
+// The six passes; P is the number of pencils per block of the pass (x: 2P real rows).
+// x pass forward: rows (c, w, v) of U reals -> A[c][w][v][kx]
+static void pass_x_fwd(const Fft3D &f, int ncomp, const double *x, int P, hipStream_t st)
+{
+    const int nrows = ncomp * f.W * f.V;
+    dim3 grid((nrows + 2 * P - 1) / (2 * P));
+    MJ_FFT_DISPATCH(plan_mask(f.px), k_fft_x_fwd, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, x, f.bufA, nrows,
+                    f.U, f.Hx, f.Hp, plan_arg(f.px), f.px.tw, P);
+    MJ_CHECK(hipGetLastError());
+}
+// y pass forward: groups (c, w); A[c][w][v][kx] -> B[c][w][ky][kx]
+static void pass_y_fwd(const Fft3D &f, int ncomp, int P, hipStream_t st)
+{
+    StridedArg g{};
+    g.nq = f.W; g.Hx = f.Hx;
+    g.cs_in = (long)f.W * f.V * f.Hp; g.qs_in = (long)f.V * f.Hp; g.es_in = f.Hp;
+    g.cs_out = (long)f.W * f.Ny * f.Hp; g.qs_out = (long)f.Ny * f.Hp; g.es_out = f.Hp;
+    g.n_in = f.V; g.n_out = f.Ny;
+    launch_strided(f.bufA, f.bufB, g, ncomp, f.py, P, false, st);
+}
+// z pass forward: groups (c, ky); B[c][w][ky][kx] -> X[c][kz][ky][kx]
+static void pass_z_fwd(const Fft3D &f, int ncomp, double2 *X, int P, hipStream_t st)
+{
+    StridedArg g{};
+    g.nq = f.Ny; g.Hx = f.Hx;
+    g.cs_in = (long)f.W * f.Ny * f.Hp; g.qs_in = f.Hp; g.es_in = (long)f.Ny * f.Hp;
+    g.cs_out = (long)f.Nz * f.Ny * f.Hp; g.qs_out = f.Hp; g.es_out = (long)f.Ny * f.Hp;
+    g.n_in = f.W; g.n_out = f.Nz;
+    launch_strided(f.bufB, X, g, ncomp, f.pz, P, false, st);
+}
+// z pass inverse: X[c][kz][ky][kx] -> B[c][w][ky][kx], w < W
+static void pass_z_inv(const Fft3D &f, int ncomp, const double2 *X, int P, hipStream_t st)
+{
+    StridedArg g{};
+    g.nq = f.Ny; g.Hx = f.Hx;
+    g.cs_in = (long)f.Nz * f.Ny * f.Hp; g.qs_in = f.Hp; g.es_in = (long)f.Ny * f.Hp;
+    g.cs_out = (long)f.W * f.Ny * f.Hp; g.qs_out = f.Hp; g.es_out = (long)f.Ny * f.Hp;
+    g.n_in = f.Nz; g.n_out = f.W;
+    launch_strided(X, f.bufB, g, ncomp, f.pz, P, true, st);
+}
+// y pass inverse: B[c][w][ky][kx] -> A[c][w][v][kx], v < V
+static void pass_y_inv(const Fft3D &f, int ncomp, int P, hipStream_t st)
+{
+    StridedArg g{};
+    g.nq = f.W; g.Hx = f.Hx;
+    g.cs_in = (long)f.W * f.Ny * f.Hp; g.qs_in = (long)f.Ny * f.Hp; g.es_in = f.Hp;
+    g.cs_out = (long)f.W * f.V * f.Hp; g.qs_out = (long)f.V * f.Hp; g.es_out = f.Hp;
+    g.n_in = f.Ny; g.n_out = f.V;
+    launch_strided(f.bufB, f.bufA, g, ncomp, f.py, P, true, st);
+}
+// x pass inverse: rows (c, w, v) of Hx -> U reals
+static void pass_x_inv(const Fft3D &f, int ncomp, double *y, int P, hipStream_t st)
+{
+    const int nrows = ncomp * f.W * f.V;
+    dim3 grid((nrows + 2 * P - 1) / (2 * P));
+    MJ_FFT_DISPATCH(plan_mask(f.px), k_fft_x_inv, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, f.bufA, y, nrows,
+                    f.U, f.Hx, f.Hp, plan_arg(f.px), f.px.tw, P);
+    MJ_CHECK(hipGetLastError());
+}
+
+// ncomp <= the plan's ncomp (the scratch buffers are sized for that)
 void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t st)
 {
-    const int U = f.U, V = f.V, W = f.W, Hx = f.Hx, Hp = f.Hp, Ny = f.Ny, Nz = f.Nz;
-    // x pass: rows (c, w, v)
-    {
-        int nrows = ncomp * W * V;
-        int P = pencils_per_block(f.Nx);
-        dim3 grid((nrows + 2 * P - 1) / (2 * P));
-        MJ_FFT_DISPATCH(plan_mask(f.px), k_fft_x_fwd, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, x, f.bufA, nrows,
-                        U, Hx, Hp, plan_arg(f.px), f.px.tw, P);
-        MJ_CHECK(hipGetLastError());
-    }
-    // y pass: groups (c, w); A[c][w][v][kx] -> B[c][w][ky][kx]
-    {
-        StridedArg g{};
-        g.nq = W; g.Hx = Hx;
-        g.cs_in = (long)W * V * Hp; g.qs_in = (long)V * Hp; g.es_in = Hp;
-        g.cs_out = (long)W * Ny * Hp; g.qs_out = (long)Ny * Hp; g.es_out = Hp;
-        g.n_in = V; g.n_out = Ny;
-        launch_strided(f.bufA, f.bufB, g, ncomp, f.py, false, st);
-    }
-    // z pass: groups (c, ky); B[c][w][ky][kx] -> X[c][kz][ky][kx]
-    {
-        StridedArg g{};
-        g.nq = Ny; g.Hx = Hx;
-        g.cs_in = (long)W * Ny * Hp; g.qs_in = Hp; g.es_in = (long)Ny * Hp;
-        g.cs_out = (long)Nz * Ny * Hp; g.qs_out = Hp; g.es_out = (long)Ny * Hp;
-        g.n_in = W; g.n_out = Nz;
-        launch_strided(f.bufB, X, g, ncomp, f.pz, false, st);
-    }
+    if (ncomp < 1 || ncomp > f.ncomp) throw std::logic_error("FFT batch larger than its plan");
+    pass_x_fwd(f, ncomp, x, f.Px, st);
+    pass_y_fwd(f, ncomp, f.Py, st);
+    pass_z_fwd(f, ncomp, X, f.Pz, st);
 }
 
 void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t st)
 {
-    const int U = f.U, V = f.V, W = f.W, Hx = f.Hx, Hp = f.Hp, Ny = f.Ny, Nz = f.Nz;
-    // z pass: X[c][kz][ky][kx] -> B[c][w][ky][kx], w < W
-    {
-        StridedArg g{};
-        g.nq = Ny; g.Hx = Hx;
-        g.cs_in = (long)Nz * Ny * Hp; g.qs_in = Hp; g.es_in = (long)Ny * Hp;
-        g.cs_out = (long)W * Ny * Hp; g.qs_out = Hp; g.es_out = (long)Ny * Hp;
-        g.n_in = Nz; g.n_out = W;
-        launch_strided(X, f.bufB, g, ncomp, f.pz, true, st);
+    if (ncomp < 1 || ncomp > f.ncomp) throw std::logic_error("FFT batch larger than its plan");
+    pass_z_inv(f, ncomp, X, f.Pz, st);
+    pass_y_inv(f, ncomp, f.Py, st);
+    pass_x_inv(f, ncomp, y, f.Px, st);
+}
+
+void fft3d_set_pencils(Fft3D &f, int cap)
+{
+    f.Px = std::max(1, std::min(cap, pencils_per_block(f.Nx)));
+    f.Py = std::max(1, std::min(cap, pencils_per_block(f.Ny)));
+    f.Pz = std::max(1, std::min(cap, pencils_per_block(f.Nz)));
+}
+
+// Picks the pencils per block of each axis pass by timing it.  A pencil's arithmetic does not
+// depend on how many pencils share its block, so every choice gives bit-identical transforms;
+// only the speed differs (row runs of the strided passes, blocks per compute unit).
+// Candidates: the most a tile holds, and 3/4, 1/2 and 1/4 of that; each pass forward and
+// inverse, best of three after one warm-up.
+void fft3d_autotune(Fft3D &f, hipStream_t st)
+{
+    const size_t nX = (size_t)f.ncomp * f.Nz * f.Ny * f.Hp;
+    double2 *X = nullptr;
+    if (hipMalloc(&X, sizeof(double2) * nX) != hipSuccess) {
+        (void)hipGetLastError();
+        throw MemError("FFT autotune scratch");
     }
-    // y pass: B[c][w][ky][kx] -> A[c][w][v][kx], v < V
-    {
-        StridedArg g{};
-        g.nq = W; g.Hx = Hx;
-        g.cs_in = (long)W * Ny * Hp; g.qs_in = (long)Ny * Hp; g.es_in = Hp;
-        g.cs_out = (long)W * V * Hp; g.qs_out = (long)V * Hp; g.es_out = Hp;
-        g.n_in = Ny; g.n_out = V;
-        launch_strided(f.bufB, f.bufA, g, ncomp, f.py, true, st);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        const size_t na = (size_t)f.ncomp * f.W * f.V * f.Hp, nb = (size_t)f.ncomp * f.W * f.Ny * f.Hp;
+        MJ_CHECK(hipMemsetAsync(X, 0, sizeof(double2) * nX, st));
+        MJ_CHECK(hipMemsetAsync(f.bufA, 0, sizeof(double2) * na, st));
+        MJ_CHECK(hipMemsetAsync(f.bufB, 0, sizeof(double2) * nb, st));
+        MJ_CHECK(hipEventCreate(&e0));
+        MJ_CHECK(hipEventCreate(&e1));
+        // bufB holds at least ncomp W V U reals: real input and output of the x pass
+        double *xr = (double *)f.bufB;
+        auto run = [&](int axis, int P) {
+            if (axis == 0) {
+                pass_x_fwd(f, f.ncomp, xr, P, st);
+                pass_x_inv(f, f.ncomp, xr, P, st);
+            } else if (axis == 1) {
+                pass_y_fwd(f, f.ncomp, P, st);
+                pass_y_inv(f, f.ncomp, P, st);
+            } else {
+                pass_z_fwd(f, f.ncomp, X, P, st);
+                pass_z_inv(f, f.ncomp, X, P, st);
+            }
+        };
+        const int Ns[3] = {f.Nx, f.Ny, f.Nz};
+        int *Ps[3] = {&f.Px, &f.Py, &f.Pz};
+        for (int axis = 0; axis < 3; axis++) {
+            const int pmax = pencils_per_block(Ns[axis]);
+            int cand[4] = {pmax, (3 * pmax) / 4, pmax / 2, pmax / 4};
+            float best = 0.0f;
+            int bestP = pmax;
+            for (int ci = 0; ci < 4; ci++) {
+                const int P = cand[ci];
+                if (P < 1 || (ci > 0 && std::find(cand, cand + ci, P) != cand + ci)) continue;
+                run(axis, P);
+                float tmin = 0.0f;
+                for (int rep = 0; rep < 3; rep++) {
+                    MJ_CHECK(hipEventRecord(e0, st));
+                    run(axis, P);
+                    MJ_CHECK(hipEventRecord(e1, st));
+                    MJ_CHECK(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    MJ_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep == 0 || ms < tmin) tmin = ms;
+                }
+                if (ci == 0 || tmin < best) {
+                    best = tmin;
+                    bestP = P;
+                }
+            }
+            *Ps[axis] = bestP;
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(X);
+        throw;
     }
-    // x pass: rows (c, w, v) of Hx -> U reals
-    {
-        int nrows = ncomp * W * V;
-        int P = pencils_per_block(f.Nx);
-        dim3 grid((nrows + 2 * P - 1) / (2 * P));
-        MJ_FFT_DISPATCH(plan_mask(f.px), k_fft_x_inv, grid, dim3(kThreads), lds_bytes(f.Nx, P), st, f.bufA, y, nrows,
-                        U, Hx, Hp, plan_arg(f.px), f.px.tw, P);
-        MJ_CHECK(hipGetLastError());
-    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(X);
 }
 
 }  // namespace mj

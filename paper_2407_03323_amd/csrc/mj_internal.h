@@ -82,10 +82,15 @@ struct Fft3D {
     // scratch: after the x pass [ncomp][W][V][Hp], after the y pass [ncomp][W][Ny][Hp]
     double2 *bufA = nullptr, *bufB = nullptr;
     int ncomp = 0;
+    int Px = 1, Py = 1, Pz = 1;  // pencils per block of the x, y and z passes
 };
 
 void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz);
 void fft3d_free(Fft3D &f);
+// pencils per block of every pass: at most cap, and at most what one tile holds
+void fft3d_set_pencils(Fft3D &f, int cap);
+// times the candidate pencil counts of each pass on the plan's own sizes and keeps the fastest
+void fft3d_autotune(Fft3D &f, hipStream_t st);
 // x: [ncomp][W][V][U] real; X: [ncomp][Nz][Ny][Hp] complex (unnormalised forward DFT of the zero-padded field)
 void fft3d_forward(Fft3D &f, const double *x, double2 *X, int ncomp, hipStream_t st);
 // X: [ncomp][Nz][Ny][Hp]; y: [ncomp][W][V][U] = unnormalised inverse DFT restricted to the box

@@ -37,6 +37,7 @@ class mj_config(ctypes.Structure):
         ("time_block", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("quad_order", ctypes.c_int32),
+        ("fft_pencils", ctypes.c_int32),
     ]
 
 
@@ -101,7 +102,7 @@ class Solver:
     """One MOT-JVIE march on the device (see include/motjvie.h for the exact semantics)."""
 
     def __init__(self, U, V, W, eps, fir=None, h=1.0, c_dt=None, n_rhs=1, cg_rtol=0.0, cg_maxit=0,
-                 time_block=0, quad_order=0, stream=None):
+                 time_block=0, quad_order=0, stream=None, fft_pencils=0):
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(W, V, U))
@@ -121,6 +122,7 @@ class Solver:
         cfg.time_block = int(time_block)
         cfg.stream = stream if stream is not None else _current_stream()
         cfg.quad_order = int(quad_order)
+        cfg.fft_pencils = int(fft_pencils)
         self._keep = (eps, fir)
         rc = self._lib.mj_create(ctypes.byref(cfg), ctypes.byref(self._h))
         if rc != MJ_OK:
@@ -143,10 +145,11 @@ class Solver:
             pass
 
     def info(self) -> dict:
-        out = np.zeros(16)
-        self._check(self._lib.mj_info(self._h, _dptr(out), 16))
+        out = np.zeros(19)
+        self._check(self._lib.mj_info(self._h, _dptr(out), 19))
         keys = ["ell", "Nx", "Ny", "Nz", "time_block", "real_depth", "n_rhs", "n", "device_bytes",
-                "gen_ms", "spectra_ms", "n_fir", "n_probes", "probe_window", "probe_pairs", "probe_gen_ms"]
+                "gen_ms", "spectra_ms", "n_fir", "n_probes", "probe_window", "probe_pairs", "probe_gen_ms",
+                "fft_pencils_x", "fft_pencils_y", "fft_pencils_z"]
         ms = ("gen_ms", "spectra_ms", "probe_gen_ms")
         return {k: (int(v) if k not in ms else float(v)) for k, v in zip(keys, out)}
 

@@ -52,7 +52,35 @@ def _cfg(U=4, eps=None, c_dt=1.0, fir=None, n_rhs=1):
     return c, eps
 
 
-@pytest.mark.parametrize("case", ["grid", "cdt", "eps", "rhs", "null"])
+def test_binding_config_matches_header():
+    """The ctypes mirror of mj_config lists the header's fields in the header's order, with
+    the same C types (the struct is passed by pointer, so a mismatch would shift every
+    field after it)."""
+    from paper_2407_03323_amd.motjvie import mj_config
+    src = open(os.path.join(ROOT, "include", "motjvie.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} mj_config;", src, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        m = re.match(r"(const )?(int32_t|double|void) (\*?)(.+)", decl)
+        assert m, decl
+        ctype = m.group(2) + ("*" if m.group(3) else "")
+        for name in m.group(4).split(","):
+            name = name.strip().lstrip("*")
+            fields.append((name, ctype if not name.startswith("*") else ctype + "*"))
+    want = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    assert [f[0] for f in fields] == [f[0] for f in mj_config._fields_]
+    for (name, ctype), (_, ct) in zip(fields, mj_config._fields_):
+        if ctype.endswith("*"):
+            assert ct is ctypes.c_void_p or issubclass(ct, ctypes._Pointer), name
+        else:
+            assert ct is want[ctype], name
+
+
+@pytest.mark.parametrize("case", ["grid", "cdt", "eps", "rhs", "pencils", "null"])
 def test_create_rejects_invalid_arguments(lib, case):
     from paper_2407_03323_amd.motjvie import MJ_EINVAL
     h = ctypes.c_void_p()
@@ -65,6 +93,9 @@ def test_create_rejects_invalid_arguments(lib, case):
         c, keep = _cfg(c_dt=0.5)
     elif case == "eps":
         c, keep = _cfg(eps=np.full(64, 0.5))
+    elif case == "pencils":
+        c, keep = _cfg()
+        c.fft_pencils = -1
     else:
         c, keep = _cfg(n_rhs=0)
     assert lib.mj_create(ctypes.byref(c), ctypes.byref(h)) == MJ_EINVAL

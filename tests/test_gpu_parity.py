@@ -61,6 +61,38 @@ def test_fft_matches_numpy(torch_cuda, UVW):
     s.close()
 
 
+def test_fft_pencils_per_block_do_not_change_results(torch_cuda):
+    """The pencils per FFT block (fixed caps 1, 2, 5, and the autotuned choice) only move
+    work between blocks: the round trip is bit-identical for every choice, and the autotuned
+    counts stay within what a tile holds."""
+    torch = torch_cuda
+    U, V, W = 11, 3, 12
+    say("fft pencils 11x3x12")
+    prob = wl.Problem("fft", U, V, W, np.full((W, V, U), 2.0), [], 1)
+    rng = np.random.default_rng(7)
+    xt = torch.tensor(rng.standard_normal((3, W, V, U)), dtype=torch.float64, device="cuda")
+    outs = []
+    for cap in (1, 2, 5, 0):
+        s = make_solver(prob, n_rhs=1, quad_order=8, fft_pencils=cap)
+        info = s.info()
+        Hx = info["Nx"] // 2 + 1
+        P = [info["fft_pencils_x"], info["fft_pencils_y"], info["fft_pencils_z"]]
+        say("  cap", cap, "pencils", P)
+        for p_, N in zip(P, (info["Nx"], info["Ny"], info["Nz"])):
+            assert 1 <= p_ <= max(1, min(16, 3072 // N))
+            if cap > 0:
+                assert p_ <= cap
+        Xt = torch.zeros((3, info["Nz"], info["Ny"], Hx, 2), dtype=torch.float64, device="cuda")
+        yt = torch.zeros_like(xt)
+        s.fft_roundtrip(xt, Xt, yt)
+        torch.cuda.synchronize()
+        outs.append((Xt.cpu().numpy(), yt.cpu().numpy()))
+        s.close()
+    for X, y in outs[1:]:
+        assert np.array_equal(X, outs[0][0])
+        assert np.array_equal(y, outs[0][1])
+
+
 # ----------------------------------------------------------------------------- generator
 def _all_offsets(U):
     r = np.arange(-(U - 1), U)
