@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64 (MFMA FP64 has the same peak)
 METRIC = "voxel·steps/s FP64 at 1.1M voxels; % HBM roofline; batched/adjoint vs plain"
 
 WORKLOADS = {
@@ -233,6 +234,12 @@ def main():
         launch_ms = st["mac_ms"]
         kname = "k_mac (history MAC, all lags every step)"
     achieved = bytes_launch / (launch_ms / 1e3) / 1e9
+    # FP64 work of the same launch: a real symmetric 3x3 times a complex 3-vector is 36 FLOP per
+    # (lag, half-spectrum point, target); target t of a block sums lags t + 1 .. ell
+    flop_launch = 36.0 * half * (sum(ell - t for t in range(B)) if B > 1 else ell)
+    tflops = flop_launch / (launch_ms / 1e3) / 1e12
+    fp64 = {"flop_per_launch": flop_launch, "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / FP64_PEAK_TFLOPS}
     traffic = mac_traffic(args.workload)
     # the whole FFT convolution of a step (forward FFT, far + near MAC, inverse FFT): algorithmic
     # bytes per step over the measured time of those three phases
@@ -273,7 +280,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "bytes_per_launch": bytes_launch,
-                     "avg_launch_ms": launch_ms, "convolution": conv},
+                     "avg_launch_ms": launch_ms, "fp64": fp64, "convolution": conv},
     }
     solver.close()
     del solver

@@ -14,11 +14,11 @@
  *     Z_0 J_n = E_n - P_{n-1},   P_{n-1} = sum_{k=1}^{ell} Z_k J_{n-k}
  * (eq:MOTInversion, eq:PnMOT), with the history sum evaluated by zero-padded 3-D
  * FFT convolution (Sec. 3, Appendix A) and the FIR regularisation
- * Z_k -> Z_k + delta_k I (Sec. 5.1) built in.
+ * Z_k -> Z_k + delta_k I (Sec. 6.1) built in.
  *
  * Conventions
  *  - Lengths in any unit; h is the voxel edge.  Times enter as c*t (same unit).
- *    This version requires c*dt == h (the paper's choice dt = dx/c, Sec. 3.3).
+ *    This version requires c*dt == h (the paper's choice dt = dx/c, Sec. 5.2).
  *  - Voxel index m = (w*V + v)*U + u, 0-based, x fastest (Sec. 2.2, 1-based there).
  *    Voxel (u,v,w) has its centre at ((u+1/2)h, (v+1/2)h, (w+1/2)h).
  *  - Vector fields are stored per component: F[a][w][v][u], a = x,y,z (the paper's
@@ -60,7 +60,7 @@ typedef struct {
     double h;                 /* voxel edge (> 0) */
     double c_dt;              /* c * dt; must equal h */
     const double *eps_r;      /* host [W][V][U], relative permittivity >= 1, finite */
-    const double *fir;        /* host taps delta_0..delta_{n_fir-1} (Sec. 5.1); may be NULL if n_fir == 0 */
+    const double *fir;        /* host taps delta_0..delta_{n_fir-1} (Sec. 6.1); may be NULL if n_fir == 0 */
     int32_t n_fir;            /* 0 = no regularisation */
     int32_t n_rhs;            /* number of right-hand sides (plane waves) marched together, >= 1 */
     double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-12 */
@@ -117,7 +117,7 @@ int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, cons
  *   Returns MJ_ENOCONV if a Z_0 solve missed cg_rtol (the march state stays consistent:
  *   J_n holds the last iterate).  Returns MJ_EUNSTABLE, and stops after that step, once the
  *   right-hand side of a Z_0 solve exceeds 1e100 in norm or is not finite: the unbounded
- *   growth of Sec. 5 (the alternating mode at f = 1/(2 dt)); mj_info entry 7 gives the step.
+ *   growth seen in Sec. 5.2 and analysed in Sec. 6 (the alternating mode at f = 1/(2 dt)); mj_info entry 7 gives the step.
  */
 int mj_run(mj_solver *s, int32_t n_steps, double *J_hist);
 

@@ -5,7 +5,7 @@ The FFT-free MOT-JVIE marched step by step exactly as Sec. 2.4 writes it:
     Z_0 J_n = E_n - P_{n-1},      P_{n-1} = sum_{k=1}^{ell} Z_k J_{n-k}      (eq:MOTInversion, eq:PnMOT)
 
 with the elements of eq:Z, the excitation of eq:E and the FIR regularisation
-Z_k -> Z_k + delta_k I of Sec. 5.1.  Z_0 is assembled as a sparse matrix and factorised
+Z_k -> Z_k + delta_k I of Sec. 6.1.  Z_0 is assembled as a sparse matrix and factorised
 directly (scipy's sparse LU); the history sum is the direct triple sum of direct.c.
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use it.
 
@@ -60,7 +60,7 @@ def chi_of(eps: np.ndarray) -> np.ndarray:
 
 def local_coefficients(eps: np.ndarray, fir: np.ndarray, kmax: int) -> np.ndarray:
     """c_k(m) = T(k dt)/eps_m + delta_k for k = 0..kmax: the identity part of Z_k
-    (eq:Z tested at its own voxel, with 1 - chi = 1/eps) plus the FIR tap (Sec. 5.1)."""
+    (eq:Z tested at its own voxel, with 1 - chi = 1/eps) plus the FIR tap (Sec. 6.1)."""
     c = np.zeros((kmax + 1,) + eps.shape)
     for k in range(kmax + 1):
         d = fir[k] if k < len(fir) else 0.0
@@ -157,7 +157,7 @@ def probe_field(Kp: np.ndarray, J: np.ndarray, sources) -> np.ndarray:
 
 
 def history_sum(K: np.ndarray, Jh: np.ndarray, eps: np.ndarray, fir: np.ndarray, ell_: int) -> np.ndarray:
-    """P_{n-1} = sum_{k>=1} Z^delta_k J_{n-k} (eq:PnMOT with Sec. 5.1's taps) for a history
+    """P_{n-1} = sum_{k>=1} Z^delta_k J_{n-k} (eq:PnMOT with Sec. 6.1's taps) for a history
     Jh[k-1] = J_{n-k}, k = 1..depth (missing lags count as zero currents):
       P = sum_k c_k J_{n-k} - chi * sum_{k=1}^{ell} K_k (*) J_{n-k}."""
     depth = Jh.shape[0]

@@ -563,7 +563,7 @@ void mj_solver::step(const StepIO &io)
     if (ev) MJ_CHECK(hipEventRecord(ev[6], st));
 }
 
-// The march grows without bound (Sec. 5: the alternating mode at f = 1/(2 dt)): stop once the
+// The march grows without bound (Sec. 5.2 and 6: the alternating mode at f = 1/(2 dt)): stop once the
 // right-hand side of a Z_0 solve leaves the finite range or passes 1e100 in norm.
 void mj_solver::check_growth() const
 {

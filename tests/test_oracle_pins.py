@@ -147,7 +147,7 @@ def test_symmetries():
 
 
 def test_support_and_stencil():
-    """Causality/Huygens support (Sec. 3.3): K_k(D) vanishes unless the lag window
+    """Causality/Huygens support (eq:Ell of Sec. 2.3; the leading zero blocks of Sec. 5.1): K_k(D) vanishes unless the lag window
     (k-2, k+1) c dt meets the distances between the two voxels; K_0 is the 27-point
     stencil when c dt = h; eq:Ell is the last lag reached by the farthest pair."""
     for D in [(0, 0, 0), (1, 1, 1), (2, 0, 0), (3, 2, 1), (7, 7, 7)]:

@@ -9,8 +9,8 @@ Units: lengths in voxel edges (h = 1), times as c*t in the same unit, so c*dt = 
 every configuration below.  Voxel (u, v, w) (0-based) has its centre at
 (u + 1/2, v + 1/2, w + 1/2) (Sec. 2.2) and index m = (w V + v) U + u.
 
-The configurations stand in for the paper's cube (eps_r = 12, Sec. 3.3 / 6.1) and
-sphere (Sec. 6.2) workloads; no public dataset is involved.
+The configurations stand in for the paper's cube (eps_r = 12, Sec. 5.2 / 7.1) and
+sphere (Sec. 7.2) workloads; no public dataset is involved.
 """
 from __future__ import annotations
 
