@@ -29,8 +29,8 @@ METRIC = "voxel·steps/s FP64 at 1.1M voxels; % HBM roofline; batched/adjoint vs
 
 WORKLOADS = {
     "C5": "104^3 cube of side 100h eps_r=12 in a 2-voxel eps_r=1 margin, c dt = h, x-pol +z Gaussian "
-          "plane wave sigma=8 dt delay 6 sigma, 17-tap binomial FIR delta=0.1125",
-    "C2": "32^3 sphere r=15h eps_r=12, c dt = h, x-pol +z Gaussian sigma=4 dt, 17-tap binomial FIR delta=0.1",
+          "plane wave sigma=8 dt delay 6 sigma, 17-tap binomial FIR delta=0.01",
+    "C2": "32^3 sphere r=15h eps_r=12, c dt = h, x-pol +z Gaussian sigma=4 dt, 17-tap binomial FIR delta=0.01",
     "C1": "8^3 cube eps_r=4, c dt = h, x-pol +z Gaussian sigma=4 dt, no FIR",
 }
 
