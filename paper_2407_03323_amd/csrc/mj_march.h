@@ -45,8 +45,10 @@ struct EpiArg {
     const double *chi, *schi, *inv_eps;
     const double *fir;       // device taps (nfir)
     int nfir;
-    int nloc;                // local history depth used (>= 5)
+    int nloc;                // local history depth used (>= nguess)
     int slot_of[kMaxLocal + 1];  // real-ring slot of J_{n-k}, k = 1..nloc
+    int nguess;              // the solve starts from sum_{k=1}^{nguess} gx[k-1] J_{n-k} (<= nloc)
+    double gx[kMaxLocal];    // extrapolation weights (the polynomial through nguess past steps)
     const double *Jring;     // [depth][nrhs][3][M]
     const double *S;         // [nrhs][3][M] convolution (normalised) or NULL at n = 1
     const WaveArg *waves;    // [nrhs]

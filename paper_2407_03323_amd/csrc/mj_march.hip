@@ -439,9 +439,8 @@ __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
     const double avg = wave_average(w, e, u, v, z, e.n * e.c_dt);
     const double c1 = 0.5 * e.inv_eps[i] + (e.nfir > 1 ? e.fir[1] : 0.0);
     const int kmax = min(e.nloc, e.n - 1);   // lags with a past current
-    // initial guess of the Z_0 solve: the quartic through the last five solutions (the
-    // current is smooth in time, so this lands close to y_n)
-    constexpr double cx[5] = {5.0, -10.0, 10.0, -5.0, 1.0};
+    // initial guess of the Z_0 solve: the polynomial through the last nguess solutions,
+    // evaluated at step n (the current is smooth in time, so this lands close to y_n)
     for (int c = 0; c < 3; c++) {
         const long o = ((long)r * 3 + c) * M + i;
         double b = chi * (avg * w.pol[c] + (e.S ? e.S[o] : 0.0));
@@ -451,7 +450,7 @@ __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
             const double jv = e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
             const double ck = (k == 1) ? c1 : (k < e.nfir ? e.fir[k] : 0.0);
             b -= ck * jv;
-            if (k <= 5) g += cx[k - 1] * jv;
+            if (k <= e.nguess) g += e.gx[k - 1] * jv;
         }
         const double y0 = g / sc;
         e.rhs[o] = b / sc;
@@ -987,11 +986,9 @@ __global__ void __launch_bounds__(256) k_adj_epilogue(EpiArg e)
         e.bq[o] = b;
         double y0 = 0.0;
         if (sc > 0.0) {
-            constexpr double cx[5] = {5.0, -10.0, 10.0, -5.0, 1.0};
             double g = 0.0;
-#pragma unroll
-            for (int k = 1; k <= 5; k++)
-                if (e.n - k >= 1) g += cx[k - 1] * e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
+            for (int k = 1; k <= e.nguess; k++)
+                if (e.n - k >= 1) g += e.gx[k - 1] * e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
             y0 = g / sc;
         }
         e.rhs[o] = sc * b;
