@@ -961,7 +961,7 @@ __global__ void __launch_bounds__(256) k_adj_source(AdjArg a)
 }
 
 // b'_j = g_j - sum_{k=1}^{nloc} c_k lambda_{j+k} + sum_{k>=1} K_k (*) nu_{j+k}; the solve takes
-// A mu = sqrt(chi) b' (Z_0^T = D^-1 A D), started from the quartic extrapolation of mu = nu / sqrt(chi).
+// A mu = sqrt(chi) b' (Z_0^T = D^-1 A D), started from the extrapolation (weights gx) of mu = nu / sqrt(chi).
 // The ring slots count the reversed step n' = N + 1 - j, so "n' - k" is step j + k.
 __global__ void __launch_bounds__(256) k_adj_epilogue(EpiArg e)
 {
