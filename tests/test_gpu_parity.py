@@ -331,6 +331,40 @@ def test_probes_match_oracle(torch_cuda):
     s.close()
 
 
+@pytest.mark.parametrize("delta", [0.01, 0.1])
+def test_stability_toolkit_matches_oracle(torch_cuda, delta):
+    """Companion-matrix dominant eigenvalue and PDSA minima of a 3^3 eps_r = 12 cube with the
+    17-tap filter, from the device-generated kernels (paper_2407_03323_amd.stability), against
+    the same quantities from the oracle's matrices; and the verdicts: delta = 0.01 stable,
+    delta = 0.1 unstable off the negative real axis (the third requirement of Sec. 6.1)."""
+    from math import comb
+    from paper_2407_03323_amd import stability as st
+    from test_oracle_stability import z_matrices
+    from oracle import mot
+    U = 3
+    say("stability toolkit 3^3 delta", delta)
+    taps = wl.binomial_highpass(17, delta)
+    eps = np.full((U, U, U), 12.0)
+    s = make_solver(wl.Problem("stab", U, U, U, eps, [], 1, fir=taps), n_rhs=1)
+    Zd = st.interaction_matrices(s, eps, taps)
+    s.close()
+    chi = 11.0 / 12.0
+    Zo = [z / chi for z in z_matrices(12.0, taps, mot.kernel_table(U, U, U, mot.ell(U, U, U)))]
+    assert len(Zd) == len(Zo)
+    scale = max(np.abs(z).max() for z in Zo)
+    assert max(np.abs(a - b).max() for a, b in zip(Zd, Zo)) <= 1e-11 * scale
+    lam_d, lam_o = st.companion_dominant(Zd), st.companion_dominant(Zo)
+    say("  dominant", lam_d, "oracle", lam_o)
+    assert abs(lam_d - lam_o) <= 1e-8 * abs(lam_o)
+    pd, po = st.pdsa_minima(Zd), st.pdsa_minima(Zo)
+    assert np.allclose(pd, po, rtol=1e-8, atol=1e-10 * scale)
+    if delta == 0.01:
+        assert abs(lam_d) < 0.99
+    else:
+        assert abs(lam_d) > 1.001 and abs(np.angle(lam_d)) < np.pi - 0.1
+        assert pd[-1] > 0.0          # D_L stays positive: the PDSA alone does not see this mode
+
+
 @pytest.mark.parametrize("name", ["C2", "C4"])
 def test_workload_march_stays_bounded(torch_cuda, name):
     """The workloads' 17-tap FIR (delta = 0.01) keeps the march stable over the configuration's

@@ -106,3 +106,16 @@ def test_companion_growth_rate_matches_the_oracle_march(kernels):
     env = np.array([nrm[i:i + 50].max() for i in range(N - 600, N - 50, 50)])
     rate = np.exp(np.polyfit(np.arange(len(env)) * 50.0, np.log(env), 1)[0])
     assert abs(rate - abs(lam)) < 2e-4 * abs(lam), (rate, abs(lam))
+
+
+def test_pdsa_regularisation_shifts_D_L_by_delta(kernels):
+    """eq:Regularization: the taps add delta I to D_L = sum_j (-1)^j Z_j (eq:RegReq1), so with the
+    rows scaled by 1/chi its smallest eigenvalue moves by exactly delta/chi; every D_n stays
+    positive definite here, although delta = 0.1 is unstable (a theta < pi mode, above)."""
+    from paper_2407_03323_amd import stability as st
+    chi = 11.0 / 12.0
+    m0 = st.pdsa_minima([z / chi for z in z_matrices(12.0, np.zeros(17), kernels)])
+    for delta in (0.01, 0.1):
+        m = st.pdsa_minima([z / chi for z in z_matrices(12.0, wl.binomial_highpass(17, delta), kernels)])
+        assert abs((m[-1] - m0[-1]) - delta / chi) < 1e-12
+        assert (m > 0).all()
