@@ -271,8 +271,9 @@ __host__ __device__ inline void gen_square(int nq, const double *glx, const doub
 __host__ __device__ inline int gen_items(int nq) { return 36 * 5 * nq; }
 
 // Item index -> (unit square, s-interval, s-node); the four edges of the square are
-// handled inside the item.  Dispatch on the plane axis.
-__host__ __device__ inline void gen_item(int nq, const double *glx, const double *glw, const double *g3x,
+// handled inside the item.  Dispatch on the plane axis.  Inlined by force: as a called
+// function its moment accumulators lived in scratch memory (192 bytes per lane).
+__host__ __device__ __attribute__((always_inline)) inline void gen_item(int nq, const double *glx, const double *glw, const double *g3x,
                                          const double *g3w, const double D[3], int a, int it, double m[kMoments])
 {
     const int iq = it % nq;
