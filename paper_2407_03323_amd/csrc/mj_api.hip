@@ -96,6 +96,10 @@ struct mj_solver {
     long npairs = 0;
     double *probe_pos = nullptr, *ptable = nullptr, *ppart = nullptr, *pout = nullptr;
     int *pair_vox = nullptr, *pair_kmin = nullptr, *row_start = nullptr, *pinv = nullptr;
+    int *ck_row = nullptr, *ck_lo = nullptr, *ck_hi = nullptr, *ck_start = nullptr;   // probe row chunks
+    double *ptable_v = nullptr;   // probe kernel table ordered by voxel (adjoint source)
+    int *pkmin_v = nullptr;
+    long pnck = 0;
     // transposed march: local history lambda, and the right-hand side before its sqrt(chi) scaling
     double *Lr = nullptr, *bq = nullptr;
     // statistics of the last run
@@ -566,6 +570,11 @@ void mj_solver::step(const StepIO &io)
             pa.Jring = Jr;
             pa.rdepth = rdepth;
             pa.part = ppart;
+            pa.ck_row = ck_row;
+            pa.ck_lo = ck_lo;
+            pa.ck_hi = ck_hi;
+            pa.ck_start = ck_start;
+            pa.nck = pnck;
             pa.out = io.Pout ? io.Pout : pout;
             mj::launch_probes(pa, st);
         }
@@ -598,6 +607,8 @@ mj::AdjArg mj_solver::adj_arg() const
     a.table = ptable;
     a.pair_kmin = pair_kmin;
     a.inv = pinv;
+    a.table_v = ptable_v;
+    a.kmin_v = pkmin_v;
     a.np = np;
     a.nw = nw;
     a.npairs = npairs;
@@ -729,6 +740,13 @@ void mj_solver::set_probes(int n_probes, const double *pos)
     dfree((void *&)pair_kmin);
     dfree((void *&)row_start);
     dfree((void *&)pinv);
+    dfree((void *&)ck_row);
+    dfree((void *&)ck_lo);
+    dfree((void *&)ck_hi);
+    dfree((void *&)ck_start);
+    dfree((void *&)ptable_v);
+    dfree((void *&)pkmin_v);
+    pnck = 0;
     np = 0;
     nw = 0;
     npairs = 0;
@@ -792,7 +810,35 @@ void mj_solver::set_probes(int n_probes, const double *pos)
     }
     int *pair_probe = dalloc<int>(std::max<size_t>(pp.size(), 1), "probe pair owners");
     ptable = dalloc<double>((size_t)std::max<long>(npairs, 1) * nw * 6, "probe kernel table");
-    ppart = dalloc<double>((size_t)nrhs * np * (ell + 1) * 3, "probe partial sums");
+    {
+        // every row (p, k) cut into chunks of at most kProbeChunk pairs, probe by probe
+        std::vector<int> crow, clo, chi_, cst;
+        for (int p = 0; p < n_probes; p++) {
+            cst.push_back((int)crow.size());
+            for (int kk = 0; kk <= ell; kk++) {
+                const int lo = rs[(size_t)p * (ell + 2) + std::max(0, kk - nwin + 1)];
+                const int hi = rs[(size_t)p * (ell + 2) + kk + 1];
+                for (int q = lo; q < hi; q += mj::kProbeChunk) {
+                    crow.push_back(p * (ell + 1) + kk);
+                    clo.push_back(q);
+                    chi_.push_back(std::min(hi, q + mj::kProbeChunk));
+                }
+            }
+        }
+        cst.push_back((int)crow.size());
+        pnck = (long)crow.size();
+        ck_row = dalloc<int>(std::max<size_t>(crow.size(), 1), "probe chunks");
+        ck_lo = dalloc<int>(std::max<size_t>(crow.size(), 1), "probe chunks");
+        ck_hi = dalloc<int>(std::max<size_t>(crow.size(), 1), "probe chunks");
+        ck_start = dalloc<int>(cst.size(), "probe chunks");
+        if (pnck > 0) {
+            MJ_CHECK(hipMemcpy(ck_row, crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice));
+            MJ_CHECK(hipMemcpy(ck_lo, clo.data(), sizeof(int) * clo.size(), hipMemcpyHostToDevice));
+            MJ_CHECK(hipMemcpy(ck_hi, chi_.data(), sizeof(int) * chi_.size(), hipMemcpyHostToDevice));
+        }
+        MJ_CHECK(hipMemcpy(ck_start, cst.data(), sizeof(int) * cst.size(), hipMemcpyHostToDevice));
+    }
+    ppart = dalloc<double>((size_t)nrhs * std::max<long>(pnck, 1) * 3, "probe partial sums");
     pout = dalloc<double>((size_t)nrhs * np * 3, "probe field");
     MJ_CHECK(hipMemcpy(probe_pos, P.data(), sizeof(double) * P.size(), hipMemcpyHostToDevice));
     MJ_CHECK(hipMemcpy(row_start, rs.data(), sizeof(int) * rs.size(), hipMemcpyHostToDevice));
@@ -814,6 +860,10 @@ void mj_solver::set_probes(int n_probes, const double *pos)
         (void)hipEventDestroy(e1);
     }
     dfree((void *&)pair_probe);
+    // the adjoint source walks the table voxel by voxel: a copy in that order
+    ptable_v = dalloc<double>((size_t)nw * n_probes * M * 6, "probe kernel table by voxel");
+    pkmin_v = dalloc<int>((size_t)n_probes * M, "probe windows by voxel");
+    mj::launch_probe_table_by_voxel(ptable, pair_kmin, pinv, npairs, n_probes, nw, M, ptable_v, pkmin_v, st);
     // the probe rows read J_{n-k} for k = 0..ell from the real-space ring
     if (rdepth < ell + 1) {
         dfree((void *&)Jr);

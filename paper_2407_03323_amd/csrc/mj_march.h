@@ -69,6 +69,8 @@ struct AdjArg {
     const double *table;     // probe kernel table [nw][npairs][6]
     const int *pair_kmin;    // [npairs]
     const int *inv;          // [np][M] pair of (probe, voxel), -1 if none
+    const double *table_v;   // the same table by voxel: [nw][np][M][6] (zeros where inv < 0)
+    const int *kmin_v;       // [np][M] first lag of the pair's window, -1 if no pair
     const double *Ehist;     // [N][nrhs][np][3]
     int np, nw, N, j;        // j: forward step of this adjoint step
     long npairs;
@@ -115,25 +117,34 @@ struct CgArg {
 // over the source voxels s of the scatterer.  Pairs (p, s) are stored per probe sorted by the
 // first lag kmin of their window, so the sources that lag k reaches through window slot
 // k - kmin form one contiguous run: row (p, k) = pairs [row_start[p][max(0, k-nw+1)],
-// row_start[p][k+1]).
+// row_start[p][k+1]).  The host cuts every row into chunks for the waves.
 struct ProbeStepArg {
     const double *table;     // [nw][npairs][6]
     const int *pair_vox;     // [npairs]
     const int *pair_kmin;    // [npairs]
     const int *row_start;    // [np][ell + 2]
     int np, ell, nw, nrhs, n;
+    // rows cut into chunks of at most kProbeChunk pairs, listed probe by probe: chunk c covers
+    // pairs [ck_lo[c], ck_hi[c]) of row ck_row[c] = p (ell + 1) + k; probe p owns chunks
+    // [ck_start[p], ck_start[p + 1])
+    const int *ck_row, *ck_lo, *ck_hi, *ck_start;
+    long nck;
     long M, npairs;
     const double *Jring;     // [rdepth][nrhs][3][M]
     int rdepth;
-    double *part;            // [nrhs][np][ell + 1][3]
+    double *part;            // [nrhs][nck][3]
     double *out;             // [nrhs][np][3]
 };
+constexpr int kProbeChunk = 1024;   // pairs of one row handled by one wave
 
 void launch_mac(const MacArg &a, hipStream_t st);
 void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st);
 void launch_probes(const ProbeStepArg &a, hipStream_t st);
 void launch_grad_term(const EpiArg &e, const double *Jn, const double *Jn1, double *Bout, hipStream_t st);
 void launch_adj_source(const AdjArg &a, hipStream_t st);
+// table_v[wl][p][m] = table[wl][inv[p][m]], kmin_v[p][m] = pair_kmin[inv[p][m]] (-1, zeros where none)
+void launch_probe_table_by_voxel(const double *table, const int *pair_kmin, const int *inv, long npairs, int np,
+                                 int nw, long M, double *table_v, int *kmin_v, hipStream_t st);
 void launch_adj_epilogue(const EpiArg &e, hipStream_t st);
 void launch_adj_lambda(const AdjArg &a, hipStream_t st);
 void launch_grad_accum(const AdjArg &a, hipStream_t st);

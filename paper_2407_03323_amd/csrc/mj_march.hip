@@ -820,64 +820,77 @@ void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, dou
 }
 
 // ---------------------------------------------------------------------------- probes
-// One wave per row (p, k): the sources whose lag window holds k, each through its window slot
-// k - kmin, against J_{n-k}; lanes stride over the run and the wave sums in fixed order.
+// One wave per chunk (at most kProbeChunk pairs of one row (p, k)): the sources whose lag window
+// holds k, each through its window slot k - kmin, against J_{n-k}; lanes take pairs q and q + 64
+// together (two independent gathers in flight), and the wave sums in fixed order.
 __global__ void __launch_bounds__(256) k_probe_rows(ProbeStepArg a)
 {
     const int lane = threadIdx.x & 63;
-    const long row = blockIdx.x * 4L + (threadIdx.x >> 6);
+    const long c = blockIdx.x * 4L + (threadIdx.x >> 6);
     const int r = blockIdx.y;
+    if (c >= a.nck) return;
     const int L1 = a.ell + 1;
-    if (row >= (long)a.np * L1) return;
-    const int p = (int)(row / L1), k = (int)(row % L1);
+    const int k = a.ck_row[c] % L1;
     double acc[3] = {0.0, 0.0, 0.0};
     const int j = a.n - k;
     if (j >= 1) {
-        const int *rs = a.row_start + (long)p * (a.ell + 2);
-        const int lo = rs[k - a.nw + 1 > 0 ? k - a.nw + 1 : 0], hi = rs[k + 1];
+        const int lo = a.ck_lo[c], hi = a.ck_hi[c];
         const double *J = a.Jring + ((long)(j % a.rdepth) * a.nrhs + r) * 3 * a.M;
-        for (int q = lo + lane; q < hi; q += 64) {
-            const int wl = k - a.pair_kmin[q];
-            const double *K = a.table + ((long)wl * a.npairs + q) * 6;
-            const long m = a.pair_vox[q];
-            const double jx = J[m], jy = J[a.M + m], jz = J[2 * a.M + m];
-            acc[0] += K[0] * jx + K[3] * jy + K[4] * jz;
-            acc[1] += K[3] * jx + K[1] * jy + K[5] * jz;
-            acc[2] += K[4] * jx + K[5] * jy + K[2] * jz;
+        for (int q0 = lo + lane; q0 < hi; q0 += 128) {
+            const int q1 = q0 + 64;
+            const bool two = q1 < hi;
+            const int qb = two ? q1 : q0;
+            const int wl0 = k - a.pair_kmin[q0], wl1 = k - a.pair_kmin[qb];
+            const long m0 = a.pair_vox[q0], m1 = a.pair_vox[qb];
+            const double *K0 = a.table + ((long)wl0 * a.npairs + q0) * 6;
+            const double *K1 = a.table + ((long)wl1 * a.npairs + qb) * 6;
+            const double x0 = J[m0], y0 = J[a.M + m0], z0 = J[2 * a.M + m0];
+            const double x1 = J[m1], y1 = J[a.M + m1], z1 = J[2 * a.M + m1];
+            const double f = two ? 1.0 : 0.0;
+            acc[0] += K0[0] * x0 + K0[3] * y0 + K0[4] * z0;
+            acc[1] += K0[3] * x0 + K0[1] * y0 + K0[5] * z0;
+            acc[2] += K0[4] * x0 + K0[5] * y0 + K0[2] * z0;
+            acc[0] += f * (K1[0] * x1 + K1[3] * y1 + K1[4] * z1);
+            acc[1] += f * (K1[3] * x1 + K1[1] * y1 + K1[5] * z1);
+            acc[2] += f * (K1[4] * x1 + K1[5] * y1 + K1[2] * z1);
         }
     }
 #pragma unroll
-    for (int c = 0; c < 3; c++)
-        for (int off = 32; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
+    for (int cc = 0; cc < 3; cc++)
+        for (int off = 32; off >= 1; off >>= 1) acc[cc] += __shfl_xor(acc[cc], off);
     if (lane == 0) {
-        double *o = a.part + (((long)r * a.np + p) * L1 + k) * 3;
+        double *o = a.part + ((long)r * a.nck + c) * 3;
         o[0] = acc[0];
         o[1] = acc[1];
         o[2] = acc[2];
     }
 }
 
-// E^s_p(n) = sum over the rows k = 0 .. ell, in order
-__global__ void k_probe_sum(ProbeStepArg a)
+// E^s_p(n) = sum over the chunks of probe p (rows k = 0 .. ell in order): one wave per
+// (rhs, probe), lane l adds chunks l, l + 64, ... in order, then a fixed butterfly.
+__global__ void __launch_bounds__(64) k_probe_sum(ProbeStepArg a)
 {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= (long)a.nrhs * a.np * 3) return;
-    const int c = (int)(t % 3);
-    const long rp = t / 3;
-    const int L1 = a.ell + 1;
-    const double *src = a.part + rp * L1 * 3 + c;
-    double s = 0.0;
-    for (int k = 0; k < L1; k++) s += src[3 * k];
-    a.out[t] = s;
+    const int r = blockIdx.x / a.np, p = blockIdx.x % a.np;
+    const int lane = threadIdx.x;
+    const double *src = a.part + (long)r * a.nck * 3;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (long i = a.ck_start[p] + lane; i < a.ck_start[p + 1]; i += 64)
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) s[cc] += src[3 * i + cc];
+#pragma unroll
+    for (int cc = 0; cc < 3; cc++)
+        for (int off = 32; off >= 1; off >>= 1) s[cc] += __shfl_xor(s[cc], off);
+    if (lane == 0)
+        for (int cc = 0; cc < 3; cc++) a.out[((long)r * a.np + p) * 3 + cc] = s[cc];
 }
 
 void launch_probes(const ProbeStepArg &a, hipStream_t st)
 {
-    const long rows = (long)a.np * (a.ell + 1);
-    hipLaunchKernelGGL(k_probe_rows, dim3((unsigned)((rows + 3) / 4), a.nrhs), dim3(256), 0, st, a);
-    MJ_CHECK(hipGetLastError());
-    const long nt = (long)a.nrhs * a.np * 3;
-    hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a);
+    if (a.nck > 0) {
+        hipLaunchKernelGGL(k_probe_rows, dim3((unsigned)((a.nck + 3) / 4), a.nrhs), dim3(256), 0, st, a);
+        MJ_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)((long)a.nrhs * a.np)), dim3(64), 0, st, a);
     MJ_CHECK(hipGetLastError());
 }
 
@@ -943,14 +956,14 @@ __global__ void __launch_bounds__(256) k_adj_source(AdjArg a)
     const int r = blockIdx.y;
     if (i >= a.M) return;
     double acc[3] = {0.0, 0.0, 0.0};
+    // the voxel-ordered copy of the table: neighbouring lanes read neighbouring records
     for (int p = 0; p < a.np; p++) {
-        const int q = a.inv[(long)p * a.M + i];
-        if (q < 0) continue;
-        const int kmin = a.pair_kmin[q];
+        const int kmin = a.kmin_v[(long)p * a.M + i];
+        if (kmin < 0) continue;
         for (int wl = 0; wl < a.nw; wl++) {
             const int jj = a.j + kmin + wl;
             if (jj > a.N) break;
-            const double *K = a.table + ((long)wl * a.npairs + q) * 6;
+            const double *K = a.table_v + (((long)wl * a.np + p) * a.M + i) * 6;
             const double *E = a.Ehist + (((long)(jj - 1) * a.nrhs + r) * a.np + p) * 3;
             acc[0] += K[0] * E[0] + K[3] * E[1] + K[4] * E[2];
             acc[1] += K[3] * E[0] + K[1] * E[1] + K[5] * E[2];
@@ -958,6 +971,26 @@ __global__ void __launch_bounds__(256) k_adj_source(AdjArg a)
         }
     }
     for (int c = 0; c < 3; c++) a.G[((long)r * 3 + c) * a.M + i] = 2.0 * acc[c];
+}
+
+__global__ void k_probe_table_by_voxel(const double *__restrict__ table, const int *__restrict__ pair_kmin,
+                                       const int *__restrict__ inv, long npairs, int np, int nw, long M,
+                                       double *__restrict__ table_v, int *__restrict__ kmin_v)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;   // (wl, p, m)
+    if (t >= (long)nw * np * M) return;
+    const long pm = t % ((long)np * M);
+    const int wl = (int)(t / ((long)np * M));
+    const int q = inv[pm];
+    double *dst = table_v + t * 6;
+    if (q < 0) {
+        for (int c = 0; c < 6; c++) dst[c] = 0.0;
+        if (wl == 0) kmin_v[pm] = -1;
+        return;
+    }
+    const double *src = table + ((long)wl * npairs + q) * 6;
+    for (int c = 0; c < 6; c++) dst[c] = src[c];
+    if (wl == 0) kmin_v[pm] = pair_kmin[q];
 }
 
 // b'_j = g_j - sum_{k=1}^{nloc} c_k lambda_{j+k} + sum_{k>=1} K_k (*) nu_{j+k}; the solve takes
@@ -1044,6 +1077,15 @@ void launch_grad_term(const EpiArg &e, const double *Jn, const double *Jn1, doub
     hipLaunchKernelGGL(k_grad_term, voxel_grid(e.M, e.nrhs), dim3(256), 0, st, e, Jn, Jn1, Bout);
     MJ_CHECK(hipGetLastError());
 }
+void launch_probe_table_by_voxel(const double *table, const int *pair_kmin, const int *inv, long npairs, int np,
+                                 int nw, long M, double *table_v, int *kmin_v, hipStream_t st)
+{
+    const long n = (long)nw * np * M;
+    hipLaunchKernelGGL(k_probe_table_by_voxel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, table, pair_kmin,
+                       inv, npairs, np, nw, M, table_v, kmin_v);
+    MJ_CHECK(hipGetLastError());
+}
+
 void launch_adj_source(const AdjArg &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_adj_source, voxel_grid(a.M, a.nrhs), dim3(256), 0, st, a);
