@@ -18,7 +18,9 @@
  *
  * Conventions
  *  - Lengths in any unit; h is the voxel edge.  Times enter as c*t (same unit).
- *    This version requires c*dt == h (the paper's choice dt = dx/c, Sec. 5.2).
+ *    c*dt may be any value in [0.3 h, h]: the paper's choice dt = dx/c (Sec. 5.2) is the
+ *    largest; up to it K_0 stays on the 27 nearest offsets, which the Z_0 solve assumes.
+ *    Smaller steps add lags (eq:Ell) and kernel work in proportion to h / (c dt).
  *  - Voxel index m = (w*V + v)*U + u, 0-based, x fastest (Sec. 2.2, 1-based there).
  *    Voxel (u,v,w) has its centre at ((u+1/2)h, (v+1/2)h, (w+1/2)h).
  *  - Vector fields are stored per component: F[a][w][v][u], a = x,y,z (the paper's
@@ -58,7 +60,7 @@ typedef struct mj_solver mj_solver;
 typedef struct {
     int32_t U, V, W;          /* voxels per axis (>= 1) */
     double h;                 /* voxel edge (> 0) */
-    double c_dt;              /* c * dt; must equal h */
+    double c_dt;              /* c * dt, in [0.3 h, h]; MJ_EINVAL outside */
     const double *eps_r;      /* host [W][V][U], relative permittivity >= 1, finite */
     const double *fir;        /* host taps delta_0..delta_{n_fir-1} (Sec. 6.1); may be NULL if n_fir == 0 */
     int32_t n_fir;            /* 0 = no regularisation */

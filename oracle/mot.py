@@ -68,14 +68,15 @@ def local_coefficients(eps: np.ndarray, fir: np.ndarray, kmax: int) -> np.ndarra
     return c
 
 
-def excitation(U, V, W, eps, wave, n: int, nquad: int = 8) -> np.ndarray:
+def excitation(U, V, W, eps, wave, n: int, nquad: int = 8, r: float = 1.0) -> np.ndarray:
     """E_n(m) = chi_m (1/h^3) Int_{V_m} E^i(r, n dt) dV  (eq:E, test voxel m and step n),
-    the voxel average taken with an nquad^3 Gauss-Legendre rule."""
-    return chi_of(eps)[None] * incident_average(U, V, W, wave, n, nquad)
+    the voxel average taken with an nquad^3 Gauss-Legendre rule; c dt = r h."""
+    return chi_of(eps)[None] * incident_average(U, V, W, wave, n, nquad, r)
 
 
-def incident_average(U, V, W, wave, n: int, nquad: int = 8) -> np.ndarray:
-    """<E^i>_m(n dt) = (1/h^3) Int_{V_m} E^i(r, n dt) dV, [3][W][V][U]."""
+def incident_average(U, V, W, wave, n: int, nquad: int = 8, r: float = 1.0) -> np.ndarray:
+    """<E^i>_m(n dt) = (1/h^3) Int_{V_m} E^i(r, n dt) dV, [3][W][V][U].  Lengths in units of h
+    (t0 and width are c t0 and the pulse width as lengths); c n dt = n r."""
     x, w = np.polynomial.legendre.leggauss(nquad)
     x = 0.5 * x
     w = 0.5 * w
@@ -84,7 +85,7 @@ def incident_average(U, V, W, wave, n: int, nquad: int = 8) -> np.ndarray:
     p = np.asarray(wave.pol, float)
     rr = np.asarray(wave.r_ref, float)
     # tau at the voxel centre, and the projections of the quadrature offsets on khat
-    tc = float(n) - wave.t0 - ((wx + 0.5 - rr[0]) * k[0] + (wy + 0.5 - rr[1]) * k[1] + (wz + 0.5 - rr[2]) * k[2])
+    tc = float(n) * r - wave.t0 - ((wx + 0.5 - rr[0]) * k[0] + (wy + 0.5 - rr[1]) * k[1] + (wz + 0.5 - rr[2]) * k[2])
     avg = np.zeros(tc.shape)
     for i in range(nquad):
         for j in range(nquad):
@@ -213,10 +214,13 @@ class Oracle:
     """Direct MOT-JVIE march for one Problem (workloads.Problem) and one right-hand side."""
 
     def __init__(self, prob, K=None, ngl: int = 16):
-        assert abs(prob.c_dt - prob.h) < 1e-14 * prob.h, "oracle assumes c dt = h"
+        # lengths in units of h; c dt = r h with r <= 1 keeps K_0 on the 27 nearest offsets
+        assert prob.h == 1.0, "the oracle works in units of h = 1"
+        self.r = float(prob.c_dt)
+        assert 0.0 < self.r <= 1.0, "the oracle takes c dt <= h"
         self.p = prob
-        self.ell = ell(prob.U, prob.V, prob.W)
-        self.K = kernel_table(prob.U, prob.V, prob.W, self.ell, ngl) if K is None else K
+        self.ell = ell(prob.U, prob.V, prob.W, 1.0, self.r)
+        self.K = kernel_table(prob.U, prob.V, prob.W, self.ell, ngl, self.r) if K is None else K
         self.fir = np.asarray(prob.fir, float)
         self.depth = max(self.ell, len(self.fir) - 1, 1)
         self.Z0 = z0_matrix(self.K[0], prob.eps, self.fir).tocsc()
@@ -232,7 +236,7 @@ class Oracle:
             lo = max(0, n - self.depth)
             Jh = J[lo:n][::-1]                       # Jh[k-1] = J_{n-k}
             P = history_sum(self.K, np.ascontiguousarray(Jh), p.eps, self.fir, self.ell)
-            E = excite(n) if excite is not None else excitation(U, V, W, p.eps, p.waves[rhs], n)
+            E = excite(n) if excite is not None else excitation(U, V, W, p.eps, p.waves[rhs], n, r=self.r)
             b = (E - P).ravel()
             J[n] = self.lu.solve(b).reshape(3, W, V, U)
             if return_P:
@@ -280,7 +284,7 @@ class Oracle:
         for n in range(1, N + 1):
             lo = max(0, n - 1 - self.ell)
             Jh = np.ascontiguousarray(J[lo:n - 1][::-1])          # Jh[k-1] = J_{n-k}, k >= 1
-            Bn = incident_average(p.U, p.V, p.W, p.waves[rhs], n)
+            Bn = incident_average(p.U, p.V, p.W, p.waves[rhs], n, r=self.r)
             Bn = Bn + tbasis(0) * J[n - 1] + conv(K0, np.ascontiguousarray(J[n - 1:n]))
             if n >= 2:
                 Bn = Bn + tbasis(1) * J[n - 2]
@@ -297,7 +301,7 @@ class Oracle:
         W, V, U = p.W, p.V, p.U
         J = self.run(n_steps, rhs)
         src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U)]
-        Kp = probe_kernels(probes, src, self.ell)
+        Kp = probe_kernels(probes, src, self.ell, r=self.r)
         E = probe_field(Kp, J, src)
         phi = float((E ** 2).sum())
         Kf = Kp[..., np.array(COMP).ravel()].reshape(Kp.shape[:3] + (3, 3))   # [np][M][k][b][a]

@@ -179,7 +179,10 @@ void mj_solver::create(const mj_config &c)
 {
     if (c.U < 1 || c.V < 1 || c.W < 1) throw ArgError("U, V, W must be >= 1");
     if (!(c.h > 0.0) || !std::isfinite(c.h)) throw ArgError("h must be positive and finite");
-    if (!(std::fabs(c.c_dt - c.h) <= 1e-12 * c.h)) throw ArgError("this version requires c*dt == h");
+    if (!(c.c_dt > 0.0) || !std::isfinite(c.c_dt)) throw ArgError("c_dt must be positive and finite");
+    // c dt <= h keeps K_0 on the 27-point stencil the Z_0 solve is built for
+    if (!(c.c_dt <= c.h * (1.0 + 1e-12) && c.c_dt >= mj::kMinCdtOverH * c.h))
+        throw ArgError("c_dt / h must be in [0.3, 1]");
     if (!c.eps_r) throw ArgError("eps_r is NULL");
     if (c.n_fir < 0 || (c.n_fir > 0 && !c.fir)) throw ArgError("bad FIR taps");
     if (c.n_fir > mj::kMaxLocal) throw ArgError("at most 64 FIR taps");
@@ -286,8 +289,8 @@ void mj_solver::set_material(const double *eps)
 void mj_solver::build_spectra()
 {
     auto t0 = std::chrono::steady_clock::now();
-    mj::gen_moments(gen, U, V, W, nquad, st);
-    bytes += (size_t)M * mj::kMaxShells * mj::kMoments * sizeof(double);
+    mj::gen_moments(gen, U, V, W, std::min(1.0, c_dt / h), nquad, st);
+    bytes += (size_t)M * gen.ms * mj::kMoments * sizeof(double);
     MJ_CHECK(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     t_gen_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -850,7 +853,7 @@ void mj_solver::set_probes(int n_probes, const double *pos)
         MJ_CHECK(hipEventCreate(&e0));
         MJ_CHECK(hipEventCreate(&e1));
         MJ_CHECK(hipEventRecord(e0, st));
-        mj::gen_offgrid_table(probe_pos, pair_probe, pair_vox, pair_kmin, npairs, U, V, nw, ell, nquad, ptable, st);
+        mj::gen_offgrid_table(probe_pos, pair_probe, pair_vox, pair_kmin, npairs, U, V, gen.r, nw, ell, nquad, ptable, st);
         MJ_CHECK(hipEventRecord(e1, st));
         MJ_CHECK(hipEventSynchronize(e1));
         float ms = 0;
@@ -898,7 +901,7 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
         MJ_CHECK(hipMemcpy(d_p, pp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(d_v, pv.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(d_k, pk.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
-        mj::gen_offgrid_table(probe_pos, d_p, d_v, d_k, cnt, U, V, 1, 0x7fffffff, nquad, d_o, st);
+        mj::gen_offgrid_table(probe_pos, d_p, d_v, d_k, cnt, U, V, gen.r, 1, 0x7fffffff, nquad, d_o, st);
         MJ_CHECK(hipStreamSynchronize(st));
         MJ_CHECK(hipMemcpy(out, d_o, sizeof(double) * 6 * cnt, hipMemcpyDeviceToHost));
     } catch (...) {

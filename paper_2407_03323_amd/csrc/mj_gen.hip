@@ -1,20 +1,20 @@
 // Space-time interaction kernels of the MOT-JVIE on the device (FP64).
 //
 // For test voxel m, source voxel m', lag k = n - n' and D = r_m - r_m' (voxel units,
-// h = 1, c dt = h), eq:Z with the piecewise-constant spatial basis (eq:SpatialBasis),
+// h = 1, c dt = r h with 0 < r <= 1), eq:Z with the piecewise-constant spatial basis (eq:SpatialBasis),
 // the voxel-average Dirac-in-time test (eq:TestOperator) and the quadratic-spline
 // temporal basis T(t) = B(t/dt + 1) (B the uniform quadratic B-spline on [0,3]) gives
 //
 //   Z^{ba}_k(m, m') = d_ab d_mm' T(k dt) / eps_m - chi_m K^{ba}_k(D),
 //   K^{ba}_k(D) = Int g_k(d) d_a d_b Lam(d - D) dd - d_ab Int gbar_k(d) Lam(d - D) dd,
-//   g_k = B(k + 1 - |d|) / (4 pi |d|),  gbar_k = B''(k + 1 - |d|) / (4 pi |d|),
+//   g_k = B(k + 1 - |d|/r) / (4 pi |d|),  gbar_k = B''(k + 1 - |d|/r) / (4 pi r^2 |d|),
 //   Lam(x) = prod_i (1 - |x_i|)_+ ,
 //
 // the derivatives of Lam taken in the distributional sense (a == b gives the second
 // difference across the planes d_a = D_a - 1, D_a, D_a + 1).
 //
-// Factorisation used here.  On the unit shell a <= |d| < a + 1 each B-spline piece is
-// a quadratic in v = |d| - a, so every lag is a fixed combination of the lag-free
+// Factorisation used here.  On the shell a r <= |d| < (a + 1) r each B-spline piece is
+// a quadratic in v = |d|/r - a, so every lag is a fixed combination of the lag-free
 // shell moments
 //   plane_a,j : sum_s w_s Int_{plane s, shell} lam lam v^j / |d| dS    (a = x, y, z; j = 0..2)
 //   cube_ab,j : Int_{shell} d_a d_b Lam v^j / |d| dV                    (ab = xy, xz, yz)
@@ -24,7 +24,7 @@
 //
 // Quadrature.  A volume moment over a sub-box (where Lam and its derivatives are
 // polynomials) is turned into face integrals by the divergence theorem with the radial
-// field y Psi(y) / |y|^3, Psi(y) = Int_a^{min(|y|, a+1)} P(u yhat) v^j u du (div = P v^j/|y|
+// field y Psi(y) / |y|^3, Psi(y) = Int_{a r}^{min(|y|, (a+1) r)} P(u yhat) v^j u du (div = P v^j/|y|
 // on the shell); Psi is a polynomial in u of degree <= 4 and is integrated exactly by
 // 3-point Gauss-Legendre.  Every face or plane integral is taken over a unit square as
 // four signed triangles with apex at the foot of the perpendicular from the origin,
@@ -48,25 +48,39 @@ constexpr double kInvFourPi = 0.07957747154594766788;
 struct GenArg {
     int Uo, Vo, Wo;
     int nq;
+    int ms;                          // shells stored per offset
+    double r;                        // c dt / h
     double glx[kMaxQ], glw[kMaxQ];   // nq-point rule on [-1, 1]
     double g3x[3], g3w[3];           // 3-point rule on [-1, 1]
 };
 
-// shell index range [a_lo, a_lo + nsh) meeting the distances between two voxels at offset D
-__host__ __device__ inline void shell_range(int dx, int dy, int dz, int &a_lo, int &nsh)
+// Shells a r <= |d| < (a + 1) r, a in [a_lo, a_lo + nsh), that meet the distance range
+// [R_min, R_max] of two voxels: a_lo = floor(R_min / r), a_lo + nsh = ceil(R_max / r).  With
+// r = 1 the squared radii are integers and the bounds are exact.
+__host__ __device__ inline void shell_bounds(double rmin2, double rmax2, double r, int &a_lo, int &nsh)
 {
-    int ex = dx > 0 ? dx - 1 : 0, ey = dy > 0 ? dy - 1 : 0, ez = dz > 0 ? dz - 1 : 0;
-    long rmin2 = (long)ex * ex + (long)ey * ey + (long)ez * ez;
-    long rmax2 = (long)(dx + 1) * (dx + 1) + (long)(dy + 1) * (dy + 1) + (long)(dz + 1) * (dz + 1);
-    int lo = (int)floor(sqrt((double)rmin2));
-    while ((long)(lo + 1) * (lo + 1) <= rmin2) lo++;
-    while ((long)lo * lo > rmin2) lo--;
-    int hi = (int)ceil(sqrt((double)rmax2));  // smallest integer >= R_max
-    while ((long)(hi - 1) * (hi - 1) >= rmax2) hi--;
-    while ((long)hi * hi < rmax2) hi++;
+    const double Rmin = sqrt(rmin2), Rmax = sqrt(rmax2);
+    int lo = (int)floor(Rmin / r);
+    while ((lo + 1) * r <= Rmin) lo++;
+    while (lo > 0 && lo * r > Rmin) lo--;
+    int hi = (int)ceil(Rmax / r);
+    while (hi - 1 > lo && (hi - 1) * r >= Rmax) hi--;
+    while (hi * r < Rmax) hi++;
     a_lo = lo;
     nsh = hi - lo;
 }
+
+__host__ __device__ inline void shell_range(int dx, int dy, int dz, double r, int &a_lo, int &nsh)
+{
+    const int ex = dx > 0 ? dx - 1 : 0, ey = dy > 0 ? dy - 1 : 0, ez = dz > 0 ? dz - 1 : 0;
+    const double rmin2 = (double)ex * ex + (double)ey * ey + (double)ez * ez;
+    const double rmax2 = (double)(dx + 1) * (dx + 1) + (double)(dy + 1) * (dy + 1) + (double)(dz + 1) * (dz + 1);
+    shell_bounds(rmin2, rmax2, r, a_lo, nsh);
+}
+
+// Upper bound on the shells of one voxel pair: R_max - R_min <= 2 sqrt 3, plus one shell cut
+// at each end and one for rounding.
+__host__ __device__ inline int shells_per_offset(double r) { return (int)(3.4641016151377546 / r) + 3; }
 
 // Fixed-size ascending sort with compile-time indices only (values stay in registers).
 template <int N>
@@ -87,27 +101,27 @@ __host__ __device__ inline void sort_fixed(double *a)
 // Every array index is a compile-time constant.
 template <int AX>
 __host__ __device__ inline void node_contrib(double m[kMoments], const double y[3], double ny, double wgt, int s,
-                                             int s1, int s2, const double D[3], int a, const double *g3x,
-                                             const double *g3w)
+                                             int s1, int s2, const double D[3], double Ra, double Rb, double inv_r,
+                                             const double *g3x, const double *g3w)
 {
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
     const double c = y[AX];
     const double inv_ny = 1.0 / ny;
     // plane term of component AX: w_s lam lam v^j / |y| on the shell
-    if (ny >= a && ny < a + 1) {
+    if (ny >= Ra && ny < Rb) {
         const double ws = (s == 0) ? -2.0 : 1.0;
         const double l1 = 1.0 - s1 * (y[A1] - D[A1]);
         const double l2 = 1.0 - s2 * (y[A2] - D[A2]);
-        const double v = ny - a;
+        const double v = (ny - Ra) * inv_r;
         const double f = wgt * ws * l1 * l2 * inv_ny;
         m[3 * AX + 0] += f;
         m[3 * AX + 1] += f * v;
         m[3 * AX + 2] += f * v * v;
     }
-    if (c == 0.0 || ny <= a) return;
+    if (c == 0.0 || ny <= Ra) return;
     // cone fluxes of the adjacent sub-boxes
-    const double hi = ny < a + 1 ? ny : (double)(a + 1);
-    const double hm = 0.5 * (hi - a), hc = 0.5 * (hi + a);
+    const double hi = ny < Rb ? ny : Rb;
+    const double hm = 0.5 * (hi - Ra), hc = 0.5 * (hi + Ra);
     const double yh[3] = {y[0] * inv_ny, y[1] * inv_ny, y[2] * inv_ny};
     const double flux_scale = wgt * inv_ny * inv_ny * inv_ny * hm;
 #pragma unroll
@@ -136,7 +150,7 @@ __host__ __device__ inline void node_contrib(double m[kMoments], const double y[
             const double l0 = 1.0 - sb[0] * (u * yh[0] - D[0]);
             const double l1 = 1.0 - sb[1] * (u * yh[1] - D[1]);
             const double l2 = 1.0 - sb[2] * (u * yh[2] - D[2]);
-            const double v = u - a;
+            const double v = (u - Ra) * inv_r;
             lamI += wq * l0 * l1 * l2;
             const double w0 = wq, w1 = wq * v, w2 = wq * v * v;
             const double pxy = sb[0] * sb[1] * l2, pxz = sb[0] * sb[2] * l1, pyz = sb[1] * sb[2] * l0;
@@ -156,16 +170,15 @@ __host__ __device__ inline void node_contrib(double m[kMoments], const double y[
 constexpr double kSentinel = 1e300;
 constexpr int kMaxGrade = 6;   // graded tau points towards the foot (ratio 3)
 
-// One work item of the face quadrature of shell a at octant offset D for a unit square in the
+// One work item of the face quadrature of shell [Ra, Rb) at octant offset D for a unit square in the
 // plane y_AX = D[AX] + s: edge e, s-interval iv of that edge, s-node iq; accumulates into m.
 // glx/glw: nq-point rule on [-1,1]; g3x/g3w: 3-point rule.
 template <int AX, int E>
 __host__ __device__ inline void gen_edge(int nq, const double *glx, const double *glw, const double *g3x,
-                                         const double *g3w, const double D[3], int a, int s, int s1, int s2, int iv,
-                                         int iq, double m[kMoments])
+                                         const double *g3w, const double D[3], double Ra, double Rb, double inv_r,
+                                         int s, int s1, int s2, int iv, int iq, double m[kMoments])
 {
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
-    const double Ra = (double)a, Rb = (double)(a + 1);
     const double c = D[AX] + s;
     const double lo1 = s1 > 0 ? D[A1] : D[A1] - 1, lo2 = s2 > 0 ? D[A2] : D[A2] - 1;
     const double hi1 = lo1 + 1.0, hi2 = lo2 + 1.0;
@@ -251,20 +264,20 @@ __host__ __device__ inline void gen_edge(int nq, const double *glx, const double
             y[A2] = tau * ey2;
             const double ny = sqrt(c2 + tau * tau * L * L);
             const double wgt = wsn * thm * glw[q] * tau;
-            node_contrib<AX>(m, y, ny, wgt, s, s1, s2, D, a, g3x, g3w);
+            node_contrib<AX>(m, y, ny, wgt, s, s1, s2, D, Ra, Rb, inv_r, g3x, g3w);
         }
     }
 }
 
 template <int AX>
 __host__ __device__ inline void gen_square(int nq, const double *glx, const double *glw, const double *g3x,
-                                           const double *g3w, const double D[3], int a, int s, int s1, int s2, int iv,
-                                           int iq, double m[kMoments])
+                                           const double *g3w, const double D[3], double Ra, double Rb, double inv_r,
+                                           int s, int s1, int s2, int iv, int iq, double m[kMoments])
 {
-    gen_edge<AX, 0>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
-    gen_edge<AX, 1>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
-    gen_edge<AX, 2>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
-    gen_edge<AX, 3>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 0>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 1>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 2>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 3>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
 }
 
 // Number of work items per (offset, shell): 36 unit squares x 5 s-intervals x nq s-nodes.
@@ -274,8 +287,10 @@ __host__ __device__ inline int gen_items(int nq) { return 36 * 5 * nq; }
 // handled inside the item.  Dispatch on the plane axis.  Inlined by force: as a called
 // function its moment accumulators lived in scratch memory (192 bytes per lane).
 __host__ __device__ __attribute__((always_inline)) inline void gen_item(int nq, const double *glx, const double *glw, const double *g3x,
-                                         const double *g3w, const double D[3], int a, int it, double m[kMoments])
+                                         const double *g3w, const double D[3], int a, double r, int it,
+                                         double m[kMoments])
 {
+    const double Ra = a * r, Rb = (a + 1) * r, inv_r = 1.0 / r;
     const int iq = it % nq;
     const int rest = it / nq;
     const int iv = rest % 5;
@@ -283,9 +298,9 @@ __host__ __device__ __attribute__((always_inline)) inline void gen_item(int nq, 
     const int ax = sq / 12, rem = sq % 12;
     const int s = rem / 4 - 1;
     const int s1 = (rem & 1) ? 1 : -1, s2 = (rem & 2) ? 1 : -1;
-    if (ax == 0) gen_square<0>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
-    else if (ax == 1) gen_square<1>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
-    else gen_square<2>(nq, glx, glw, g3x, g3w, D, a, s, s1, s2, iv, iq, m);
+    if (ax == 0) gen_square<0>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    else if (ax == 1) gen_square<1>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    else gen_square<2>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
 }
 
 __device__ inline double wave_sum(double v)
@@ -301,8 +316,8 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict_
     const int dx = idx % ga.Uo, dy = (idx / ga.Uo) % ga.Vo, dz = idx / (ga.Uo * ga.Vo);
     const double D[3] = {(double)dx, (double)dy, (double)dz};
     int a_lo, nsh;
-    shell_range(dx, dy, dz, a_lo, nsh);
-    double *out = mom + (size_t)idx * kMaxShells * kMoments;
+    shell_range(dx, dy, dz, ga.r, a_lo, nsh);
+    double *out = mom + (size_t)idx * ga.ms * kMoments;
     const int nq = ga.nq;
     __shared__ double glx[kMaxQ], glw[kMaxQ], g3x[3], g3w[3];
     for (int i = threadIdx.x; i < kMaxQ; i += kGenThreads) {
@@ -315,13 +330,14 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict_
     }
     __syncthreads();
     const int nitems = gen_items(nq);
-    for (int sh = 0; sh < kMaxShells; sh++) {
+    const double r = ga.r;
+    for (int sh = 0; sh < ga.ms; sh++) {
         double m[kMoments];
 #pragma unroll
         for (int i = 0; i < kMoments; i++) m[i] = 0.0;
         const int a = a_lo + sh;
         if (sh < nsh) {
-            for (int it = threadIdx.x; it < nitems; it += kGenThreads) gen_item(nq, glx, glw, g3x, g3w, D, a, it, m);
+            for (int it = threadIdx.x; it < nitems; it += kGenThreads) gen_item(nq, glx, glw, g3x, g3w, D, a, r, it, m);
         }
 #pragma unroll
         for (int i = 0; i < kMoments; i++) {
@@ -332,12 +348,15 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict_
 }
 
 // K_k at an octant offset >= 0 from the moments of its shells a_lo .. a_lo + nsh - 1.
-__host__ __device__ inline void kernel_from_shells(const double *mom_d, int a_lo, int nsh, int k, double K[6])
+__host__ __device__ inline void kernel_from_shells(const double *mom_d, int a_lo, int nsh, int k, double r,
+                                                   double K[6])
 {
     for (int i = 0; i < 6; i++) K[i] = 0.0;
-    // B(k+1-|d|) on shell k-p as a quadratic in v = |d| - a:  p=0: (1-v)^2/2, p=1: (1+2v-2v^2)/2, p=2: v^2/2
+    // B(k+1-|d|/r) on shell k-p as a quadratic in v = |d|/r - a:  p=0: (1-v)^2/2, p=1: (1+2v-2v^2)/2,
+    // p=2: v^2/2; the time derivatives bring B'' / r^2
     const double cg[3][3] = {{0.5, -1.0, 0.5}, {0.5, 1.0, -1.0}, {0.0, 0.0, 0.5}};
-    const double cb[3] = {1.0, -2.0, 1.0};  // B'' on the three pieces
+    const double ir2 = 1.0 / (r * r);
+    const double cb[3] = {ir2, -2.0 * ir2, ir2};  // B'' on the three pieces
     for (int p = 0; p < 3; p++) {
         int sh = k - p - a_lo;
         if (sh < 0 || sh >= nsh) continue;
@@ -351,23 +370,29 @@ __host__ __device__ inline void kernel_from_shells(const double *mom_d, int a_lo
 }
 
 // K_k at integer octant offset (dx,dy,dz) >= 0 from the shell moments.
-__host__ __device__ inline void kernel_from_moments(const double *mom_d, int dx, int dy, int dz, int k, double K[6])
+__host__ __device__ inline void kernel_from_moments(const double *mom_d, int dx, int dy, int dz, int k, double r,
+                                                    double K[6])
 {
     int a_lo, nsh;
-    shell_range(dx, dy, dz, a_lo, nsh);
-    kernel_from_shells(mom_d, a_lo, nsh, k, K);
+    shell_range(dx, dy, dz, r, a_lo, nsh);
+    kernel_from_shells(mom_d, a_lo, nsh, k, r, K);
     // exact zeros of the odd components on their symmetry planes
     if (dx == 0 || dy == 0) K[3] = 0.0;
     if (dx == 0 || dz == 0) K[4] = 0.0;
     if (dy == 0 || dz == 0) K[5] = 0.0;
 }
 
-__device__ inline void kernel_at(const double *mom, int Uo, int Vo, int Wo, int k, int Dx, int Dy, int Dz,
-                                 double K[6])
+struct MomView {
+    const double *mom;   // [Wo][Vo][Uo][ms][kMoments]
+    int Uo, Vo, Wo, ms;
+    double r;
+};
+
+__device__ inline void kernel_at(const MomView &g, int k, int Dx, int Dy, int Dz, double K[6])
 {
     int ax = Dx < 0 ? -Dx : Dx, ay = Dy < 0 ? -Dy : Dy, az = Dz < 0 ? -Dz : Dz;
-    const double *md = mom + ((size_t)(az * Vo + ay) * Uo + ax) * kMaxShells * kMoments;
-    kernel_from_moments(md, ax, ay, az, k, K);
+    const double *md = g.mom + ((size_t)(az * g.Vo + ay) * g.Uo + ax) * g.ms * kMoments;
+    kernel_from_moments(md, ax, ay, az, k, g.r, K);
     double sx = Dx < 0 ? -1.0 : 1.0, sy = Dy < 0 ? -1.0 : 1.0, sz = Dz < 0 ? -1.0 : 1.0;
     K[3] *= sx * sy;
     K[4] *= sx * sz;
@@ -376,9 +401,9 @@ __device__ inline void kernel_at(const double *mom, int Uo, int Vo, int Wo, int 
 
 // Periodic embedding on the Nx x Ny x Nz grid: index i holds offset i (i < U) or i - N
 // (i > N - U); the remaining indices are zero (Appendix A, first column of the circulant).
-__global__ void k_kernel_grid(const double *__restrict__ mom, int Uo, int Vo, int Wo, int k, int Nx, int Ny, int Nz,
-                              double *__restrict__ grid)
+__global__ void k_kernel_grid(MomView g, int k, int Nx, int Ny, int Nz, double *__restrict__ grid)
 {
+    const int Uo = g.Uo, Vo = g.Vo, Wo = g.Wo;
     size_t n = (size_t)Nx * Ny * Nz;
     size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -387,24 +412,24 @@ __global__ void k_kernel_grid(const double *__restrict__ mom, int Uo, int Vo, in
     int Dy = iy < Vo ? iy : (iy > Ny - Vo ? iy - Ny : INT32_MAX);
     int Dz = iz < Wo ? iz : (iz > Nz - Wo ? iz - Nz : INT32_MAX);
     double K[6] = {0, 0, 0, 0, 0, 0};
-    if (Dx != INT32_MAX && Dy != INT32_MAX && Dz != INT32_MAX) kernel_at(mom, Uo, Vo, Wo, k, Dx, Dy, Dz, K);
+    if (Dx != INT32_MAX && Dy != INT32_MAX && Dz != INT32_MAX) kernel_at(g, k, Dx, Dy, Dz, K);
     for (int c = 0; c < 6; c++) grid[c * n + i] = K[c];
 }
 
-__global__ void k_kernel_values(const double *__restrict__ mom, int Uo, int Vo, int Wo, int n,
-                                const int *__restrict__ lag, const int *__restrict__ off, double *__restrict__ out)
+__global__ void k_kernel_values(MomView g, int n, const int *__restrict__ lag, const int *__restrict__ off,
+                                double *__restrict__ out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double K[6];
-    kernel_at(mom, Uo, Vo, Wo, lag[i], off[3 * i], off[3 * i + 1], off[3 * i + 2], K);
+    kernel_at(g, lag[i], off[3 * i], off[3 * i + 1], off[3 * i + 2], K);
     for (int c = 0; c < 6; c++) out[6 * i + c] = K[c];
 }
 
 // ---------------------------------------------------------------------------- off-grid offsets
 // Shell range for a real octant offset D >= 0 (the distances between points of the two
 // voxels lie in [|max(D - 1, 0)|, |D + 1|]).
-__host__ __device__ inline void shell_range_real(const double D[3], int &a_lo, int &nsh)
+__host__ __device__ inline void shell_range_real(const double D[3], double r, int &a_lo, int &nsh)
 {
     double a2 = 0.0, b2 = 0.0;
     for (int i = 0; i < 3; i++) {
@@ -412,10 +437,8 @@ __host__ __device__ inline void shell_range_real(const double D[3], int &a_lo, i
         a2 += e * e;
         b2 += (D[i] + 1.0) * (D[i] + 1.0);
     }
-    a_lo = (int)floor(sqrt(a2));
-    int hi = (int)ceil(sqrt(b2));
-    nsh = hi - a_lo;
-    if (nsh > kMaxShells) nsh = kMaxShells;   // cannot happen: R_max - R_min <= 2 sqrt 3
+    shell_bounds(a2, b2, r, a_lo, nsh);
+    if (nsh > kShellCap) nsh = kShellCap;   // cannot happen for r >= kMinCdtOverH
 }
 
 // K_k for k = kmin .. kmin + nw - 1 at the signed real offset Ds, serially (host checks and
@@ -444,6 +467,7 @@ struct OffgridArg {
     const int *pair_vox;      // [npairs] source voxel, linear index u + U (v + V w)
     const int *pair_kmin;     // [npairs] first lag of the window
     int U, V;
+    double r;                 // c dt / h
     int nw;                   // lags per pair
     int kmax;                 // lags above kmax are stored as zero
     long npairs;
@@ -461,10 +485,10 @@ __global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, Ge
     double D[3], sg[3];
     fold_offset(Ds, D, sg);
     int a_lo, nsh;
-    shell_range_real(D, a_lo, nsh);
+    shell_range_real(D, oa.r, a_lo, nsh);
     const int nq = ga.nq;
     __shared__ double glx[kMaxQ], glw[kMaxQ], g3x[3], g3w[3];
-    __shared__ double mom[kMaxShells * kMoments];
+    __shared__ double mom[kShellCap * kMoments];
     for (int t = threadIdx.x; t < kMaxQ; t += kGenThreads) {
         glx[t] = ga.glx[t];
         glw[t] = ga.glw[t];
@@ -479,7 +503,8 @@ __global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, Ge
         double m[kMoments];
 #pragma unroll
         for (int t = 0; t < kMoments; t++) m[t] = 0.0;
-        for (int it = threadIdx.x; it < nitems; it += kGenThreads) gen_item(nq, glx, glw, g3x, g3w, D, a_lo + sh, it, m);
+        for (int it = threadIdx.x; it < nitems; it += kGenThreads)
+            gen_item(nq, glx, glw, g3x, g3w, D, a_lo + sh, oa.r, it, m);
 #pragma unroll
         for (int t = 0; t < kMoments; t++) {
             const double s_ = wave_sum(m[t]);
@@ -491,7 +516,7 @@ __global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, Ge
         const int k = oa.pair_kmin[i] + wl;
         double K[6] = {0, 0, 0, 0, 0, 0};
         if (k <= oa.kmax) {
-            kernel_from_shells(mom, a_lo, nsh, k, K);
+            kernel_from_shells(mom, a_lo, nsh, k, oa.r, K);
             finish_offgrid(D, sg, K);
         }
         double *o = oa.out + ((long)wl * oa.npairs + i) * 6;
@@ -534,21 +559,26 @@ void legendre_rule(int n, double *x, double *w)
 
 }  // namespace
 
-void gen_moments(GenResult &g, int U, int V, int W, int nquad, hipStream_t st)
+void gen_moments(GenResult &g, int U, int V, int W, double r, int nquad, hipStream_t st)
 {
     if (nquad < 4 || nquad > kMaxQ) throw ArgError("quad_order must be in [4, 24]");
+    if (!(r >= kMinCdtOverH && r <= 1.0)) throw ArgError("c dt / h must be in [0.3, 1]");
     GenArg ga{};
     ga.Uo = U;
     ga.Vo = V;
     ga.Wo = W;
     ga.nq = nquad;
+    ga.r = r;
+    ga.ms = shells_per_offset(r);
     legendre_rule(nquad, ga.glx, ga.glw);
     legendre_rule(3, ga.g3x, ga.g3w);
     g.Uo = U;
     g.Vo = V;
     g.Wo = W;
+    g.ms = ga.ms;
+    g.r = r;
     size_t noff = (size_t)U * V * W;
-    size_t bytes = noff * kMaxShells * kMoments * sizeof(double);
+    size_t bytes = noff * g.ms * kMoments * sizeof(double);
     if (hipMalloc(&g.moments, bytes) != hipSuccess) throw MemError("kernel moments");
     MJ_CHECK(hipMemsetAsync(g.moments, 0, bytes, st));
     hipLaunchKernelGGL(k_gen_moments, dim3((unsigned)noff), dim3(kGenThreads), 0, st, g.moments, ga);
@@ -559,7 +589,8 @@ void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *
 {
     size_t n = (size_t)Nx * Ny * Nz;
     dim3 blk(256), grd((unsigned)((n + 255) / 256));
-    hipLaunchKernelGGL(k_kernel_grid, grd, blk, 0, st, g.moments, g.Uo, g.Vo, g.Wo, k, Nx, Ny, Nz, grid);
+    const MomView mv{g.moments, g.Uo, g.Vo, g.Wo, g.ms, g.r};
+    hipLaunchKernelGGL(k_kernel_grid, grd, blk, 0, st, mv, k, Nx, Ny, Nz, grid);
     MJ_CHECK(hipGetLastError());
 }
 
@@ -567,16 +598,17 @@ void gen_kernel_values(const GenResult &g, int n, const int *lag_dev, const int 
                        hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_kernel_values, dim3((n + 127) / 128), dim3(128), 0, st, g.moments, g.Uo, g.Vo, g.Wo, n,
-                       lag_dev, off_dev, out_dev);
+    const MomView mv{g.moments, g.Uo, g.Vo, g.Wo, g.ms, g.r};
+    hipLaunchKernelGGL(k_kernel_values, dim3((n + 127) / 128), dim3(128), 0, st, mv, n, lag_dev, off_dev, out_dev);
     MJ_CHECK(hipGetLastError());
 }
 
 void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const int *pair_vox_dev,
-                       const int *pair_kmin_dev, long npairs, int U, int V, int nw, int kmax, int nquad,
+                       const int *pair_kmin_dev, long npairs, int U, int V, double r, int nw, int kmax, int nquad,
                        double *out_dev, hipStream_t st)
 {
     if (npairs <= 0) return;
+    if (!(r >= kMinCdtOverH && r <= 1.0)) throw ArgError("c dt / h must be in [0.3, 1]");
     if (nquad < 4 || nquad > kMaxQ) throw ArgError("quad_order must be in [4, 24]");
     if (npairs > 0x7fffffffL) throw ArgError("too many probe pairs");
     GenArg ga{};
@@ -590,6 +622,7 @@ void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const i
     oa.pair_kmin = pair_kmin_dev;
     oa.U = U;
     oa.V = V;
+    oa.r = r;
     oa.nw = nw;
     oa.kmax = kmax;
     oa.npairs = npairs;

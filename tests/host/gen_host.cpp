@@ -4,8 +4,8 @@
 #include "../../paper_2407_03323_amd/csrc/mj_gen.hip"
 
 namespace mj {
-// K_k(D) for k = 0..kmax at a real offset D (units of h), nq-point rule
-extern "C" void host_kernels(double Dx, double Dy, double Dz, int nq, int kmax, double *out)
+// K_k(D) for k = 0..kmax at a real offset D (units of h), c dt = r h, nq-point rule
+extern "C" void host_kernels(double Dx, double Dy, double Dz, double r, int nq, int kmax, double *out)
 {
     GenArg ga{};
     ga.nq = nq;
@@ -15,13 +15,13 @@ extern "C" void host_kernels(double Dx, double Dy, double Dz, int nq, int kmax, 
     double D[3], sg[3];
     fold_offset(Ds, D, sg);
     int a_lo, nsh;
-    shell_range_real(D, a_lo, nsh);
-    double mom[kMaxShells * kMoments] = {0};
+    shell_range_real(D, r, a_lo, nsh);
+    double mom[kShellCap * kMoments] = {0};
     for (int sh = 0; sh < nsh; sh++)
         for (int it = 0; it < gen_items(nq); it++)
-            gen_item(ga.nq, ga.glx, ga.glw, ga.g3x, ga.g3w, D, a_lo + sh, it, mom + sh * kMoments);
+            gen_item(ga.nq, ga.glx, ga.glw, ga.g3x, ga.g3w, D, a_lo + sh, r, it, mom + sh * kMoments);
     for (int k = 0; k <= kmax; k++) {
-        kernel_from_shells(mom, a_lo, nsh, k, out + 6 * k);
+        kernel_from_shells(mom, a_lo, nsh, k, r, out + 6 * k);
         finish_offgrid(D, sg, out + 6 * k);
     }
 }

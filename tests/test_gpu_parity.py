@@ -641,6 +641,84 @@ def test_full_size_104_sampled(torch_cuda):
     s.close()
 
 
+# ----------------------------------------------------------------------------- c dt < h
+@pytest.mark.parametrize("UVW,r", [((5, 4, 4), 0.5), ((4, 3, 3), 0.3)])
+def test_short_step_generator_matches_oracle(torch_cuda, UVW, r):
+    """c dt = r h < h: every K_k(D) of the grid (all offsets, k = 0..ell) against the oracle."""
+    from oracle import mot
+    U, V, W = UVW
+    say("generator c dt = %g h, %dx%dx%d" % (r, U, V, W))
+    ell = mot.ell(U, V, W, 1.0, r)
+    prob = wl.Problem("short-step", U, V, W, wl.random_eps(U, V, W, 3, 2.0, 5.0), [], 1, c_dt=r)
+    s = make_solver(prob)
+    assert s.ell == ell
+    Ko = oracle_kernel_table(U, V, W, ell, r=r)
+    r_ = [np.arange(-(n - 1), n) for n in (U, V, W)]
+    dz, dy, dx = np.meshgrid(r_[2], r_[1], r_[0], indexing="ij")
+    offs = np.stack([dx.ravel(), dy.ravel(), dz.ravel()], axis=1)
+    worst = 0.0
+    for k in range(ell + 1):
+        got = s.kernel_values(np.full(len(offs), k), offs)
+        ref = np.stack([Ko[k, c][offs[:, 2] + W - 1, offs[:, 1] + V - 1, offs[:, 0] + U - 1] for c in range(6)], axis=1)
+        worst = max(worst, np.abs(got - ref).max() / np.abs(Ko).max())
+    say("  ell", ell, "worst / max|K|", worst)
+    assert worst <= 1e-12
+    s.close()
+
+
+def test_short_step_march_and_probes_match_oracle(torch_cuda):
+    """A 5 x 4 x 4 heterogeneous block marched at c dt = h/2 with a 3-tap FIR, time blocks of 8,
+    and the scattered field at six probes: J and E^s against the oracle's march and probe sum."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n, r = 5, 4, 4, 80, 0.5
+    say("march + probes c dt = h/2, 5x4x4")
+    eps = wl.random_eps(U, V, W, 31, 2.0, 9.0)
+    eps[0, 0, 0] = 1.0
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("short-step", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1), c_dt=r)
+    probes = np.concatenate([wl.fibonacci_sphere(5, 5.0, (U / 2, V / 2, W / 2)), np.array([[2.5, 1.5, 2.5]])])
+    ell = mot.ell(U, V, W, 1.0, r)
+    K = oracle_kernel_table(U, V, W, ell, r=r)
+    J = mot.Oracle(prob, K=K).run(n)
+    src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U) if eps[w, v, u] != 1.0]
+    ref = mot.probe_field(mot.probe_kernels(probes, src, ell, r=r), J, src)
+    s = make_solver(prob, time_block=8)
+    s.set_probes(probes)
+    Jt = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    Pt = torch.zeros((n, 1, len(probes), 3), dtype=torch.float64, device="cuda")
+    s.run(n, Jt, Pt)
+    torch.cuda.synchronize()
+    eJ = _rel(Jt.cpu().numpy()[:, 0], J)
+    eP = _rel(Pt.cpu().numpy()[:, 0], ref)
+    say("  ell", s.ell, "J rel L2", eJ, "probe rel L2", eP, "cg iters", s.stats()["cg_iters"])
+    assert s.ell == ell
+    assert eJ <= 1e-8 and eP <= 1e-8
+    s.close()
+
+
+def test_short_step_adjoint_gradient_matches_oracle(torch_cuda):
+    """The transposed march and the eps-gradient at c dt = h/2 (5 x 4 x 3, checkpoints every 9)."""
+    from oracle import mot
+    torch = torch_cuda
+    prob, probes = _adjoint_case()
+    prob.c_dt = 0.5
+    say("adjoint c dt = h/2, 5x4x3")
+    K = oracle_kernel_table(prob.U, prob.V, prob.W, mot.ell(prob.U, prob.V, prob.W, 1.0, 0.5), r=0.5)
+    phi_ref, grad_ref, _ = mot.Oracle(prob, K=K).probe_objective_gradient(prob.n_steps, probes)
+    s = make_solver(prob, time_block=8)
+    s.set_probes(probes)
+    g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    phi = s.adjoint_gradient(prob.n_steps, g, 9)
+    torch.cuda.synchronize()
+    e_phi = abs(phi - phi_ref) / abs(phi_ref)
+    e_g = _rel(g.cpu().numpy(), grad_ref)
+    say("  phi rel", e_phi, "grad rel L2", e_g)
+    assert e_phi <= 1e-10 and e_g <= 1e-8
+    s.close()
+
+
 # ----------------------------------------------------------------------------- degenerate cases
 @pytest.mark.parametrize("UVW", [(1, 1, 1), (7, 1, 1), (1, 5, 2), (3, 3, 1)])
 def test_march_degenerate_grids(torch_cuda, UVW):

@@ -605,3 +605,124 @@ def test_adjoint_gradient_local_form():
     eps = prob.eps
     ref = (lam * loc).sum(axis=(0, 1)) / (eps * (eps - 1.0))
     assert np.abs(ref - grad).max() < 1e-9 * np.abs(grad).max()
+
+
+# ----------------------------------------------------------------------------- c dt < h
+# The same identities at c dt = r h, r < 1: the time basis is a partition of unity at any step,
+# so the lag sum is still the static kernel; the moment identities carry the step through
+# s = R / (c dt) (sum_k k^2 T(k dt - R/c) = s^2 + s + 1/2 gives the 1/r^2 on the second moment).
+SHORT = [0.5, 0.7, 0.3]
+
+
+def kernel_lags_r(D, r, extra=2):
+    _, b = lag_window(D)
+    kmax = int(np.floor(b / r)) + 2 + extra
+    return np.array([mot.kernel_entry(k, D, r=r) for k in range(kmax + 1)])
+
+
+@pytest.mark.parametrize("r", SHORT)
+@pytest.mark.parametrize("D", [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 1, 0), (3, 1, -2)])
+def test_short_step_static_sum_equals_newell(D, r):
+    Ks = kernel_lags_r(D, r)
+    assert np.abs(Ks.sum(0) + pins.newell_tensor(D)).max() < 5e-14
+
+
+@pytest.mark.parametrize("r", SHORT[:2])
+@pytest.mark.parametrize("D", [(1, 0, 0), (1, 1, 1), (3, 2, 2), (5, 3, 2)])
+def test_short_step_first_moment(D, r):
+    Ks = kernel_lags_r(D, r)
+    k = np.arange(len(Ks))[:, None]
+    assert np.abs((k * Ks).sum(0) - 0.5 * Ks.sum(0)).max() < 1e-11 * np.abs(Ks).max()
+
+
+@pytest.mark.parametrize("r", SHORT[:2])
+@pytest.mark.parametrize("D", [(3, 2, 2), (5, 3, 2), (-6, 0, 0)])
+def test_short_step_second_moment_far_field(D, r):
+    """sum_k k^2 K_k = -N/2 - (1/r^2) Int (d_ab + dhat_a dhat_b)/(4 pi R) Lam(d - D) dd."""
+    Ks = kernel_lags_r(D, r)
+    k = np.arange(len(Ks))[:, None]
+    static = pins.overlap_gl(D, pins.static_second_derivative)
+    ref = 0.5 * static - pins.overlap_gl(D, pins.second_moment_integrand) / (r * r)
+    assert np.abs((k ** 2 * Ks).sum(0) - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("r", SHORT)
+def test_short_step_support_and_stencil(r):
+    """K_k(D) vanishes unless (k - 2, k + 1) r meets [R_min, R_max]; for r <= 1 K_0 stays on the
+    27-point stencil; the farthest pair of an 8^3 grid reaches the last lag of eq:Ell."""
+    for D in [(0, 0, 0), (1, 1, 1), (2, 0, 0), (3, 2, 1)]:
+        Ks = kernel_lags_r(D, r, extra=3)
+        a, b = lag_window(D)
+        scale = np.abs(Ks).max()
+        for k in range(len(Ks)):
+            if not ((k + 1) * r > a and (k - 2) * r < b):
+                assert np.abs(Ks[k]).max() < 1e-13 * scale + 1e-15
+    for D in [(1, 1, 1), (1, 0, 1), (0, 0, 0)]:
+        assert np.abs(mot.kernel_entry(0, D, r=r)).max() > 1e-6
+    for D in [(2, 0, 0), (2, 1, 1), (0, 2, 2)]:
+        assert np.abs(mot.kernel_entry(0, D, r=r)).max() < 1e-15
+    L = mot.ell(8, 8, 8, 1.0, r)
+    assert L == int(np.floor(8 * sqrt(3) / r)) + 2
+    Dfar = (7, 7, 7)
+    assert np.abs(mot.kernel_entry(L, Dfar, r=r)).max() > 1e-12
+    assert np.abs(mot.kernel_entry(L + 1, Dfar, r=r)).max() < 1e-15
+
+
+def test_short_step_excitation_axis_wave_closed_form():
+    """c n dt = n r in the retarded time of the voxel average."""
+    r = 0.5
+    p = wl.homogeneous_cube(4, 5.0, 10, 4.0)
+    wave = p.waves[0]
+    for n in (3, 24, 41, 55):
+        E = mot.excitation(4, 4, 4, p.eps, wave, n, r=r)
+        for w in range(4):
+            tc = n * r - wave.t0 - (w + 0.5)
+            ref = 0.8 * wave.amp * pins.axis_wave_voxel_average(tc, wave.width)
+            assert np.allclose(E[0, w], ref, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("r", [0.5, 0.8])
+def test_short_step_one_voxel_clausius_mossotti(r):
+    eps = 6.0
+    p = wl.homogeneous_cube(1, eps, 10, 4.0)
+    p.c_dt = r
+    J = mot.Oracle(p).run(600, excite=_constant_excitation(p, (1.0, 0.0, 0.0)))
+    assert abs(J[-1, 0, 0, 0, 0] - 3 * (eps - 1) / (eps + 2)) < 1e-12
+
+
+@pytest.mark.slow
+def test_short_step_steady_state_against_newell():
+    """The 3^3 block of the c dt = h test at c dt = h/2: the static limit does not depend on dt."""
+    U = 3
+    eps = wl.random_eps(U, U, U, 7, 2.0, 6.0)
+    p = wl.Problem("ss", U, U, U, eps, [], 10, fir=np.zeros(0), c_dt=0.5)
+    o = mot.Oracle(p)
+    E0 = np.array([1.0, 0.5, -0.25])
+    const = _constant_excitation(p, E0)
+    J = o.run(1200, excite=lambda n: const(n) * 0.5 * (1.0 + erf((n - 200.0) / 24.0)))
+    M = U ** 3
+    chi = mot.chi_of(eps).ravel()
+    A = np.zeros((3 * M, 3 * M))
+    coords = [(u, v, w) for w in range(U) for v in range(U) for u in range(U)]
+    for i, ci in enumerate(coords):
+        for j, cj in enumerate(coords):
+            N = pins.newell_tensor(tuple(ci[t] - cj[t] for t in range(3)))
+            for b in range(3):
+                for a in range(3):
+                    A[b * M + i, a * M + j] += chi[i] * N[mot.COMP[b][a]]
+    for b in range(3):
+        A[b * M:(b + 1) * M, b * M:(b + 1) * M] += np.diag(1.0 / eps.ravel())
+    rhs = np.concatenate([chi * E0[b] for b in range(3)])
+    Jinf = np.linalg.solve(A, rhs)
+    assert np.abs(J[-1].reshape(-1) - Jinf).max() < 1e-10 * np.abs(Jinf).max()
+
+
+def test_short_step_time_shift_invariance():
+    p = wl.homogeneous_cube(3, 6.0, 80, 3.0)
+    p.c_dt = 0.5
+    p.waves[0].t0 = 30.0
+    o = mot.Oracle(p)
+    J1 = o.run(140)
+    p.waves[0].t0 += 2.5            # five steps of c dt = 1/2
+    J2 = o.run(140)
+    assert np.abs(J2[5:] - J1[:-5]).max() < 1e-13 * np.abs(J1).max()
