@@ -17,12 +17,13 @@
  * Z_k -> Z_k + delta_k I (Sec. 6.1) built in.
  *
  * Conventions
- *  - Lengths in any unit; h is the voxel edge.  Times enter as c*t (same unit).
- *    c*dt may be any value in [0.3 h, h]: the paper's choice dt = dx/c (Sec. 5.2) is the
- *    largest; up to it K_0 stays on the 27 nearest offsets, which the Z_0 solve assumes.
- *    Smaller steps add lags (eq:Ell) and kernel work in proportion to h / (c dt).
+ *  - Lengths in any unit; voxels are h x hy x hz (Sec. 2.2: dx, dy, dz; hy = hz = h by
+ *    default).  Times enter as c*t (same unit).  c*dt may be any value in
+ *    [0.3 max(h, hy, hz), min(h, hy, hz)]: the paper's choice dt = dx/c on cubic voxels
+ *    (Sec. 5.2) is the largest; up to it K_0 stays on the 27 nearest offsets, which the Z_0
+ *    solve assumes.  Smaller steps add lags (eq:Ell) and kernel work in proportion to h/(c dt).
  *  - Voxel index m = (w*V + v)*U + u, 0-based, x fastest (Sec. 2.2, 1-based there).
- *    Voxel (u,v,w) has its centre at ((u+1/2)h, (v+1/2)h, (w+1/2)h).
+ *    Voxel (u,v,w) has its centre at ((u+1/2)h, (v+1/2)hy, (w+1/2)hz).
  *  - Vector fields are stored per component: F[a][w][v][u], a = x,y,z (the paper's
  *    eq:CurrentVector interleaves the components per voxel; same numbers).
  *  - All arithmetic is IEEE binary64.
@@ -59,8 +60,8 @@ typedef struct mj_solver mj_solver;
 
 typedef struct {
     int32_t U, V, W;          /* voxels per axis (>= 1) */
-    double h;                 /* voxel edge (> 0) */
-    double c_dt;              /* c * dt, in [0.3 h, h]; MJ_EINVAL outside */
+    double h;                 /* voxel edge along x (> 0) */
+    double c_dt;              /* c * dt, in [0.3 max edge, min edge]; MJ_EINVAL outside */
     const double *eps_r;      /* host [W][V][U], relative permittivity >= 1, finite */
     const double *fir;        /* host taps delta_0..delta_{n_fir-1} (Sec. 6.1); may be NULL if n_fir == 0 */
     int32_t n_fir;            /* 0 = no regularisation */
@@ -73,6 +74,8 @@ typedef struct {
     int32_t fft_pencils;      /* pencils per block of the FFT passes: 0 = pick per pass by timing at
                                  mj_create; > 0 = at most this many (capped by what one LDS tile holds).
                                  The transforms are bit-identical for every choice. < 0: MJ_EINVAL */
+    double hy, hz;            /* voxel edges along y and z; 0 selects h.  Zero-initialise a config
+                                 written for cubic voxels and these keep it cubic */
 } mj_config;
 
 /*
@@ -126,11 +129,11 @@ int mj_run(mj_solver *s, int32_t n_steps, double *J_hist);
 /*
  * mj_set_probes -- points where the scattered field is sampled during the march.
  *   pos: host [n_probes][3], same length unit as h, origin at the grid corner (voxel
- *   (u, v, w) is centred at ((u + 1/2) h, (v + 1/2) h, (w + 1/2) h)); copied.  0 <= n_probes
+ *   (u, v, w) is centred at ((u + 1/2) h, (v + 1/2) hy, (w + 1/2) hz)); copied.  0 <= n_probes
  *   <= 65536; n_probes = 0 removes the probes.  Allowed only at n = 0 (after mj_create or
  *   mj_reset), else MJ_ESTATE.
  *   The field is the scattered-field operator of the formulation (Sec. 2.1) tested, like
- *   eq:Z, on a virtual voxel of side h centred at the probe (eps_0 = 1):
+ *   eq:Z, on a virtual voxel of the grid's shape centred at the probe (eps_0 = 1):
  *     E^s_p(n) = sum_{k=0}^{ell} sum_{m'} K_k(r_p - r_m') J_{n-k}(m')
  *   over the voxels m' with eps_r != 1.  (K is S(J) less its local part J, and the
  *   scattered field is S(J) - J, so no local term appears, inside the scatterer or not.)

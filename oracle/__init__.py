@@ -45,13 +45,17 @@ def lib():
                                       ctypes.c_double, ctypes.c_int, dp]
         L.or_kernel_table.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, dp]
+        L.or_kernel_entry_h.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, dp]
+        L.or_kernel_table_h.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, dp]
         L.or_conv.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
                               ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
         L.or_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         ip = ctypes.POINTER(ctypes.c_int)
-        L.or_conv_pairs.argtypes = [ctypes.c_double, ctypes.c_int, ip, ctypes.c_long, ip, ctypes.c_long, dp,
+        L.or_conv_pairs.argtypes = [ctypes.c_double, dp, ctypes.c_int, ip, ctypes.c_long, ip, ctypes.c_long, dp,
                                     ctypes.c_int, dp]
-        L.or_probe_kernels.argtypes = [ctypes.c_double, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_long,
+        L.or_probe_kernels.argtypes = [ctypes.c_double, dp, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_long,
                                        ctypes.c_int, dp]
         L.or_box_integrals.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]

@@ -12,19 +12,21 @@
  *
  *   Z^{ba}_{m,m',k} = d_ab d_mm' T(k dt)/eps_m - chi_m K^{ba}_k(D),   D = r_m - r_m'
  *
- *   K^{ba}_k(D) = (1/h^3) [ Int g_k(d) d_a d_b Lam(d - D) dd
- *                           - d_ab c^-2 Int gbar_k(d) Lam(d - D) dd ]
+ *   K^{ba}_k(D) = (1/(hx hy hz)) [ Int g_k(d) d_a d_b Lam(d - D) dd
+ *                                  - d_ab c^-2 Int gbar_k(d) Lam(d - D) dd ]
  *
  *   g_k(d)    = T(k dt - |d|/c) / (4 pi |d|),   gbar_k(d) = T''(k dt - |d|/c) / (4 pi |d|)
- *   Lam(x)    = prod_i (h - |x_i|)_+   (overlap volume of two voxels at offset x)
+ *   Lam(x)    = prod_i (h_i - |x_i|)_+   (overlap volume of two voxels at offset x)
  *
  * The curl-curl of the retarded potential is split with grad(div) - Laplacian
  * and the wave equation, and both spatial derivatives are moved onto Lam
  * (distributional derivatives):
  *   a != b : d_a d_b Lam = lam'(x_a) lam'(x_b) lam(x_c)  -- bounded, cube integrals
- *   a == b : d_a^2 lam   = delta(s+h) - 2 delta(s) + delta(s-h) -- plane integrals
+ *   a == b : d_a^2 lam   = (delta(s+h_a) - 2 delta(s) + delta(s-h_a)) / h_a -- plane integrals
+ * with lam(x) = 1 - |x|/h_i per axis (Lam / (hx hy hz) = prod_i lam(x_i)).
  *
- * Units: h = 1 (lengths in voxel edges), r = c dt / h.  K is dimensionless.
+ * Units: lengths in the unit of h = (hx, hy, hz) (1, 1, 1 for cubic voxels), r = c dt in the
+ * same unit; offsets D are given in voxel steps per axis.  K is dimensionless.
  *
  * Quadrature (every integrand is analytic between the spheres |d| = knot radius):
  *  - a cube integral of F = phi(|d|) P(d) (P polynomial) is turned into face
@@ -98,9 +100,10 @@ double or_bspline(double x) { return bspl(x); }
 /* Oracle context for one lag k and one offset D.                             */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    double r;          /* c dt / h */
+    double r;          /* c dt */
     int k;             /* lag */
-    double D[3];       /* offset in voxel units */
+    double h[3];       /* voxel edges */
+    double D[3];       /* offset as a length: voxel steps times h */
     int ngl;
     double glx[MAXGL], glw[MAXGL];
     double g4x[4], g4w[4];
@@ -116,8 +119,8 @@ static double radial_u2(const octx *o, int kind, double u)
     return bspl2(x) * u / (4.0 * M_PI * o->r * o->r);
 }
 
-/* Sub-box polynomial weights.  Box sign s[i] = +1 for [D_i, D_i+1], -1 for [D_i-1, D_i].
- * lam(x) = 1 - |x| = 1 - s (x) on the box;  lam'(x) = -sign(x) = -s.  */
+/* Sub-box polynomial weights.  Box sign s[i] = +1 for [D_i, D_i+h_i], -1 for [D_i-h_i, D_i].
+ * lam(x) = 1 - |x|/h_i = 1 - s x / h_i on the box;  lam'(x) = -s / h_i.  */
 typedef struct { int s[3]; } boxw;
 
 /* wfun: 0 = Lam = lam lam lam;  1 = xy: lam' lam' lam;  2 = xz;  3 = yz */
@@ -125,8 +128,8 @@ static double box_weight(const octx *o, const boxw *b, int wfun, const double p[
 {
     double l[3], dl[3];
     for (int i = 0; i < 3; i++) {
-        l[i] = 1.0 - b->s[i] * (p[i] - o->D[i]);
-        dl[i] = -(double)b->s[i];
+        l[i] = 1.0 - b->s[i] * (p[i] - o->D[i]) / o->h[i];
+        dl[i] = -(double)b->s[i] / o->h[i];
     }
     switch (wfun) {
     case 0: return l[0] * l[1] * l[2];
@@ -190,8 +193,8 @@ static int face_integrand(const fctx *f, const double y[3], double v[4])
     if (ny <= 0.0) { v[0] = 0.0; return 1; }
     double x = o->k + 1.0 - ny / o->r;
     double g = bspl(x) / (4.0 * M_PI * ny);
-    double l1 = 1.0 - f->ps1 * (y[f->pa1] - o->D[f->pa1]);
-    double l2 = 1.0 - f->ps2 * (y[f->pa2] - o->D[f->pa2]);
+    double l1 = 1.0 - f->ps1 * (y[f->pa1] - o->D[f->pa1]) / o->h[f->pa1];
+    double l2 = 1.0 - f->ps2 * (y[f->pa2] - o->D[f->pa2]) / o->h[f->pa2];
     v[0] = g * l1 * l2;
     return 1;
 }
@@ -300,8 +303,8 @@ static void box_integrals(const octx *o, const boxw *b, double res[4])
 {
     double lo[3], hi[3];
     for (int i = 0; i < 3; i++) {
-        if (b->s[i] > 0) { lo[i] = o->D[i]; hi[i] = o->D[i] + 1.0; }
-        else { lo[i] = o->D[i] - 1.0; hi[i] = o->D[i]; }
+        if (b->s[i] > 0) { lo[i] = o->D[i]; hi[i] = o->D[i] + o->h[i]; }
+        else { lo[i] = o->D[i] - o->h[i]; hi[i] = o->D[i]; }
     }
     res[0] = res[1] = res[2] = res[3] = 0.0;
     for (int ax = 0; ax < 3; ax++) {
@@ -315,11 +318,14 @@ static void box_integrals(const octx *o, const boxw *b, double res[4])
     }
 }
 
-static void octx_init(octx *o, double r, int k, const double D[3], int ngl)
+static void octx_init(octx *o, double r, const double h[3], int k, const double D[3], int ngl)
 {
     o->r = r;
     o->k = k;
-    o->D[0] = D[0]; o->D[1] = D[1]; o->D[2] = D[2];
+    for (int i = 0; i < 3; i++) {
+        o->h[i] = h[i];
+        o->D[i] = D[i] * h[i];
+    }
     if (ngl < 2) ngl = 2;
     if (ngl > MAXGL) ngl = MAXGL;
     o->ngl = ngl;
@@ -329,25 +335,27 @@ static void octx_init(octx *o, double r, int k, const double D[3], int ngl)
 }
 
 /*
- * K_k(D) for one lag and one (real-valued) offset; out = {xx, yy, zz, xy, xz, yz}.
+ * K_k(D) for one lag and one (real-valued) offset D in voxel steps, voxel edges h, c dt = r;
+ * out = {xx, yy, zz, xy, xz, yz}.
  */
-void or_kernel_entry(double r, int k, double Dx, double Dy, double Dz, int ngl, double *out)
+void or_kernel_entry_h(double r, const double *h, int k, double Dx, double Dy, double Dz, int ngl, double *out)
 {
     octx o;
-    double D[3] = {Dx, Dy, Dz};
-    octx_init(&o, r, k, D, ngl);
+    const double Dv[3] = {Dx, Dy, Dz};
+    octx_init(&o, r, h, k, Dv, ngl);
+    const double *D = o.D;
     for (int i = 0; i < 6; i++) out[i] = 0.0;
 
-    /* a == b: second difference across the planes y_a = D_a + s, weights (1,-2,1) */
+    /* a == b: second difference across the planes y_a = D_a + s h_a, weights (1,-2,1)/h_a */
     for (int a = 0; a < 3; a++) {
         int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
         for (int s = -1; s <= 1; s++) {
-            double ws = (s == 0) ? -2.0 : 1.0;
-            double c = D[a] + s;
+            double ws = ((s == 0) ? -2.0 : 1.0) / h[a];
+            double c = D[a] + s * h[a];
             for (int s1 = -1; s1 <= 1; s1 += 2) {
                 for (int s2 = -1; s2 <= 1; s2 += 2) {
-                    double lo1 = s1 > 0 ? D[a1] : D[a1] - 1.0, hi1 = lo1 + 1.0;
-                    double lo2 = s2 > 0 ? D[a2] : D[a2] - 1.0, hi2 = lo2 + 1.0;
+                    double lo1 = s1 > 0 ? D[a1] : D[a1] - h[a1], hi1 = lo1 + h[a1];
+                    double lo2 = s2 > 0 ? D[a2] : D[a2] - h[a2], hi2 = lo2 + h[a2];
                     fctx f = {&o, 1, NULL, 0.0, a1, a2, s1, s2};
                     double v = 0.0;
                     face_quad(&f, a, c, lo1, hi1, lo2, hi2, 1, &v);
@@ -372,15 +380,24 @@ void or_kernel_entry(double r, int k, double Dx, double Dy, double Dz, int ngl, 
             }
 }
 
-/* Largest and smallest distance between points of two voxels at integer-or-real offset D. */
-static void offset_radii(const double D[3], double *rmin, double *rmax)
+static const double unit_h[3] = {1.0, 1.0, 1.0};
+
+/* Cubic voxels of edge 1, c dt = r. */
+void or_kernel_entry(double r, int k, double Dx, double Dy, double Dz, int ngl, double *out)
+{
+    or_kernel_entry_h(r, unit_h, k, Dx, Dy, Dz, ngl, out);
+}
+
+/* Largest and smallest distance between points of two voxels at integer-or-real offset D
+ * (voxel steps), edges h. */
+static void offset_radii(const double D[3], const double h[3], double *rmin, double *rmax)
 {
     double a = 0.0, b = 0.0;
     for (int i = 0; i < 3; i++) {
         double d = fabs(D[i]);
-        double m = d - 1.0 > 0.0 ? d - 1.0 : 0.0;
+        double m = d - 1.0 > 0.0 ? (d - 1.0) * h[i] : 0.0;
         a += m * m;
-        b += (d + 1.0) * (d + 1.0);
+        b += (d + 1.0) * (d + 1.0) * h[i] * h[i];
     }
     *rmin = sqrt(a);
     *rmax = sqrt(b);
@@ -392,7 +409,8 @@ static void offset_radii(const double D[3], double *rmin, double *rmax)
  * skip_outside != 0: entries whose lag window (r(k-2), r(k+1)) misses the
  * distance range of the two voxels are set to exactly 0 instead of computed.
  */
-void or_kernel_table(double r, int U, int V, int W, int kmax, int ngl, int skip_outside, double *K)
+void or_kernel_table_h(double r, const double *h, int U, int V, int W, int kmax, int ngl, int skip_outside,
+                       double *K)
 {
     long nx = 2L * U - 1, ny = 2L * V - 1, nz = 2L * W - 1;
     long noff = nx * ny * nz;
@@ -407,12 +425,17 @@ void or_kernel_table(double r, int U, int V, int W, int kmax, int ngl, int skip_
         int active = 1;
         if (skip_outside) {
             double rmin, rmax;
-            offset_radii(D, &rmin, &rmax);
+            offset_radii(D, h, &rmin, &rmax);
             if (!(r * (k + 1) > rmin && r * (k - 2) < rmax)) active = 0;
         }
-        if (active) or_kernel_entry(r, k, D[0], D[1], D[2], ngl, out);
+        if (active) or_kernel_entry_h(r, h, k, D[0], D[1], D[2], ngl, out);
         for (int c = 0; c < 6; c++) K[((long)k * 6 + c) * noff + rem] = out[c];
     }
+}
+
+void or_kernel_table(double r, int U, int V, int W, int kmax, int ngl, int skip_outside, double *K)
+{
+    or_kernel_table_h(r, unit_h, U, V, W, kmax, ngl, skip_outside, K);
 }
 
 /* Exposed for tests: Gauss-Legendre rule of this file. */
@@ -423,7 +446,7 @@ void or_box_integrals(double r, int k, double Dx, double Dy, double Dz, int sx, 
 {
     octx o;
     double D[3] = {Dx, Dy, Dz};
-    octx_init(&o, r, k, D, ngl);
+    octx_init(&o, r, unit_h, k, D, ngl);
     boxw b = {{sx, sy, sz}};
     box_integrals(&o, &b, out4);
 }
@@ -434,7 +457,7 @@ double or_plane_integral(double r, int k, double Dx, double Dy, double Dz, int a
 {
     octx o;
     double D[3] = {Dx, Dy, Dz};
-    octx_init(&o, r, k, D, ngl);
+    octx_init(&o, r, unit_h, k, D, ngl);
     int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
     double lo1 = s1 > 0 ? D[a1] : D[a1] - 1.0, hi1 = lo1 + 1.0;
     double lo2 = s2 > 0 ? D[a2] : D[a2] - 1.0, hi2 = lo2 + 1.0;

@@ -28,9 +28,15 @@ from . import dptr, iptr, lib
 COMP = ((0, 3, 4), (3, 1, 5), (4, 5, 2))
 
 
-def ell(U: int, V: int, W: int, h: float = 1.0, c_dt: float = 1.0) -> int:
-    """Number of non-zero lags beyond Z_0 (eq:Ell)."""
-    return int(floor(sqrt((U * h) ** 2 + (V * h) ** 2 + (W * h) ** 2) / c_dt)) + 2
+def ell(U: int, V: int, W: int, h: float = 1.0, c_dt: float = 1.0, hy=None, hz=None) -> int:
+    """Number of non-zero lags beyond Z_0 (eq:Ell); voxel edges h, hy, hz (default h)."""
+    hy = h if hy is None else hy
+    hz = h if hz is None else hz
+    return int(floor(sqrt((U * h) ** 2 + (V * hy) ** 2 + (W * hz) ** 2) / c_dt)) + 2
+
+
+def _edges(hv) -> np.ndarray:
+    return np.ascontiguousarray(np.ones(3) if hv is None else np.asarray(hv, dtype=np.float64).reshape(3))
 
 
 def tbasis(t_over_dt: float) -> float:
@@ -39,17 +45,18 @@ def tbasis(t_over_dt: float) -> float:
     return lib().or_bspline(float(t_over_dt) + 1.0)
 
 
-def kernel_entry(k: int, D, ngl: int = 16, r: float = 1.0) -> np.ndarray:
+def kernel_entry(k: int, D, ngl: int = 16, r: float = 1.0, hv=None) -> np.ndarray:
+    """K_k(D) for an offset D in voxel steps, c dt = r and voxel edges hv (default 1, 1, 1)."""
     out = np.zeros(6)
-    lib().or_kernel_entry(r, int(k), float(D[0]), float(D[1]), float(D[2]), int(ngl), dptr(out))
+    lib().or_kernel_entry_h(r, dptr(_edges(hv)), int(k), float(D[0]), float(D[1]), float(D[2]), int(ngl), dptr(out))
     return out
 
 
 def kernel_table(U: int, V: int, W: int, kmax: int, ngl: int = 16, r: float = 1.0,
-                 skip_outside: bool = True) -> np.ndarray:
+                 skip_outside: bool = True, hv=None) -> np.ndarray:
     """K[k][6][2W-1][2V-1][2U-1] for k = 0..kmax (offset D at index D + (U-1, V-1, W-1))."""
     K = np.zeros((kmax + 1, 6, 2 * W - 1, 2 * V - 1, 2 * U - 1))
-    lib().or_kernel_table(r, U, V, W, kmax, ngl, 1 if skip_outside else 0, dptr(K))
+    lib().or_kernel_table_h(r, dptr(_edges(hv)), U, V, W, kmax, ngl, 1 if skip_outside else 0, dptr(K))
     return K
 
 
@@ -68,15 +75,17 @@ def local_coefficients(eps: np.ndarray, fir: np.ndarray, kmax: int) -> np.ndarra
     return c
 
 
-def excitation(U, V, W, eps, wave, n: int, nquad: int = 8, r: float = 1.0) -> np.ndarray:
-    """E_n(m) = chi_m (1/h^3) Int_{V_m} E^i(r, n dt) dV  (eq:E, test voxel m and step n),
-    the voxel average taken with an nquad^3 Gauss-Legendre rule; c dt = r h."""
-    return chi_of(eps)[None] * incident_average(U, V, W, wave, n, nquad, r)
+def excitation(U, V, W, eps, wave, n: int, nquad: int = 8, r: float = 1.0, hv=None) -> np.ndarray:
+    """E_n(m) = chi_m (1/|V_m|) Int_{V_m} E^i(r, n dt) dV  (eq:E, test voxel m and step n),
+    the voxel average taken with an nquad^3 Gauss-Legendre rule; c dt = r, voxel edges hv."""
+    return chi_of(eps)[None] * incident_average(U, V, W, wave, n, nquad, r, hv)
 
 
-def incident_average(U, V, W, wave, n: int, nquad: int = 8, r: float = 1.0) -> np.ndarray:
-    """<E^i>_m(n dt) = (1/h^3) Int_{V_m} E^i(r, n dt) dV, [3][W][V][U].  Lengths in units of h
-    (t0 and width are c t0 and the pulse width as lengths); c n dt = n r."""
+def incident_average(U, V, W, wave, n: int, nquad: int = 8, r: float = 1.0, hv=None) -> np.ndarray:
+    """<E^i>_m(n dt) = (1/|V_m|) Int_{V_m} E^i(r, n dt) dV, [3][W][V][U].  Lengths in the unit of
+    the voxel edges hv (default 1, 1, 1); t0 and width are c t0 and the pulse width as lengths;
+    c n dt = n r."""
+    hx, hy, hz = _edges(hv)
     x, w = np.polynomial.legendre.leggauss(nquad)
     x = 0.5 * x
     w = 0.5 * w
@@ -85,12 +94,13 @@ def incident_average(U, V, W, wave, n: int, nquad: int = 8, r: float = 1.0) -> n
     p = np.asarray(wave.pol, float)
     rr = np.asarray(wave.r_ref, float)
     # tau at the voxel centre, and the projections of the quadrature offsets on khat
-    tc = float(n) * r - wave.t0 - ((wx + 0.5 - rr[0]) * k[0] + (wy + 0.5 - rr[1]) * k[1] + (wz + 0.5 - rr[2]) * k[2])
+    tc = float(n) * r - wave.t0 - (((wx + 0.5) * hx - rr[0]) * k[0] + ((wy + 0.5) * hy - rr[1]) * k[1] +
+                                    ((wz + 0.5) * hz - rr[2]) * k[2])
     avg = np.zeros(tc.shape)
     for i in range(nquad):
         for j in range(nquad):
             for l in range(nquad):
-                s = x[i] * k[0] + x[j] * k[1] + x[l] * k[2]
+                s = x[i] * hx * k[0] + x[j] * hy * k[1] + x[l] * hz * k[2]
                 avg += w[i] * w[j] * w[l] * np.exp(-((tc - s) / wave.width) ** 2)
     avg *= wave.amp
     return np.stack([avg * p[0], avg * p[1], avg * p[2]])
@@ -115,7 +125,7 @@ def conv(K: np.ndarray, Jh: np.ndarray, targets=None) -> np.ndarray:
     return out
 
 
-def conv_pairs(targets, sources, Js: np.ndarray, ngl: int = 16, r: float = 1.0) -> np.ndarray:
+def conv_pairs(targets, sources, Js: np.ndarray, ngl: int = 16, r: float = 1.0, hv=None) -> np.ndarray:
     """sum_{k=1}^{nlag} sum_s K_k(r_t - r_s) J_{n-k}(s) for integer voxel coordinates
     targets [nt][3], sources [ns][3] and source currents Js[k-1][3][ns] = J_{n-k};
     every kernel value is computed on the spot.  Returns [3][nt]."""
@@ -123,18 +133,18 @@ def conv_pairs(targets, sources, Js: np.ndarray, ngl: int = 16, r: float = 1.0) 
     s = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
     J = np.ascontiguousarray(Js, dtype=np.float64)
     out = np.zeros((3, len(t)))
-    lib().or_conv_pairs(r, J.shape[0], iptr(t), len(t), iptr(s), len(s), dptr(J), ngl, dptr(out))
+    lib().or_conv_pairs(r, dptr(_edges(hv)), J.shape[0], iptr(t), len(t), iptr(s), len(s), dptr(J), ngl, dptr(out))
     return out
 
 
-def probe_kernels(probes, sources, kmax: int, ngl: int = 16, r: float = 1.0) -> np.ndarray:
-    """Kp[p][s][k][6] = K_k(r_p - r_s), k = 0..kmax, for probe points [np][3] (units of h from
-    the grid corner) and integer source voxels [ns][3] (centres at +1/2): eq:Z tested on a
-    virtual voxel centred at the probe."""
+def probe_kernels(probes, sources, kmax: int, ngl: int = 16, r: float = 1.0, hv=None) -> np.ndarray:
+    """Kp[p][s][k][6] = K_k(r_p - r_s), k = 0..kmax, for probe points [np][3] (voxel steps per
+    axis from the grid corner) and integer source voxels [ns][3] (centres at +1/2): eq:Z tested
+    on a virtual voxel centred at the probe."""
     P = np.ascontiguousarray(np.asarray(probes, dtype=np.float64).reshape(-1, 3))
     s = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1, 3))
     out = np.zeros((len(P), len(s), kmax + 1, 6))
-    lib().or_probe_kernels(r, int(kmax), dptr(P), len(P), iptr(s), len(s), int(ngl), dptr(out))
+    lib().or_probe_kernels(r, dptr(_edges(hv)), int(kmax), dptr(P), len(P), iptr(s), len(s), int(ngl), dptr(out))
     return out
 
 
@@ -210,17 +220,25 @@ def z0_matrix(K0: np.ndarray, eps: np.ndarray, fir: np.ndarray) -> sp.csr_matrix
     return A
 
 
+def problem_edges(prob) -> np.ndarray:
+    """Voxel edges (h, hy, hz) of a Problem; hy, hz of 0 (or absent) mean h."""
+    hy = getattr(prob, "hy", 0.0) or prob.h
+    hz = getattr(prob, "hz", 0.0) or prob.h
+    return np.array([prob.h, hy, hz], dtype=np.float64)
+
+
 class Oracle:
     """Direct MOT-JVIE march for one Problem (workloads.Problem) and one right-hand side."""
 
     def __init__(self, prob, K=None, ngl: int = 16):
-        # lengths in units of h; c dt = r h with r <= 1 keeps K_0 on the 27 nearest offsets
+        # lengths in units of the x edge; c dt <= every edge keeps K_0 on the 27 nearest offsets
         assert prob.h == 1.0, "the oracle works in units of h = 1"
         self.r = float(prob.c_dt)
-        assert 0.0 < self.r <= 1.0, "the oracle takes c dt <= h"
+        self.hv = problem_edges(prob)
+        assert 0.0 < self.r <= self.hv.min(), "the oracle takes c dt <= every voxel edge"
         self.p = prob
-        self.ell = ell(prob.U, prob.V, prob.W, 1.0, self.r)
-        self.K = kernel_table(prob.U, prob.V, prob.W, self.ell, ngl, self.r) if K is None else K
+        self.ell = ell(prob.U, prob.V, prob.W, 1.0, self.r, self.hv[1], self.hv[2])
+        self.K = kernel_table(prob.U, prob.V, prob.W, self.ell, ngl, self.r, hv=self.hv) if K is None else K
         self.fir = np.asarray(prob.fir, float)
         self.depth = max(self.ell, len(self.fir) - 1, 1)
         self.Z0 = z0_matrix(self.K[0], prob.eps, self.fir).tocsc()
@@ -236,7 +254,7 @@ class Oracle:
             lo = max(0, n - self.depth)
             Jh = J[lo:n][::-1]                       # Jh[k-1] = J_{n-k}
             P = history_sum(self.K, np.ascontiguousarray(Jh), p.eps, self.fir, self.ell)
-            E = excite(n) if excite is not None else excitation(U, V, W, p.eps, p.waves[rhs], n, r=self.r)
+            E = excite(n) if excite is not None else excitation(U, V, W, p.eps, p.waves[rhs], n, r=self.r, hv=self.hv)
             b = (E - P).ravel()
             J[n] = self.lu.solve(b).reshape(3, W, V, U)
             if return_P:
@@ -284,7 +302,7 @@ class Oracle:
         for n in range(1, N + 1):
             lo = max(0, n - 1 - self.ell)
             Jh = np.ascontiguousarray(J[lo:n - 1][::-1])          # Jh[k-1] = J_{n-k}, k >= 1
-            Bn = incident_average(p.U, p.V, p.W, p.waves[rhs], n, r=self.r)
+            Bn = incident_average(p.U, p.V, p.W, p.waves[rhs], n, r=self.r, hv=self.hv)
             Bn = Bn + tbasis(0) * J[n - 1] + conv(K0, np.ascontiguousarray(J[n - 1:n]))
             if n >= 2:
                 Bn = Bn + tbasis(1) * J[n - 2]
@@ -301,7 +319,7 @@ class Oracle:
         W, V, U = p.W, p.V, p.U
         J = self.run(n_steps, rhs)
         src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U)]
-        Kp = probe_kernels(probes, src, self.ell, r=self.r)
+        Kp = probe_kernels(probes, src, self.ell, r=self.r, hv=self.hv)
         E = probe_field(Kp, J, src)
         phi = float((E ** 2).sum())
         Kf = Kp[..., np.array(COMP).ravel()].reshape(Kp.shape[:3] + (3, 3))   # [np][M][k][b][a]

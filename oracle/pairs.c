@@ -16,11 +16,11 @@
 #include <math.h>
 #include <stdlib.h>
 
-void or_kernel_entry(double r, int k, double Dx, double Dy, double Dz, int ngl, double *out);
+void or_kernel_entry_h(double r, const double *h, int k, double Dx, double Dy, double Dz, int ngl, double *out);
 
 static const int comp_of[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
 
-void or_conv_pairs(double r, int nlag, const int *tgt, long nt, const int *src, long ns,
+void or_conv_pairs(double r, const double *h, int nlag, const int *tgt, long nt, const int *src, long ns,
                    const double *Js, int ngl, double *out)
 {
     for (long i = 0; i < 3 * nt; i++) out[i] = 0.0;
@@ -33,16 +33,16 @@ void or_conv_pairs(double r, int nlag, const int *tgt, long nt, const int *src, 
             for (int i = 0; i < 3; i++) {
                 D[i] = (double)(tgt[3 * it + i] - src[3 * is + i]);
                 double d = fabs(D[i]);
-                double m = d - 1.0 > 0.0 ? d - 1.0 : 0.0;
+                double m = d - 1.0 > 0.0 ? (d - 1.0) * h[i] : 0.0;
                 a2 += m * m;
-                b2 += (d + 1.0) * (d + 1.0);
+                b2 += (d + 1.0) * (d + 1.0) * h[i] * h[i];
             }
             double rmin = sqrt(a2), rmax = sqrt(b2);
             for (int k = 1; k <= nlag; k++) {
                 /* the lag's support (r(k-2), r(k+1)) must meet the pair's distances */
                 if (!(r * (k + 1) > rmin && r * (k - 2) < rmax)) continue;
                 double K[6];
-                or_kernel_entry(r, k, D[0], D[1], D[2], ngl, K);
+                or_kernel_entry_h(r, h, k, D[0], D[1], D[2], ngl, K);
                 const double *J = Js + (long)(k - 1) * 3 * ns;
                 for (int b = 0; b < 3; b++)
                     for (int a = 0; a < 3; a++)
@@ -63,11 +63,11 @@ void or_conv_pairs(double r, int nlag, const int *tgt, long nt, const int *src, 
  * E^s_p(n) = sum_k sum_s K_k(r_p - r_s) J_{n-k}(s): the scattered-field operator of the
  * formulation (Sec. 2.1) tested like eq:Z on a voxel that is not part of the grid.
  *
- *   probe [np][3]  points in units of h from the grid corner
+ *   probe [np][3]  points in voxel steps per axis from the grid corner
  *   src   [ns][3]  integer voxel coordinates (u, v, w)
  */
-void or_probe_kernels(double r, int kmax, const double *probe, long np, const int *src, long ns, int ngl,
-                      double *out)
+void or_probe_kernels(double r, const double *h, int kmax, const double *probe, long np, const int *src, long ns,
+                      int ngl, double *out)
 {
 #pragma omp parallel for collapse(2) schedule(dynamic, 4)
     for (long ip = 0; ip < np; ip++)
@@ -76,9 +76,9 @@ void or_probe_kernels(double r, int kmax, const double *probe, long np, const in
             for (int i = 0; i < 3; i++) {
                 D[i] = probe[3 * ip + i] - ((double)src[3 * is + i] + 0.5);
                 double d = fabs(D[i]);
-                double m = d - 1.0 > 0.0 ? d - 1.0 : 0.0;
+                double m = d - 1.0 > 0.0 ? (d - 1.0) * h[i] : 0.0;
                 a2 += m * m;
-                b2 += (d + 1.0) * (d + 1.0);
+                b2 += (d + 1.0) * (d + 1.0) * h[i] * h[i];
             }
             double rmin = sqrt(a2), rmax = sqrt(b2);
             double *o = out + ((ip * ns + is) * (long)(kmax + 1)) * 6;
@@ -88,7 +88,7 @@ void or_probe_kernels(double r, int kmax, const double *probe, long np, const in
                     for (int c = 0; c < 6; c++) K[c] = 0.0;
                     continue;
                 }
-                or_kernel_entry(r, k, D[0], D[1], D[2], ngl, K);
+                or_kernel_entry_h(r, h, k, D[0], D[1], D[2], ngl, K);
             }
         }
 }

@@ -53,7 +53,7 @@ struct mj_solver {
     // geometry and configuration
     int U = 0, V = 0, W = 0;
     long M = 0;
-    double h = 1.0, c_dt = 1.0;
+    double h = 1.0, hy = 1.0, hz = 1.0, c_dt = 1.0;
     int nrhs = 1, ell = 0;
     int Nx = 0, Ny = 0, Nz = 0, Hx = 0, Hp = 0;
     std::vector<double> fir;
@@ -180,9 +180,15 @@ void mj_solver::create(const mj_config &c)
     if (c.U < 1 || c.V < 1 || c.W < 1) throw ArgError("U, V, W must be >= 1");
     if (!(c.h > 0.0) || !std::isfinite(c.h)) throw ArgError("h must be positive and finite");
     if (!(c.c_dt > 0.0) || !std::isfinite(c.c_dt)) throw ArgError("c_dt must be positive and finite");
-    // c dt <= h keeps K_0 on the 27-point stencil the Z_0 solve is built for
-    if (!(c.c_dt <= c.h * (1.0 + 1e-12) && c.c_dt >= mj::kMinCdtOverH * c.h))
-        throw ArgError("c_dt / h must be in [0.3, 1]");
+    if (!(c.hy >= 0.0) || !(c.hz >= 0.0) || !std::isfinite(c.hy) || !std::isfinite(c.hz))
+        throw ArgError("hy, hz must be finite and >= 0 (0: equal to h)");
+    {
+        // c dt <= every edge keeps K_0 on the 27-point stencil the Z_0 solve is built for
+        const double ey = c.hy > 0.0 ? c.hy : c.h, ez = c.hz > 0.0 ? c.hz : c.h;
+        const double hmin = std::min(c.h, std::min(ey, ez)), hmax = std::max(c.h, std::max(ey, ez));
+        if (!(c.c_dt <= hmin * (1.0 + 1e-12) && c.c_dt >= mj::kMinCdtOverH * hmax))
+            throw ArgError("c_dt must lie in [0.3 max(h, hy, hz), min(h, hy, hz)]");
+    }
     if (!c.eps_r) throw ArgError("eps_r is NULL");
     if (c.n_fir < 0 || (c.n_fir > 0 && !c.fir)) throw ArgError("bad FIR taps");
     if (c.n_fir > mj::kMaxLocal) throw ArgError("at most 64 FIR taps");
@@ -193,6 +199,8 @@ void mj_solver::create(const mj_config &c)
     W = c.W;
     M = (long)U * V * W;
     h = c.h;
+    hy = c.hy > 0.0 ? c.hy : c.h;
+    hz = c.hz > 0.0 ? c.hz : c.h;
     c_dt = c.c_dt;
     nrhs = c.n_rhs;
     cg_rtol = c.cg_rtol > 0 ? c.cg_rtol : 1e-12;
@@ -207,7 +215,7 @@ void mj_solver::create(const mj_config &c)
     for (double e : eps)
         if (!(e >= 1.0) || !std::isfinite(e)) throw ArgError("eps_r must be finite and >= 1");
     // eq:Ell
-    double diag = std::sqrt((double)U * U + (double)V * V + (double)W * W) * h;
+    double diag = std::sqrt((U * h) * (U * h) + (V * hy) * (V * hy) + (W * hz) * (W * hz));
     ell = (int)std::floor(diag / c_dt + 1e-12) + 2;
     // zero padding N >= 2U - 1 per axis (Appendix A)
     Nx = mj::fft_pick_size(2 * U - 1);
@@ -289,7 +297,11 @@ void mj_solver::set_material(const double *eps)
 void mj_solver::build_spectra()
 {
     auto t0 = std::chrono::steady_clock::now();
-    mj::gen_moments(gen, U, V, W, std::min(1.0, c_dt / h), nquad, st);
+    {
+        // generator units: the x edge
+        const double hv[3] = {1.0, hy / h, hz / h};
+        mj::gen_moments(gen, U, V, W, c_dt / h, hv, nquad, st);
+    }
     bytes += (size_t)M * gen.ms * mj::kMoments * sizeof(double);
     MJ_CHECK(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
@@ -444,6 +456,8 @@ mj::EpiArg mj_solver::epi_arg() const
     e.nrhs = nrhs;
     e.n = n;
     e.h = h;
+    e.hy = hy;
+    e.hz = hz;
     e.c_dt = c_dt;
     e.chi = chi;
     e.schi = schi;
@@ -754,9 +768,11 @@ void mj_solver::set_probes(int n_probes, const double *pos)
     nw = 0;
     npairs = 0;
     if (n_probes == 0) return;
+    // probe points in voxel steps per axis; distances in units of the x edge
     const double r = c_dt / h;
+    const double edge[3] = {h, hy, hz}, hv[3] = {1.0, hy / h, hz / h};
     std::vector<double> P(3 * (size_t)n_probes);
-    for (size_t i = 0; i < P.size(); i++) P[i] = pos[i] / h;
+    for (size_t i = 0; i < P.size(); i++) P[i] = pos[i] / edge[i % 3];
     // every voxel is a source: voxels with eps_r = 1 carry no current in the march, but the
     // transposed march needs the probe kernels there (their lambda enters the eps-gradient)
     std::vector<int> src((size_t)M);
@@ -774,9 +790,9 @@ void mj_solver::set_probes(int n_probes, const double *pos)
             double a2 = 0, b2 = 0;
             for (int i = 0; i < 3; i++) {
                 const double ad = std::fabs(d[i]);
-                const double e = ad > 1.0 ? ad - 1.0 : 0.0;
+                const double e = ad > 1.0 ? (ad - 1.0) * hv[i] : 0.0;
                 a2 += e * e;
-                b2 += (ad + 1.0) * (ad + 1.0);
+                b2 += ((ad + 1.0) * hv[i]) * ((ad + 1.0) * hv[i]);
             }
             // lags with r(k + 1) > R_min and r(k - 2) < R_max
             const int kmin = std::max(0, (int)std::floor(std::sqrt(a2) / r));
@@ -853,7 +869,7 @@ void mj_solver::set_probes(int n_probes, const double *pos)
         MJ_CHECK(hipEventCreate(&e0));
         MJ_CHECK(hipEventCreate(&e1));
         MJ_CHECK(hipEventRecord(e0, st));
-        mj::gen_offgrid_table(probe_pos, pair_probe, pair_vox, pair_kmin, npairs, U, V, gen.r, nw, ell, nquad, ptable, st);
+        mj::gen_offgrid_table(probe_pos, pair_probe, pair_vox, pair_kmin, npairs, U, V, gen.r, gen.hv, nw, ell, nquad, ptable, st);
         MJ_CHECK(hipEventRecord(e1, st));
         MJ_CHECK(hipEventSynchronize(e1));
         float ms = 0;
@@ -901,7 +917,7 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
         MJ_CHECK(hipMemcpy(d_p, pp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(d_v, pv.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(d_k, pk.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
-        mj::gen_offgrid_table(probe_pos, d_p, d_v, d_k, cnt, U, V, gen.r, 1, 0x7fffffff, nquad, d_o, st);
+        mj::gen_offgrid_table(probe_pos, d_p, d_v, d_k, cnt, U, V, gen.r, gen.hv, 1, 0x7fffffff, nquad, d_o, st);
         MJ_CHECK(hipStreamSynchronize(st));
         MJ_CHECK(hipMemcpy(out, d_o, sizeof(double) * 6 * cnt, hipMemcpyDeviceToHost));
     } catch (...) {

@@ -1,17 +1,18 @@
 // Space-time interaction kernels of the MOT-JVIE on the device (FP64).
 //
-// For test voxel m, source voxel m', lag k = n - n' and D = r_m - r_m' (voxel units,
-// h = 1, c dt = r h with 0 < r <= 1), eq:Z with the piecewise-constant spatial basis (eq:SpatialBasis),
+// For test voxel m, source voxel m', lag k = n - n' and D = r_m - r_m' (lengths in units of
+// the x edge: voxel edges h = (1, hy, hz), c dt = r <= min h), eq:Z with the
+// piecewise-constant spatial basis (eq:SpatialBasis),
 // the voxel-average Dirac-in-time test (eq:TestOperator) and the quadratic-spline
 // temporal basis T(t) = B(t/dt + 1) (B the uniform quadratic B-spline on [0,3]) gives
 //
 //   Z^{ba}_k(m, m') = d_ab d_mm' T(k dt) / eps_m - chi_m K^{ba}_k(D),
 //   K^{ba}_k(D) = Int g_k(d) d_a d_b Lam(d - D) dd - d_ab Int gbar_k(d) Lam(d - D) dd,
 //   g_k = B(k + 1 - |d|/r) / (4 pi |d|),  gbar_k = B''(k + 1 - |d|/r) / (4 pi r^2 |d|),
-//   Lam(x) = prod_i (1 - |x_i|)_+ ,
+//   Lam(x) = prod_i (1 - |x_i| / h_i)_+ ,
 //
 // the derivatives of Lam taken in the distributional sense (a == b gives the second
-// difference across the planes d_a = D_a - 1, D_a, D_a + 1).
+// difference across the planes d_a = D_a - h_a, D_a, D_a + h_a, divided by h_a).
 //
 // Factorisation used here.  On the shell a r <= |d| < (a + 1) r each B-spline piece is
 // a quadratic in v = |d|/r - a, so every lag is a fixed combination of the lag-free
@@ -49,7 +50,8 @@ struct GenArg {
     int Uo, Vo, Wo;
     int nq;
     int ms;                          // shells stored per offset
-    double r;                        // c dt / h
+    double r;                        // c dt
+    double hv[3], ih[3];             // voxel edges and their inverses
     double glx[kMaxQ], glw[kMaxQ];   // nq-point rule on [-1, 1]
     double g3x[3], g3w[3];           // 3-point rule on [-1, 1]
 };
@@ -70,17 +72,22 @@ __host__ __device__ inline void shell_bounds(double rmin2, double rmax2, double 
     nsh = hi - lo;
 }
 
-__host__ __device__ inline void shell_range(int dx, int dy, int dz, double r, int &a_lo, int &nsh)
+__host__ __device__ inline void shell_range(int dx, int dy, int dz, const double hv[3], double r, int &a_lo,
+                                            int &nsh)
 {
     const int ex = dx > 0 ? dx - 1 : 0, ey = dy > 0 ? dy - 1 : 0, ez = dz > 0 ? dz - 1 : 0;
-    const double rmin2 = (double)ex * ex + (double)ey * ey + (double)ez * ez;
-    const double rmax2 = (double)(dx + 1) * (dx + 1) + (double)(dy + 1) * (dy + 1) + (double)(dz + 1) * (dz + 1);
+    const double rmin2 = (ex * hv[0]) * (ex * hv[0]) + (ey * hv[1]) * (ey * hv[1]) + (ez * hv[2]) * (ez * hv[2]);
+    const double rmax2 = ((dx + 1) * hv[0]) * ((dx + 1) * hv[0]) + ((dy + 1) * hv[1]) * ((dy + 1) * hv[1]) +
+                         ((dz + 1) * hv[2]) * ((dz + 1) * hv[2]);
     shell_bounds(rmin2, rmax2, r, a_lo, nsh);
 }
 
-// Upper bound on the shells of one voxel pair: R_max - R_min <= 2 sqrt 3, plus one shell cut
-// at each end and one for rounding.
-__host__ __device__ inline int shells_per_offset(double r) { return (int)(3.4641016151377546 / r) + 3; }
+// Upper bound on the shells of one voxel pair: R_max - R_min <= 2 |h|, plus one shell cut at
+// each end and one for rounding.
+__host__ __device__ inline int shells_per_offset(double r, const double hv[3])
+{
+    return (int)(2.0 * sqrt(hv[0] * hv[0] + hv[1] * hv[1] + hv[2] * hv[2]) / r) + 3;
+}
 
 // Fixed-size ascending sort with compile-time indices only (values stay in registers).
 template <int N>
@@ -97,21 +104,22 @@ __host__ __device__ inline void sort_fixed(double *a)
 }
 
 // Contribution of one face node y (weight wgt = dA * quadrature weight) on the square of
-// plane y_AX = c = D[AX] + s with sub-square signs (s1, s2) along the in-plane axes.
+// plane y_AX = c = D[AX] + s h_AX with sub-square signs (s1, s2) along the in-plane axes.
 // Every array index is a compile-time constant.
-template <int AX>
+// ANI = false compiles the cubic-voxel case, where every edge factor is 1.
+template <int AX, bool ANI>
 __host__ __device__ inline void node_contrib(double m[kMoments], const double y[3], double ny, double wgt, int s,
                                              int s1, int s2, const double D[3], double Ra, double Rb, double inv_r,
-                                             const double *g3x, const double *g3w)
+                                             const double *ih, const double *g3x, const double *g3w)
 {
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
     const double c = y[AX];
     const double inv_ny = 1.0 / ny;
     // plane term of component AX: w_s lam lam v^j / |y| on the shell
     if (ny >= Ra && ny < Rb) {
-        const double ws = (s == 0) ? -2.0 : 1.0;
-        const double l1 = 1.0 - s1 * (y[A1] - D[A1]);
-        const double l2 = 1.0 - s2 * (y[A2] - D[A2]);
+        const double ws = ANI ? ((s == 0) ? -2.0 : 1.0) * ih[AX] : ((s == 0) ? -2.0 : 1.0);
+        const double l1 = ANI ? 1.0 - s1 * (y[A1] - D[A1]) * ih[A1] : 1.0 - s1 * (y[A1] - D[A1]);
+        const double l2 = ANI ? 1.0 - s2 * (y[A2] - D[A2]) * ih[A2] : 1.0 - s2 * (y[A2] - D[A2]);
         const double v = (ny - Ra) * inv_r;
         const double f = wgt * ws * l1 * l2 * inv_ny;
         m[3 * AX + 0] += f;
@@ -147,13 +155,15 @@ __host__ __device__ inline void node_contrib(double m[kMoments], const double y[
         for (int q = 0; q < 3; q++) {
             const double u = hc + hm * g3x[q];
             const double wq = g3w[q] * u;
-            const double l0 = 1.0 - sb[0] * (u * yh[0] - D[0]);
-            const double l1 = 1.0 - sb[1] * (u * yh[1] - D[1]);
-            const double l2 = 1.0 - sb[2] * (u * yh[2] - D[2]);
+            const double l0 = ANI ? 1.0 - sb[0] * (u * yh[0] - D[0]) * ih[0] : 1.0 - sb[0] * (u * yh[0] - D[0]);
+            const double l1 = ANI ? 1.0 - sb[1] * (u * yh[1] - D[1]) * ih[1] : 1.0 - sb[1] * (u * yh[1] - D[1]);
+            const double l2 = ANI ? 1.0 - sb[2] * (u * yh[2] - D[2]) * ih[2] : 1.0 - sb[2] * (u * yh[2] - D[2]);
             const double v = (u - Ra) * inv_r;
             lamI += wq * l0 * l1 * l2;
             const double w0 = wq, w1 = wq * v, w2 = wq * v * v;
-            const double pxy = sb[0] * sb[1] * l2, pxz = sb[0] * sb[2] * l1, pyz = sb[1] * sb[2] * l0;
+            const double pxy = ANI ? sb[0] * sb[1] * l2 * (ih[0] * ih[1]) : sb[0] * sb[1] * l2;
+            const double pxz = ANI ? sb[0] * sb[2] * l1 * (ih[0] * ih[2]) : sb[0] * sb[2] * l1;
+            const double pyz = ANI ? sb[1] * sb[2] * l0 * (ih[1] * ih[2]) : sb[1] * sb[2] * l0;
             cb[0][0] += w0 * pxy; cb[0][1] += w1 * pxy; cb[0][2] += w2 * pxy;
             cb[1][0] += w0 * pxz; cb[1][1] += w1 * pxz; cb[1][2] += w2 * pxz;
             cb[2][0] += w0 * pyz; cb[2][1] += w1 * pyz; cb[2][2] += w2 * pyz;
@@ -171,17 +181,19 @@ constexpr double kSentinel = 1e300;
 constexpr int kMaxGrade = 6;   // graded tau points towards the foot (ratio 3)
 
 // One work item of the face quadrature of shell [Ra, Rb) at octant offset D for a unit square in the
-// plane y_AX = D[AX] + s: edge e, s-interval iv of that edge, s-node iq; accumulates into m.
+// plane y_AX = D[AX] + s h_AX: edge e, s-interval iv of that edge, s-node iq; accumulates into m.
 // glx/glw: nq-point rule on [-1,1]; g3x/g3w: 3-point rule.
-template <int AX, int E>
+template <int AX, int E, bool ANI>
 __host__ __device__ inline void gen_edge(int nq, const double *glx, const double *glw, const double *g3x,
                                          const double *g3w, const double D[3], double Ra, double Rb, double inv_r,
-                                         int s, int s1, int s2, int iv, int iq, double m[kMoments])
+                                         const double *hv, const double *ih, int s, int s1, int s2, int iv, int iq,
+                                         double m[kMoments])
 {
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
-    const double c = D[AX] + s;
-    const double lo1 = s1 > 0 ? D[A1] : D[A1] - 1, lo2 = s2 > 0 ? D[A2] : D[A2] - 1;
-    const double hi1 = lo1 + 1.0, hi2 = lo2 + 1.0;
+    const double e0_ = ANI ? hv[AX] : 1.0, e1_ = ANI ? hv[A1] : 1.0, e2_ = ANI ? hv[A2] : 1.0;
+    const double c = D[AX] + s * e0_;
+    const double lo1 = s1 > 0 ? D[A1] : D[A1] - e1_, lo2 = s2 > 0 ? D[A2] : D[A2] - e2_;
+    const double hi1 = lo1 + e1_, hi2 = lo2 + e2_;
     // edge e: signed distance p of its line from the foot; range [e0, e1] of the edge coordinate
     // E = 0: y_A2 = lo2 (s along A1); 1: y_A1 = hi1 (s along A2); 2: y_A2 = hi2; 3: y_A1 = lo1
     constexpr bool fixed_is_1 = (E == 1 || E == 3);
@@ -264,20 +276,21 @@ __host__ __device__ inline void gen_edge(int nq, const double *glx, const double
             y[A2] = tau * ey2;
             const double ny = sqrt(c2 + tau * tau * L * L);
             const double wgt = wsn * thm * glw[q] * tau;
-            node_contrib<AX>(m, y, ny, wgt, s, s1, s2, D, Ra, Rb, inv_r, g3x, g3w);
+            node_contrib<AX, ANI>(m, y, ny, wgt, s, s1, s2, D, Ra, Rb, inv_r, ih, g3x, g3w);
         }
     }
 }
 
-template <int AX>
+template <int AX, bool ANI>
 __host__ __device__ inline void gen_square(int nq, const double *glx, const double *glw, const double *g3x,
                                            const double *g3w, const double D[3], double Ra, double Rb, double inv_r,
-                                           int s, int s1, int s2, int iv, int iq, double m[kMoments])
+                                           const double *hv, const double *ih, int s, int s1, int s2, int iv, int iq,
+                                           double m[kMoments])
 {
-    gen_edge<AX, 0>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
-    gen_edge<AX, 1>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
-    gen_edge<AX, 2>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
-    gen_edge<AX, 3>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 0, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 1, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 2, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
+    gen_edge<AX, 3, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
 }
 
 // Number of work items per (offset, shell): 36 unit squares x 5 s-intervals x nq s-nodes.
@@ -286,9 +299,10 @@ __host__ __device__ inline int gen_items(int nq) { return 36 * 5 * nq; }
 // Item index -> (unit square, s-interval, s-node); the four edges of the square are
 // handled inside the item.  Dispatch on the plane axis.  Inlined by force: as a called
 // function its moment accumulators lived in scratch memory (192 bytes per lane).
+template <bool ANI>
 __host__ __device__ __attribute__((always_inline)) inline void gen_item(int nq, const double *glx, const double *glw, const double *g3x,
-                                         const double *g3w, const double D[3], int a, double r, int it,
-                                         double m[kMoments])
+                                         const double *g3w, const double D[3], int a, double r, const double *hv,
+                                         const double *ih, int it, double m[kMoments])
 {
     const double Ra = a * r, Rb = (a + 1) * r, inv_r = 1.0 / r;
     const int iq = it % nq;
@@ -298,9 +312,9 @@ __host__ __device__ __attribute__((always_inline)) inline void gen_item(int nq, 
     const int ax = sq / 12, rem = sq % 12;
     const int s = rem / 4 - 1;
     const int s1 = (rem & 1) ? 1 : -1, s2 = (rem & 2) ? 1 : -1;
-    if (ax == 0) gen_square<0>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
-    else if (ax == 1) gen_square<1>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
-    else gen_square<2>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, s, s1, s2, iv, iq, m);
+    if (ax == 0) gen_square<0, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
+    else if (ax == 1) gen_square<1, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
+    else gen_square<2, ANI>(nq, glx, glw, g3x, g3w, D, Ra, Rb, inv_r, hv, ih, s, s1, s2, iv, iq, m);
 }
 
 __device__ inline double wave_sum(double v)
@@ -310,13 +324,14 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+template <bool ANI>
 __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict__ mom, GenArg ga)
 {
     const int idx = blockIdx.x;
     const int dx = idx % ga.Uo, dy = (idx / ga.Uo) % ga.Vo, dz = idx / (ga.Uo * ga.Vo);
-    const double D[3] = {(double)dx, (double)dy, (double)dz};
+    const double D[3] = {dx * ga.hv[0], dy * ga.hv[1], dz * ga.hv[2]};
     int a_lo, nsh;
-    shell_range(dx, dy, dz, ga.r, a_lo, nsh);
+    shell_range(dx, dy, dz, ga.hv, ga.r, a_lo, nsh);
     double *out = mom + (size_t)idx * ga.ms * kMoments;
     const int nq = ga.nq;
     __shared__ double glx[kMaxQ], glw[kMaxQ], g3x[3], g3w[3];
@@ -337,7 +352,8 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_moments(double *__restrict_
         for (int i = 0; i < kMoments; i++) m[i] = 0.0;
         const int a = a_lo + sh;
         if (sh < nsh) {
-            for (int it = threadIdx.x; it < nitems; it += kGenThreads) gen_item(nq, glx, glw, g3x, g3w, D, a, r, it, m);
+            for (int it = threadIdx.x; it < nitems; it += kGenThreads)
+                gen_item<ANI>(nq, glx, glw, g3x, g3w, D, a, r, ga.hv, ga.ih, it, m);
         }
 #pragma unroll
         for (int i = 0; i < kMoments; i++) {
@@ -371,10 +387,10 @@ __host__ __device__ inline void kernel_from_shells(const double *mom_d, int a_lo
 
 // K_k at integer octant offset (dx,dy,dz) >= 0 from the shell moments.
 __host__ __device__ inline void kernel_from_moments(const double *mom_d, int dx, int dy, int dz, int k, double r,
-                                                    double K[6])
+                                                    const double hv[3], double K[6])
 {
     int a_lo, nsh;
-    shell_range(dx, dy, dz, r, a_lo, nsh);
+    shell_range(dx, dy, dz, hv, r, a_lo, nsh);
     kernel_from_shells(mom_d, a_lo, nsh, k, r, K);
     // exact zeros of the odd components on their symmetry planes
     if (dx == 0 || dy == 0) K[3] = 0.0;
@@ -386,13 +402,14 @@ struct MomView {
     const double *mom;   // [Wo][Vo][Uo][ms][kMoments]
     int Uo, Vo, Wo, ms;
     double r;
+    double hv[3];
 };
 
 __device__ inline void kernel_at(const MomView &g, int k, int Dx, int Dy, int Dz, double K[6])
 {
     int ax = Dx < 0 ? -Dx : Dx, ay = Dy < 0 ? -Dy : Dy, az = Dz < 0 ? -Dz : Dz;
     const double *md = g.mom + ((size_t)(az * g.Vo + ay) * g.Uo + ax) * g.ms * kMoments;
-    kernel_from_moments(md, ax, ay, az, k, g.r, K);
+    kernel_from_moments(md, ax, ay, az, k, g.r, g.hv, K);
     double sx = Dx < 0 ? -1.0 : 1.0, sy = Dy < 0 ? -1.0 : 1.0, sz = Dz < 0 ? -1.0 : 1.0;
     K[3] *= sx * sy;
     K[4] *= sx * sz;
@@ -429,13 +446,15 @@ __global__ void k_kernel_values(MomView g, int n, const int *__restrict__ lag, c
 // ---------------------------------------------------------------------------- off-grid offsets
 // Shell range for a real octant offset D >= 0 (the distances between points of the two
 // voxels lie in [|max(D - 1, 0)|, |D + 1|]).
-__host__ __device__ inline void shell_range_real(const double D[3], double r, int &a_lo, int &nsh)
+// D in voxel steps per axis; edges hv.
+__host__ __device__ inline void shell_range_real(const double D[3], const double hv[3], double r, int &a_lo,
+                                                 int &nsh)
 {
     double a2 = 0.0, b2 = 0.0;
     for (int i = 0; i < 3; i++) {
-        const double e = D[i] > 1.0 ? D[i] - 1.0 : 0.0;
+        const double e = D[i] > 1.0 ? (D[i] - 1.0) * hv[i] : 0.0;
         a2 += e * e;
-        b2 += (D[i] + 1.0) * (D[i] + 1.0);
+        b2 += ((D[i] + 1.0) * hv[i]) * ((D[i] + 1.0) * hv[i]);
     }
     shell_bounds(a2, b2, r, a_lo, nsh);
     if (nsh > kShellCap) nsh = kShellCap;   // cannot happen for r >= kMinCdtOverH
@@ -462,12 +481,13 @@ __host__ __device__ inline void finish_offgrid(const double D[3], const double s
 }
 
 struct OffgridArg {
-    const double *pos;        // [np][3] test-voxel centres, units of h from the grid corner
+    const double *pos;        // [np][3] test-voxel centres, voxel steps per axis from the grid corner
     const int *pair_probe;    // [npairs]
     const int *pair_vox;      // [npairs] source voxel, linear index u + U (v + V w)
     const int *pair_kmin;     // [npairs] first lag of the window
     int U, V;
-    double r;                 // c dt / h
+    double r;                 // c dt
+    double hv[3], ih[3];      // voxel edges and their inverses
     int nw;                   // lags per pair
     int kmax;                 // lags above kmax are stored as zero
     long npairs;
@@ -476,16 +496,18 @@ struct OffgridArg {
 
 // One 64-lane block per (test voxel, source voxel) pair: shell moments by the same face
 // quadrature as the grid kernels, then the pair's window of lags.
+template <bool ANI>
 __global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, GenArg ga)
 {
     const long i = blockIdx.x;
     const int p = oa.pair_probe[i], vox = oa.pair_vox[i];
     const int u = vox % oa.U, v = (vox / oa.U) % oa.V, w = vox / (oa.U * oa.V);
     const double Ds[3] = {oa.pos[3 * p] - (u + 0.5), oa.pos[3 * p + 1] - (v + 0.5), oa.pos[3 * p + 2] - (w + 0.5)};
-    double D[3], sg[3];
-    fold_offset(Ds, D, sg);
+    double Dv[3], sg[3];
+    fold_offset(Ds, Dv, sg);
     int a_lo, nsh;
-    shell_range_real(D, oa.r, a_lo, nsh);
+    shell_range_real(Dv, oa.hv, oa.r, a_lo, nsh);
+    const double D[3] = {Dv[0] * oa.hv[0], Dv[1] * oa.hv[1], Dv[2] * oa.hv[2]};
     const int nq = ga.nq;
     __shared__ double glx[kMaxQ], glw[kMaxQ], g3x[3], g3w[3];
     __shared__ double mom[kShellCap * kMoments];
@@ -504,7 +526,7 @@ __global__ void __launch_bounds__(kGenThreads) k_offgrid_table(OffgridArg oa, Ge
 #pragma unroll
         for (int t = 0; t < kMoments; t++) m[t] = 0.0;
         for (int it = threadIdx.x; it < nitems; it += kGenThreads)
-            gen_item(nq, glx, glw, g3x, g3w, D, a_lo + sh, oa.r, it, m);
+            gen_item<ANI>(nq, glx, glw, g3x, g3w, D, a_lo + sh, oa.r, oa.hv, oa.ih, it, m);
 #pragma unroll
         for (int t = 0; t < kMoments; t++) {
             const double s_ = wave_sum(m[t]);
@@ -559,17 +581,30 @@ void legendre_rule(int n, double *x, double *w)
 
 }  // namespace
 
-void gen_moments(GenResult &g, int U, int V, int W, double r, int nquad, hipStream_t st)
+static void check_geometry(double r, const double hv[3])
+{
+    const double hmin = fmin(hv[0], fmin(hv[1], hv[2])), hmax = fmax(hv[0], fmax(hv[1], hv[2]));
+    if (!(hmin > 0.0) || !(r <= hmin * (1.0 + 1e-12)) || !(r >= kMinCdtOverH * hmax))
+        throw ArgError("c dt must lie in [0.3 max(h), min(h)]");
+    if (shells_per_offset(r, hv) > kShellCap) throw ArgError("too many kernel shells per voxel pair");
+}
+
+void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3], int nquad, hipStream_t st)
 {
     if (nquad < 4 || nquad > kMaxQ) throw ArgError("quad_order must be in [4, 24]");
-    if (!(r >= kMinCdtOverH && r <= 1.0)) throw ArgError("c dt / h must be in [0.3, 1]");
+    check_geometry(r, hv);
     GenArg ga{};
     ga.Uo = U;
     ga.Vo = V;
     ga.Wo = W;
     ga.nq = nquad;
     ga.r = r;
-    ga.ms = shells_per_offset(r);
+    for (int i = 0; i < 3; i++) {
+        ga.hv[i] = hv[i];
+        ga.ih[i] = 1.0 / hv[i];
+        g.hv[i] = hv[i];
+    }
+    ga.ms = shells_per_offset(r, hv);
     legendre_rule(nquad, ga.glx, ga.glw);
     legendre_rule(3, ga.g3x, ga.g3w);
     g.Uo = U;
@@ -581,7 +616,10 @@ void gen_moments(GenResult &g, int U, int V, int W, double r, int nquad, hipStre
     size_t bytes = noff * g.ms * kMoments * sizeof(double);
     if (hipMalloc(&g.moments, bytes) != hipSuccess) throw MemError("kernel moments");
     MJ_CHECK(hipMemsetAsync(g.moments, 0, bytes, st));
-    hipLaunchKernelGGL(k_gen_moments, dim3((unsigned)noff), dim3(kGenThreads), 0, st, g.moments, ga);
+    if (hv[1] != 1.0 || hv[2] != 1.0)
+        hipLaunchKernelGGL(k_gen_moments<true>, dim3((unsigned)noff), dim3(kGenThreads), 0, st, g.moments, ga);
+    else
+        hipLaunchKernelGGL(k_gen_moments<false>, dim3((unsigned)noff), dim3(kGenThreads), 0, st, g.moments, ga);
     MJ_CHECK(hipGetLastError());
 }
 
@@ -589,7 +627,7 @@ void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *
 {
     size_t n = (size_t)Nx * Ny * Nz;
     dim3 blk(256), grd((unsigned)((n + 255) / 256));
-    const MomView mv{g.moments, g.Uo, g.Vo, g.Wo, g.ms, g.r};
+    const MomView mv{g.moments, g.Uo, g.Vo, g.Wo, g.ms, g.r, {g.hv[0], g.hv[1], g.hv[2]}};
     hipLaunchKernelGGL(k_kernel_grid, grd, blk, 0, st, mv, k, Nx, Ny, Nz, grid);
     MJ_CHECK(hipGetLastError());
 }
@@ -598,17 +636,17 @@ void gen_kernel_values(const GenResult &g, int n, const int *lag_dev, const int 
                        hipStream_t st)
 {
     if (n <= 0) return;
-    const MomView mv{g.moments, g.Uo, g.Vo, g.Wo, g.ms, g.r};
+    const MomView mv{g.moments, g.Uo, g.Vo, g.Wo, g.ms, g.r, {g.hv[0], g.hv[1], g.hv[2]}};
     hipLaunchKernelGGL(k_kernel_values, dim3((n + 127) / 128), dim3(128), 0, st, mv, n, lag_dev, off_dev, out_dev);
     MJ_CHECK(hipGetLastError());
 }
 
 void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const int *pair_vox_dev,
-                       const int *pair_kmin_dev, long npairs, int U, int V, double r, int nw, int kmax, int nquad,
-                       double *out_dev, hipStream_t st)
+                       const int *pair_kmin_dev, long npairs, int U, int V, double r, const double hv[3], int nw,
+                       int kmax, int nquad, double *out_dev, hipStream_t st)
 {
     if (npairs <= 0) return;
-    if (!(r >= kMinCdtOverH && r <= 1.0)) throw ArgError("c dt / h must be in [0.3, 1]");
+    check_geometry(r, hv);
     if (nquad < 4 || nquad > kMaxQ) throw ArgError("quad_order must be in [4, 24]");
     if (npairs > 0x7fffffffL) throw ArgError("too many probe pairs");
     GenArg ga{};
@@ -623,11 +661,18 @@ void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const i
     oa.U = U;
     oa.V = V;
     oa.r = r;
+    for (int i = 0; i < 3; i++) {
+        oa.hv[i] = hv[i];
+        oa.ih[i] = 1.0 / hv[i];
+    }
     oa.nw = nw;
     oa.kmax = kmax;
     oa.npairs = npairs;
     oa.out = out_dev;
-    hipLaunchKernelGGL(k_offgrid_table, dim3((unsigned)npairs), dim3(kGenThreads), 0, st, oa, ga);
+    if (hv[1] != 1.0 || hv[2] != 1.0)
+        hipLaunchKernelGGL(k_offgrid_table<true>, dim3((unsigned)npairs), dim3(kGenThreads), 0, st, oa, ga);
+    else
+        hipLaunchKernelGGL(k_offgrid_table<false>, dim3((unsigned)npairs), dim3(kGenThreads), 0, st, oa, ga);
     MJ_CHECK(hipGetLastError());
 }
 

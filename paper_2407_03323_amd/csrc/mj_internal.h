@@ -98,19 +98,21 @@ void fft3d_inverse(Fft3D &f, const double2 *X, double *y, int ncomp, hipStream_t
 
 // ---------------------------------------------------------------------------- generator
 // Shell moments per octant offset (see mj_gen.hip).  kMoments values per (offset, shell); the
-// shells are r = c dt / h wide, so a voxel pair meets at most 2 sqrt 3 / r + 3 of them.
+// shells are c dt wide, so a voxel pair with edges h meets at most 2 |h| / (c dt) + 3 of them.
 constexpr int kMoments = 19;
-constexpr double kMinCdtOverH = 0.3;   // smallest c dt / h the generator accepts
-constexpr int kShellCap = 16;          // shells per offset at r = kMinCdtOverH: 14
+constexpr double kMinCdtOverH = 0.3;   // smallest c dt / max(h) the generator accepts
+constexpr int kShellCap = 16;          // shells per offset at c dt = 0.3 max(h): at most 14
 
 struct GenResult {
     double *moments = nullptr;  // [Woct][Voct][Uoct][ms][kMoments]
     int Uo = 0, Vo = 0, Wo = 0;
     int ms = 0;                 // shells stored per offset
-    double r = 1.0;             // c dt / h
+    double r = 1.0;             // c dt, in units of the x edge
+    double hv[3] = {1.0, 1.0, 1.0};   // voxel edges, in units of the x edge
 };
 
-void gen_moments(GenResult &g, int U, int V, int W, double r, int nquad, hipStream_t st);
+// r = c dt and hv = voxel edges, both in units of the x edge (hv[0] = 1)
+void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3], int nquad, hipStream_t st);
 // K_k on the full periodic grid [6][Nz][Ny][Nx] (real), from the octant moments
 void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *grid, hipStream_t st);
 // K_k(D) for a list of (k, D): out[n][6]
@@ -118,8 +120,8 @@ void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *
 // corner) for source voxels pair_vox (linear index), lags pair_kmin .. pair_kmin + nw - 1
 // (zero above kmax): out[nw][pair][6].
 void gen_offgrid_table(const double *pos_dev, const int *pair_probe_dev, const int *pair_vox_dev,
-                       const int *pair_kmin_dev, long npairs, int U, int V, double r, int nw, int kmax, int nquad,
-                       double *out_dev, hipStream_t st);
+                       const int *pair_kmin_dev, long npairs, int U, int V, double r, const double hv[3], int nw,
+                       int kmax, int nquad, double *out_dev, hipStream_t st);
 
 void gen_kernel_values(const GenResult &g, int n, const int *lag_dev, const int *off_dev, double *out_dev,
                        hipStream_t st);

@@ -41,7 +41,7 @@ struct EpiArg {
     int U, V, W;
     int nrhs;
     int n;                   // current step
-    double h, c_dt;
+    double h, hy, hz, c_dt;  // voxel edges (x, y, z) and c dt
     const double *chi, *schi, *inv_eps;
     const double *fir;       // device taps (nfir)
     int nfir;

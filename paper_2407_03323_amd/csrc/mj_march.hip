@@ -390,18 +390,18 @@ void launch_mac_near(const BlockMacArg &a, hipStream_t st)
 // axis the wave does not depend on is the identity).
 __device__ inline double wave_average(const WaveArg &w, const EpiArg &e, int u, int v, int z, double ct)
 {
-    const double tc = ct - w.ct0 - ((u + 0.5) * e.h - w.rref[0]) * w.k[0] - ((v + 0.5) * e.h - w.rref[1]) * w.k[1] -
-                      ((z + 0.5) * e.h - w.rref[2]) * w.k[2];
+    const double tc = ct - w.ct0 - ((u + 0.5) * e.h - w.rref[0]) * w.k[0] - ((v + 0.5) * e.hy - w.rref[1]) * w.k[1] -
+                      ((z + 0.5) * e.hz - w.rref[2]) * w.k[2];
     const double iw = 1.0 / w.width;
     const int nx = w.k[0] != 0.0 ? 8 : 1, ny = w.k[1] != 0.0 ? 8 : 1, nz = w.k[2] != 0.0 ? 8 : 1;
     double sum = 0.0;
     for (int i = 0; i < nx; i++) {
         const double ox = nx > 1 ? e.glx8[i] * e.h * w.k[0] : 0.0, wx = nx > 1 ? e.glw8[i] : 1.0;
         for (int j = 0; j < ny; j++) {
-            const double oy = ny > 1 ? e.glx8[j] * e.h * w.k[1] : 0.0, wy = ny > 1 ? e.glw8[j] : 1.0;
+            const double oy = ny > 1 ? e.glx8[j] * e.hy * w.k[1] : 0.0, wy = ny > 1 ? e.glw8[j] : 1.0;
             double sl = 0.0;
             for (int l = 0; l < nz; l++) {
-                const double oz = nz > 1 ? e.glx8[l] * e.h * w.k[2] : 0.0, wz = nz > 1 ? e.glw8[l] : 1.0;
+                const double oz = nz > 1 ? e.glx8[l] * e.hz * w.k[2] : 0.0, wz = nz > 1 ? e.glw8[l] : 1.0;
                 const double x = (tc - ox - oy - oz) * iw;
                 sl += wz * exp(-x * x);
             }

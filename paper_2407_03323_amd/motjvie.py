@@ -38,6 +38,7 @@ class mj_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("quad_order", ctypes.c_int32),
         ("fft_pencils", ctypes.c_int32),
+        ("hy", ctypes.c_double), ("hz", ctypes.c_double),
     ]
 
 
@@ -102,7 +103,7 @@ class Solver:
     """One MOT-JVIE march on the device (see include/motjvie.h for the exact semantics)."""
 
     def __init__(self, U, V, W, eps, fir=None, h=1.0, c_dt=None, n_rhs=1, cg_rtol=0.0, cg_maxit=0,
-                 time_block=0, quad_order=0, stream=None, fft_pencils=0):
+                 time_block=0, quad_order=0, stream=None, fft_pencils=0, hy=0.0, hz=0.0):
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(W, V, U))
@@ -123,6 +124,7 @@ class Solver:
         cfg.stream = stream if stream is not None else _current_stream()
         cfg.quad_order = int(quad_order)
         cfg.fft_pencils = int(fft_pencils)
+        cfg.hy, cfg.hz = float(hy), float(hz)
         self._keep = (eps, fir)
         rc = self._lib.mj_create(ctypes.byref(cfg), ctypes.byref(self._h))
         if rc != MJ_OK:
@@ -246,6 +248,7 @@ class Solver:
 def solver_for(problem, **kw) -> Solver:
     """Solver for a workloads.Problem, with its plane waves set."""
     s = Solver(problem.U, problem.V, problem.W, problem.eps, fir=problem.fir, h=problem.h, c_dt=problem.c_dt,
+               hy=getattr(problem, "hy", 0.0), hz=getattr(problem, "hz", 0.0),
                n_rhs=kw.pop("n_rhs", len(problem.waves) or 1), **kw)
     if problem.waves:
         s.set_plane_waves(problem.waves)

@@ -28,16 +28,18 @@ def _oracle_digest():
     return h.hexdigest()[:12]
 
 
-def oracle_kernel_table(U, V, W, kmax, ngl=16, r=1.0):
-    """Oracle kernel table (c dt = r h), cached on disk per oracle source version (the cache is
-    only a speed-up: it is recomputed from oracle/ whenever missing)."""
+def oracle_kernel_table(U, V, W, kmax, ngl=16, r=1.0, hv=None):
+    """Oracle kernel table (c dt = r, voxel edges hv, default cubic), cached on disk per oracle
+    source version (the cache is only a speed-up: it is recomputed from oracle/ whenever missing)."""
     from oracle import mot
     os.makedirs(CACHE, exist_ok=True)
     tag = "" if r == 1.0 else "_r%.6g" % r
+    if hv is not None and tuple(hv) != (1.0, 1.0, 1.0):
+        tag += "_h%.6g_%.6g_%.6g" % tuple(hv)
     path = os.path.join(CACHE, "K_%s_%dx%dx%d_k%d_n%d%s.npy" % (_oracle_digest(), U, V, W, kmax, ngl, tag))
     if os.path.exists(path):
         return np.load(path)
-    K = mot.kernel_table(U, V, W, kmax, ngl, r)
+    K = mot.kernel_table(U, V, W, kmax, ngl, r, hv=hv)
     tmp = path + ".tmp%d.npy" % os.getpid()
     np.save(tmp, K)
     os.replace(tmp, path)

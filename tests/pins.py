@@ -86,6 +86,31 @@ def newell_tensor(D):
     return np.array([nxx, nyy, nzz, nxy, nxz, nyz])
 
 
+def newell_tensor_h(D, h):
+    """Demagnetising tensor between two hx x hy x hz prisms whose centres are D_i h_i apart
+    (Newell, Williams & Dunlop 1993 for unequal edges: the sixth differences step by h_i and
+    the volume is hx hy hz).  Returns (xx, yy, zz, xy, xz, yz); its trace is 1 at D = 0."""
+    hx, hy, hz = (float(v) for v in h)
+    X, Y, Z = float(D[0]) * hx, float(D[1]) * hy, float(D[2]) * hz
+    c = -1.0 / (4.0 * pi * hx * hy * hz)
+    w = {-1: 1.0, 0: -2.0, 1: 1.0}
+
+    def diff(fun, sx, sy, sz):
+        t = 0.0
+        for i in (-1, 0, 1):
+            for j in (-1, 0, 1):
+                for k in (-1, 0, 1):
+                    t += w[i] * w[j] * w[k] * fun(X + i * sx, Y + j * sy, Z + k * sz)
+        return t
+    nxx = c * diff(newell_f, hx, hy, hz)
+    nyy = c * diff(lambda a, b, d: newell_f(b, d, a), hx, hy, hz)
+    nzz = c * diff(lambda a, b, d: newell_f(d, a, b), hx, hy, hz)
+    nxy = c * diff(newell_g, hx, hy, hz)
+    nxz = c * diff(lambda a, b, d: newell_g(a, d, b), hx, hy, hz)
+    nyz = c * diff(lambda a, b, d: newell_g(b, d, a), hx, hy, hz)
+    return np.array([nxx, nyy, nzz, nxy, nxz, nyz])
+
+
 PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 
 
@@ -112,6 +137,28 @@ def overlap_gl(D, integrand, n=16):
     return total
 
 
+def overlap_gl_h(D, h, integrand, n=16):
+    """(1/(hx hy hz)) Int F(d) Lam(d - D h) dd for prisms of edges h (Lam the overlap volume),
+    by tensor Gauss-Legendre over the 8 sub-boxes; F smooth on the box as for overlap_gl."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    x = 0.5 * (x + 1.0)
+    w = 0.5 * w
+    h = np.asarray(h, float)
+    P = np.asarray(D, float) * h
+    total = np.zeros(6)
+    tx, ty, tz = np.meshgrid(x, x, x, indexing="ij")
+    wt = (w[:, None, None] * w[None, :, None] * w[None, None, :])
+    lam = (1 - tx) * (1 - ty) * (1 - tz)
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            for sz in (-1, 1):
+                d = np.stack([P[0] + sx * h[0] * tx, P[1] + sy * h[1] * ty, P[2] + sz * h[2] * tz])
+                F = integrand(d)
+                # dd = hx hy hz dt and Lam / (hx hy hz) = prod (1 - t_i)
+                total += np.array([np.sum(F[c] * lam * wt) for c in range(6)]) * h.prod()
+    return total
+
+
 def static_second_derivative(d):
     """d_a d_b (1/(4 pi R)) = (3 d_a d_b - delta_ab R^2) / (4 pi R^5) away from the origin."""
     R2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
@@ -134,11 +181,11 @@ def second_moment_integrand(d):
     return out
 
 
-def axis_wave_voxel_average(tau_centre, width):
-    """(1/h) Int_{-1/2}^{1/2} exp(-((tau_centre - z)/width)^2) dz in closed form (erf)."""
+def axis_wave_voxel_average(tau_centre, width, hz=1.0):
+    """(1/hz) Int_{-hz/2}^{hz/2} exp(-((tau_centre - z)/width)^2) dz in closed form (erf)."""
     from math import erfc
-    a = (tau_centre + 0.5) / width
-    b = (tau_centre - 0.5) / width
+    a = (tau_centre + 0.5 * hz) / width
+    b = (tau_centre - 0.5 * hz) / width
     # erf(a) - erf(b) written with erfc on the side away from zero (no cancellation in the tails)
     if b >= 0:
         d = erfc(b) - erfc(a)
@@ -146,4 +193,4 @@ def axis_wave_voxel_average(tau_centre, width):
         d = erfc(-a) - erfc(-b)
     else:
         d = erf(a) - erf(b)
-    return 0.5 * width * sqrt(pi) * d
+    return 0.5 * width * sqrt(pi) * d / hz

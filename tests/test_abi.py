@@ -80,7 +80,8 @@ def test_binding_config_matches_header():
             assert ct is want[ctype], name
 
 
-@pytest.mark.parametrize("case", ["grid", "cdt", "cdt_small", "eps", "rhs", "pencils", "null"])
+@pytest.mark.parametrize("case", ["grid", "cdt", "cdt_small", "edge_short", "edge_long", "eps", "rhs", "pencils",
+                                  "null"])
 def test_create_rejects_invalid_arguments(lib, case):
     from paper_2407_03323_amd.motjvie import MJ_EINVAL
     h = ctypes.c_void_p()
@@ -93,6 +94,12 @@ def test_create_rejects_invalid_arguments(lib, case):
         c, keep = _cfg(c_dt=1.5)          # c dt > h: K_0 would leave the 27-point stencil
     elif case == "cdt_small":
         c, keep = _cfg(c_dt=0.2)          # below the generator's 0.3 h
+    elif case == "edge_short":
+        c, keep = _cfg()
+        c.hy = 0.5                        # c dt = h > hy
+    elif case == "edge_long":
+        c, keep = _cfg()
+        c.hz = 4.0                        # c dt < 0.3 max edge
     elif case == "eps":
         c, keep = _cfg(eps=np.full(64, 0.5))
     elif case == "pencils":

@@ -30,11 +30,12 @@ def gen_host():
            src, "-o", lib]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
     L = ctypes.CDLL(lib)
-    L.host_kernels.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.host_kernels.argtypes = [ctypes.c_double] * 6 + [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
 
-    def run(D, kmax, nq=16, r=1.0):
+    def run(D, kmax, nq=16, r=1.0, hv=(1.0, 1.0, 1.0)):
+        assert hv[0] == 1.0
         out = np.zeros((kmax + 1, 6))
-        L.host_kernels(float(D[0]), float(D[1]), float(D[2]), float(r), nq, kmax,
+        L.host_kernels(float(D[0]), float(D[1]), float(D[2]), float(r), float(hv[1]), float(hv[2]), nq, kmax,
                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return out
     return run
@@ -65,5 +66,18 @@ def test_generator_on_host_matches_oracle_short_step(gen_host, D, r):
     ref = np.array([mot.kernel_entry(k, D, ngl=ngl, r=r) for k in range(kmax + 1)])
     # an off-centre overlap of the two voxels puts 1/R's singularity inside the box away from
     # every symmetry plane, where the oracle's quadrature is good to ~1e-9 only
+    tol = 3e-12 if all(float(d).is_integer() for d in D) else 1e-10
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("hv,r", [((1.0, 0.7, 1.3), 0.7), ((1.0, 1.5, 2.0), 0.6)])
+@pytest.mark.parametrize("D", [(0, 0, 0), (1, 0, 0), (0, 1, 1), (1, 1, 1), (-3, 2, 1), (5, 4, -3), (1.3, -0.7, 0.45)])
+def test_generator_on_host_matches_oracle_prism_voxels(gen_host, D, hv, r):
+    """hx x hy x hz voxels: planes and sub-boxes scaled per axis, 1/h_a on the second differences."""
+    b = np.sqrt(sum(((abs(d) + 1) * h) ** 2 for d, h in zip(D, hv)))
+    kmax = int(b / r) + 3
+    got = gen_host(D, kmax, r=r, hv=hv)
+    ngl = 16 if all(float(d).is_integer() for d in D) else 24
+    ref = np.array([mot.kernel_entry(k, D, ngl=ngl, r=r, hv=hv) for k in range(kmax + 1)])
     tol = 3e-12 if all(float(d).is_integer() for d in D) else 1e-10
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()

@@ -719,6 +719,76 @@ def test_short_step_adjoint_gradient_matches_oracle(torch_cuda):
     s.close()
 
 
+# ----------------------------------------------------------------------------- hx x hy x hz voxels
+PRISM = (1.0, 0.7, 1.3)
+
+
+def test_prism_voxel_generator_matches_oracle(torch_cuda):
+    """Voxels 1 x 0.7 x 1.3 with c dt = 0.7 (the shortest edge): every K_k(D) of a 5 x 4 x 3
+    grid against the oracle."""
+    from oracle import mot
+    U, V, W, r = 5, 4, 3, 0.7
+    say("generator prism voxels 5x4x3")
+    ell = mot.ell(U, V, W, 1.0, r, PRISM[1], PRISM[2])
+    prob = wl.Problem("prism", U, V, W, wl.random_eps(U, V, W, 3, 2.0, 5.0), [], 1, c_dt=r, hy=PRISM[1], hz=PRISM[2])
+    s = make_solver(prob)
+    assert s.ell == ell
+    Ko = oracle_kernel_table(U, V, W, ell, r=r, hv=PRISM)
+    r_ = [np.arange(-(n - 1), n) for n in (U, V, W)]
+    dz, dy, dx = np.meshgrid(r_[2], r_[1], r_[0], indexing="ij")
+    offs = np.stack([dx.ravel(), dy.ravel(), dz.ravel()], axis=1)
+    worst = 0.0
+    for k in range(ell + 1):
+        got = s.kernel_values(np.full(len(offs), k), offs)
+        ref = np.stack([Ko[k, c][offs[:, 2] + W - 1, offs[:, 1] + V - 1, offs[:, 0] + U - 1] for c in range(6)], axis=1)
+        worst = max(worst, np.abs(got - ref).max() / np.abs(Ko).max())
+    say("  ell", ell, "worst / max|K|", worst)
+    assert worst <= 1e-12
+    s.close()
+
+
+def test_prism_voxel_march_probes_and_gradient_match_oracle(torch_cuda):
+    """A 5 x 4 x 3 heterogeneous block of 1 x 0.7 x 1.3 voxels, c dt = 0.6, 3-tap FIR: J, the
+    field at four probes and the adjoint eps-gradient against the oracle.  Probe points go to the
+    library as lengths and to the oracle in voxel steps."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n, r = 5, 4, 3, 50, 0.6
+    say("march + probes + gradient, prism voxels 5x4x3")
+    eps = wl.random_eps(U, V, W, 23, 2.0, 9.0)
+    eps[0, 0, 0] = 1.0
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("prism", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1), c_dt=r, hy=PRISM[1], hz=PRISM[2])
+    probes = wl.fibonacci_sphere(4, 5.0, (U / 2, V / 2, W / 2))
+    ell = mot.ell(U, V, W, 1.0, r, PRISM[1], PRISM[2])
+    K = oracle_kernel_table(U, V, W, ell, r=r, hv=PRISM)
+    o = mot.Oracle(prob, K=K)
+    J = o.run(n)
+    src = [(u, v, w) for w in range(W) for v in range(V) for u in range(U) if eps[w, v, u] != 1.0]
+    ref = mot.probe_field(mot.probe_kernels(probes, src, ell, r=r, hv=PRISM), J, src)
+    phi_ref, grad_ref, _ = o.probe_objective_gradient(n, probes)
+    s = make_solver(prob, time_block=8)
+    s.set_probes(probes * np.asarray(PRISM))
+    Jt = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    Pt = torch.zeros((n, 1, len(probes), 3), dtype=torch.float64, device="cuda")
+    s.run(n, Jt, Pt)
+    torch.cuda.synchronize()
+    eJ = _rel(Jt.cpu().numpy()[:, 0], J)
+    eP = _rel(Pt.cpu().numpy()[:, 0], ref)
+    s.reset()
+    g = torch.zeros((W, V, U), dtype=torch.float64, device="cuda")
+    phi = s.adjoint_gradient(n, g, 9)
+    torch.cuda.synchronize()
+    e_phi = abs(phi - phi_ref) / abs(phi_ref)
+    e_g = _rel(g.cpu().numpy(), grad_ref)
+    say("  ell", s.ell, "J", eJ, "probes", eP, "phi", e_phi, "grad", e_g)
+    assert s.ell == ell
+    assert eJ <= 1e-8 and eP <= 1e-8
+    assert e_phi <= 1e-10 and e_g <= 1e-8
+    s.close()
+
+
 # ----------------------------------------------------------------------------- degenerate cases
 @pytest.mark.parametrize("UVW", [(1, 1, 1), (7, 1, 1), (1, 5, 2), (3, 3, 1)])
 def test_march_degenerate_grids(torch_cuda, UVW):

@@ -726,3 +726,100 @@ def test_short_step_time_shift_invariance():
     p.waves[0].t0 += 2.5            # five steps of c dt = 1/2
     J2 = o.run(140)
     assert np.abs(J2[5:] - J1[:-5]).max() < 1e-13 * np.abs(J1).max()
+
+
+# ----------------------------------------------------------------------------- unequal voxel edges
+# Voxels hx x hy x hz (hx = 1 sets the unit).  The identities keep their form with Newell's
+# prism tensor, the overlap of two prisms and the distance range of two prisms.
+HV = (1.0, 0.7, 1.3)
+
+
+def lag_window_h(D, hv):
+    a = sum((max(abs(d) - 1, 0) * h) ** 2 for d, h in zip(D, hv)) ** 0.5
+    b = sum(((abs(d) + 1) * h) ** 2 for d, h in zip(D, hv)) ** 0.5
+    return a, b
+
+
+def kernel_lags_h(D, r, hv, extra=2):
+    _, b = lag_window_h(D, hv)
+    kmax = int(np.floor(b / r)) + 2 + extra
+    return np.array([mot.kernel_entry(k, D, r=r, hv=hv) for k in range(kmax + 1)])
+
+
+@pytest.mark.parametrize("r", [0.7, 0.5])
+@pytest.mark.parametrize("D", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (2, -1, 0), (3, 1, -2)])
+def test_prism_static_sum_equals_newell(D, r):
+    Ks = kernel_lags_h(D, r, HV)
+    assert np.abs(Ks.sum(0) + pins.newell_tensor_h(D, HV)).max() < 5e-14
+
+
+@pytest.mark.parametrize("D", [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 1, 0)])
+def test_prism_trace_identity(D):
+    Ks = kernel_lags_h(D, 0.7, HV)
+    want = -1.0 if D == (0, 0, 0) else 0.0
+    assert abs(Ks.sum(0)[:3].sum() - want) < 1e-13
+
+
+@pytest.mark.parametrize("D", [(1, 1, 1), (3, 2, 2), (5, -3, 2)])
+def test_prism_first_and_second_moments(D):
+    r = 0.6
+    Ks = kernel_lags_h(D, r, HV)
+    k = np.arange(len(Ks))[:, None]
+    assert np.abs((k * Ks).sum(0) - 0.5 * Ks.sum(0)).max() < 1e-11 * np.abs(Ks).max()
+    if D != (1, 1, 1):
+        static = pins.overlap_gl_h(D, HV, pins.static_second_derivative)
+        assert np.abs(Ks.sum(0) - static).max() < 1e-10 * np.abs(static).max()
+        ref = 0.5 * static - pins.overlap_gl_h(D, HV, pins.second_moment_integrand) / (r * r)
+        assert np.abs((k ** 2 * Ks).sum(0) - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_prism_axis_swap():
+    """Swapping two axes together with their edges permutes the components."""
+    r = 0.6
+    for D, k in [((2, 1, 0), 4), ((3, -2, 1), 6), ((1.3, 0.4, -2.2), 5)]:
+        K = mot.kernel_entry(k, D, r=r, hv=HV)
+        Ks = mot.kernel_entry(k, (D[1], D[0], D[2]), r=r, hv=(HV[1], HV[0], HV[2]))
+        assert np.abs(Ks - K[[1, 0, 2, 3, 5, 4]]).max() < 1e-13 * np.abs(K).max()
+
+
+def test_prism_support_and_stencil():
+    r = 0.7          # = the shortest edge: K_0 still on the 27 nearest offsets
+    for D in [(0, 0, 0), (1, 1, 1), (0, 2, 0), (3, 2, 1)]:
+        Ks = kernel_lags_h(D, r, HV, extra=3)
+        a, b = lag_window_h(D, HV)
+        scale = np.abs(Ks).max()
+        for k in range(len(Ks)):
+            if not ((k + 1) * r > a and (k - 2) * r < b):
+                assert np.abs(Ks[k]).max() < 1e-13 * scale + 1e-15
+    for D in [(1, 1, 1), (0, 1, 0), (0, 0, 0)]:
+        assert np.abs(mot.kernel_entry(0, D, r=r, hv=HV)).max() > 1e-4
+    for D in [(2, 0, 0), (0, 2, 0), (0, 0, 2), (2, 1, 1)]:
+        assert np.abs(mot.kernel_entry(0, D, r=r, hv=HV)).max() < 1e-15
+    assert mot.ell(5, 4, 3, 1.0, r, HV[1], HV[2]) == int(np.floor(sqrt(25 + (4 * 0.7) ** 2 + (3 * 1.3) ** 2) / r)) + 2
+
+
+def test_prism_excitation_axis_wave_closed_form():
+    hv = (1.0, 0.7, 1.3)
+    p = wl.homogeneous_cube(4, 5.0, 10, 4.0)
+    wave = p.waves[0]
+    for n in (3, 14, 22):
+        E = mot.excitation(4, 4, 4, p.eps, wave, n, r=0.7, hv=hv)
+        for w in range(4):
+            tc = n * 0.7 - wave.t0 - (w + 0.5) * hv[2]
+            ref = 0.8 * wave.amp * pins.axis_wave_voxel_average(tc, wave.width, hv[2])
+            assert np.allclose(E[0, w], ref, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_prism_one_voxel_static_limit(axis):
+    """One hx x hy x hz voxel under a constant field along an axis settles at
+    J = chi E / (1/eps + chi N_aa(0)) with Newell's self factor of the prism."""
+    eps = 6.0
+    p = wl.homogeneous_cube(1, eps, 10, 4.0)
+    p.c_dt, p.hy, p.hz = 0.7, HV[1], HV[2]
+    E0 = [0.0, 0.0, 0.0]
+    E0[axis] = 1.0
+    J = mot.Oracle(p).run(500, excite=_constant_excitation(p, E0))
+    chi = (eps - 1) / eps
+    N = pins.newell_tensor_h((0, 0, 0), HV)[axis]
+    assert abs(J[-1, axis, 0, 0, 0] - chi / (1 / eps + chi * N)) < 1e-12

@@ -49,6 +49,8 @@ class Problem:
     probes: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     h: float = 1.0
     c_dt: float = 1.0
+    hy: float = 0.0                 # y and z voxel edges; 0 means h (cubic voxels)
+    hz: float = 0.0
 
     @property
     def M(self) -> int:
