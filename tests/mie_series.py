@@ -56,3 +56,36 @@ def axis_field(eps_r: float, radius: float, k: float, r: float) -> complex:
         dh = spherical_jn(n, rho, derivative=True) + 1j * spherical_yn(n, rho, derivative=True)
         tot += (1j) ** n * (2 * n + 1) / 2.0 * (1j * a[n - 1] * (h + rho * dh) / rho - b[n - 1] * h)
     return tot
+
+
+def internal_coefficients(eps_r: float, x: float, nmax: int | None = None):
+    """Internal-field coefficients c_n, d_n, n = 1..nmax (the field inside is
+    sum_n E_n (c_n M_o1n - i d_n N_e1n) with j_n(m k r) radial functions), from the same
+    tangential-field matching as coefficients(), non-magnetic sphere:
+        c_n = [j_n(x) xi_n'(x) - h_n(x) psi_n'(x)] / [j_n(mx) xi_n'(x) - h_n(x) psi_n'(mx)]
+        d_n = m [j_n(x) xi_n'(x) - h_n(x) psi_n'(x)] / [m^2 j_n(mx) xi_n'(x) - h_n(x) psi_n'(mx)]
+    with psi_n(r) = r j_n(r), xi_n(r) = r h_n(r) and ' the derivative in r."""
+    m = np.sqrt(eps_r)
+    nmax = n_terms(x) if nmax is None else nmax
+    c = np.zeros(nmax, complex)
+    d = np.zeros(nmax, complex)
+    for n in range(1, nmax + 1):
+        jx, djx = spherical_jn(n, x), spherical_jn(n, x, derivative=True)
+        yx, dyx = spherical_yn(n, x), spherical_yn(n, x, derivative=True)
+        jm, djm = spherical_jn(n, m * x), spherical_jn(n, m * x, derivative=True)
+        dpsi = jx + x * djx
+        dpsim = jm + m * x * djm
+        h, dh = jx + 1j * yx, djx + 1j * dyx
+        dxi = h + x * dh
+        num = jx * dxi - h * dpsi
+        c[n - 1] = num / (jm * dxi - h * dpsim)
+        d[n - 1] = m * num / (m * m * jm * dxi - h * dpsim)
+    return c, d
+
+
+def centre_field(eps_r: float, x: float) -> complex:
+    """Field at the sphere's centre per unit incident amplitude, along the polarisation: only the
+    n = 1 electric term is non-zero there, and N_e11(0) = (2/3) x_hat with E_1 = 3i/2, so the
+    field is d_1 (the static limit 3/(eps_r + 2) is the Clausius-Mossotti factor)."""
+    _, d = internal_coefficients(eps_r, x, 1)
+    return complex(d[0])
