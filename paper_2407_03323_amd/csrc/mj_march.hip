@@ -550,8 +550,10 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
 }
 
 // c_0 = T(0)/eps + delta_0 with T(0) = 1/2 and 1/eps = 1 - chi, and the Jacobi weight
-// 1 / (c_0 - chi K_0^{xx}(0)), both from s = sqrt(chi) (the diagonal of K_0 at D = 0 is
-// isotropic for a cube): two coefficient streams fewer per pass
+// 1 / (c_0 - chi K_0^{xx}(0)), both from s = sqrt(chi): two coefficient streams fewer per pass.
+// The diagonal of K_0 at D = 0 is isotropic for cubic voxels; for unequal edges the x entry
+// stands in for all three, which keeps the preconditioner symmetric positive definite (the
+// solve still converges to the same tolerance)
 __device__ inline double cg_c0(const CgArg &a, double s) { return 0.5 * (1.0 - s * s) + a.d0; }
 __device__ inline double cg_md(const CgArg &a, double s, double c0) { return 1.0 / (c0 - s * s * a.k0c); }
 
