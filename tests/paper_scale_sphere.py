@@ -82,7 +82,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=52500)       # 100 lm
     ap.add_argument("--chunk", type=int, default=500)
-    ap.add_argument("--out", default="gpurun_out/sphere105")
+    ap.add_argument("--out", default="sphere105_out")
     ap.add_argument("--analyse", default=None, help="analyse a saved centre_current.npy instead of marching")
     args = ap.parse_args()
     prob, inside = sphere_problem()
