@@ -191,6 +191,26 @@ int mj_adjoint_gradient(mj_solver *s, int32_t n_steps, int32_t ckpt_every, doubl
 int mj_reset(mj_solver *s);
 
 /*
+ * mj_get_state, mj_set_state -- checkpoint and resume a march.  The state is everything that a
+ * later step of eq:MOTInversion reads from earlier steps:
+ *   - the step count n;
+ *   - the spectral history ring (the FFT of J_{n-k}, k = 1..ell, Sec. 3);
+ *   - the current time block's far-part sums (Sec. 4.1);
+ *   - the real-space currents that the FIR stencil, the Z_0 initial guess and the probes read.
+ * The adjoint (mj_adjoint_gradient) keeps its own checkpoints and is not part of it.
+ *   mj_get_state: buf host, nullable.  With buf NULL, *bytes receives the size needed.
+ *   Otherwise *bytes must be at least that size (else MJ_EINVAL), and it receives the size
+ *   written.  The size grows as ell x n_rhs x 48 B x the padded half-spectrum points: about
+ *   40 GB at 104^3.
+ *   mj_set_state: buf host.  The state must come from a solver with the same grid, n_rhs,
+ *   ell, time block and real-space depth (so the same probes, if any, set before this call),
+ *   else MJ_EINVAL.  The material, taps and plane waves are the caller's to match.  A march
+ *   resumed this way repeats the original steps bit for bit.
+ */
+int mj_get_state(const mj_solver *s, void *buf, size_t *bytes);
+int mj_set_state(mj_solver *s, const void *buf, size_t bytes);
+
+/*
  * mj_history_sum -- P_{n-1} = sum_{k>=1} Z^delta_k J_{n-k} (eq:PnMOT with the FIR taps)
  *   for an explicit history, through the same FFT / spectral multiply-accumulate / inverse
  *   FFT path that the march uses (right-hand side 0).

@@ -169,6 +169,9 @@ struct mj_solver {
     void check_growth() const;
     void run(int n_steps, double *Jout, double *Pout);
     void adjoint_gradient(int n_steps, int ckpt_every, double *phi, double *grad_dev, double *probe_hist);
+    size_t state_bytes() const;
+    void get_state(void *buf) const;
+    void set_state(const void *buf, size_t bytes);
     void set_probes(int n_probes, const double *pos);
     void offgrid_values(int n, const int *probe, const int *vox, const int *lag, double *out);
     void solve_z0();
@@ -933,6 +936,80 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
     (void)hipFree(d_o);
 }
 
+// March state: a fixed header, then the spectral ring, the time block's far sums and the
+// real-space history, each copied whole (slots the march does not read yet copy as they are).
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, U, V, W, nrhs, ell, B, rdepth, Nx, Ny, Nz, Hp;
+    int64_t n, ring_bytes, far_bytes, jr_bytes;
+};
+constexpr char kStateMagic[8] = {'M', 'J', 'S', 'T', 'A', 'T', 'E', '1'};
+}  // namespace
+
+size_t mj_solver::state_bytes() const
+{
+    const size_t sp = (size_t)spec_plane(), v3 = (size_t)nrhs * 3;
+    return sizeof(StateHeader) + sizeof(double2) * (size_t)ell * v3 * sp +
+           (farbuf ? sizeof(double2) * (size_t)B * v3 * sp : 0) + sizeof(double) * (size_t)rdepth * v3 * M;
+}
+
+void mj_solver::get_state(void *buf) const
+{
+    const size_t sp = (size_t)spec_plane(), v3 = (size_t)nrhs * 3;
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.version = 1;
+    h.U = U;
+    h.V = V;
+    h.W = W;
+    h.nrhs = nrhs;
+    h.ell = ell;
+    h.B = B;
+    h.rdepth = rdepth;
+    h.Nx = Nx;
+    h.Ny = Ny;
+    h.Nz = Nz;
+    h.Hp = Hp;
+    h.n = n;
+    h.ring_bytes = (int64_t)(sizeof(double2) * (size_t)ell * v3 * sp);
+    h.far_bytes = farbuf ? (int64_t)(sizeof(double2) * (size_t)B * v3 * sp) : 0;
+    h.jr_bytes = (int64_t)(sizeof(double) * (size_t)rdepth * v3 * M);
+    char *p = (char *)buf;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    MJ_CHECK(hipStreamSynchronize(st));
+    MJ_CHECK(hipMemcpy(p, ring, (size_t)h.ring_bytes, hipMemcpyDeviceToHost));
+    p += h.ring_bytes;
+    if (h.far_bytes) MJ_CHECK(hipMemcpy(p, farbuf, (size_t)h.far_bytes, hipMemcpyDeviceToHost));
+    p += h.far_bytes;
+    MJ_CHECK(hipMemcpy(p, Jr, (size_t)h.jr_bytes, hipMemcpyDeviceToHost));
+}
+
+void mj_solver::set_state(const void *buf, size_t bytes)
+{
+    StateHeader h;
+    if (bytes < sizeof h) throw ArgError("state buffer too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1) throw ArgError("not a march state");
+    if (h.U != U || h.V != V || h.W != W || h.nrhs != nrhs || h.ell != ell || h.B != B || h.Nx != Nx ||
+        h.Ny != Ny || h.Nz != Nz || h.Hp != Hp)
+        throw ArgError("state of a solver with another grid, n_rhs, ell or time block");
+    if (h.rdepth != rdepth) throw ArgError("state of a solver with another history depth (probes differ)");
+    if (bytes < state_bytes() || (size_t)h.ring_bytes + (size_t)h.far_bytes + (size_t)h.jr_bytes + sizeof h !=
+                                     state_bytes())
+        throw ArgError("state buffer has the wrong size");
+    if (h.n < 0 || h.n > INT32_MAX) throw ArgError("bad step count in the state");
+    const char *p = (const char *)buf + sizeof h;
+    MJ_CHECK(hipStreamSynchronize(st));
+    MJ_CHECK(hipMemcpy(ring, p, (size_t)h.ring_bytes, hipMemcpyHostToDevice));
+    p += h.ring_bytes;
+    if (h.far_bytes) MJ_CHECK(hipMemcpy(farbuf, p, (size_t)h.far_bytes, hipMemcpyHostToDevice));
+    p += h.far_bytes;
+    MJ_CHECK(hipMemcpy(Jr, p, (size_t)h.jr_bytes, hipMemcpyHostToDevice));
+    n = (int)h.n;
+}
+
 // Gradient of Phi = sum_{n=1}^{N} sum_r sum_p |E^s_{r,p}(n)|^2 with respect to eps_r of every
 // voxel, by the transposed march (see mj_march.hip) with checkpointing:
 //  1. forward march of all N steps, keeping the probe field of every step and, at the start
@@ -1247,6 +1324,27 @@ int mj_reset(mj_solver *s)
     if (!s) return MJ_EINVAL;
     s->n = 0;
     return MJ_OK;
+}
+
+int mj_get_state(const mj_solver *s, void *buf, size_t *bytes)
+{
+    if (!s || !bytes) return MJ_EINVAL;
+    mj_solver *sm = const_cast<mj_solver *>(s);
+    return guarded(sm, [&] {
+        const size_t need = s->state_bytes();
+        if (buf) {
+            if (*bytes < need) throw ArgError("state buffer too small");
+            s->get_state(buf);
+        }
+        *bytes = need;
+    });
+}
+
+int mj_set_state(mj_solver *s, const void *buf, size_t bytes)
+{
+    if (!s) return MJ_EINVAL;
+    if (!buf) return fail(s, MJ_EINVAL, "state buffer is NULL");
+    return guarded(s, [&] { s->set_state(buf, bytes); });
 }
 
 int mj_history_sum(mj_solver *s, const double *J_hist, int32_t depth, double *P)

@@ -72,9 +72,11 @@ def load_library(path: str = LIB_PATH):
     L.mj_probe_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, ip, dp]
     L.mj_set_eps.argtypes = [vp, dp]
     L.mj_adjoint_gradient.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, vp, vp]
+    L.mj_get_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mj_set_state.argtypes = [vp, vp, ctypes.c_size_t]
     for f in ("mj_create", "mj_info", "mj_set_plane_waves", "mj_run", "mj_reset", "mj_history_sum",
               "mj_kernel_values", "mj_stats", "mj_fft_roundtrip", "mj_set_probes", "mj_march",
-              "mj_probe_kernel_values", "mj_set_eps", "mj_adjoint_gradient"):
+              "mj_probe_kernel_values", "mj_set_eps", "mj_adjoint_gradient", "mj_get_state", "mj_set_state"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -202,6 +204,19 @@ class Solver:
 
     def reset(self):
         self._check(self._lib.mj_reset(self._h))
+
+    def get_state(self) -> np.ndarray:
+        """The march state (step count and every history the next steps read) as host bytes."""
+        nb = ctypes.c_size_t(0)
+        self._check(self._lib.mj_get_state(self._h, None, ctypes.byref(nb)))
+        buf = np.empty(nb.value, dtype=np.uint8)
+        self._check(self._lib.mj_get_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nb)))
+        return buf
+
+    def set_state(self, buf):
+        """Resume from get_state() of a solver with the same configuration (and probes)."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._lib.mj_set_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
 
     def history_sum(self, J_hist, P):
         """P_{n-1} for the explicit history J_hist[k-1] = J_{n-k} (CUDA tensors)."""

@@ -826,6 +826,58 @@ def test_prism_voxel_march_probes_and_gradient_match_oracle(torch_cuda):
     s.close()
 
 
+# ----------------------------------------------------------------------------- checkpoint / resume
+@pytest.mark.parametrize("tb,with_probes", [(8, True), (1, False), (16, False)])
+def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes):
+    """mj_get_state after 37 steps (inside a time block), mj_set_state on a fresh solver of the
+    same configuration: the next 53 steps repeat the uninterrupted march bit for bit (currents
+    and probe field).  A state from another time block or a cut buffer is refused."""
+    from paper_2407_03323_amd.motjvie import MJ_EINVAL, MotJvieError
+    torch = torch_cuda
+    U, V, W, n1, N = 6, 5, 4, 37, 90
+    say("checkpoint/resume tb=%d probes=%s" % (tb, with_probes))
+    eps = wl.random_eps(U, V, W, 41, 2.0, 9.0)
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("resume", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], N,
+                      fir=wl.binomial_highpass(5, 0.01))
+    probes = wl.fibonacci_sphere(3, 5.0, (U / 2, V / 2, W / 2))
+    npb = len(probes) if with_probes else 0
+
+    def solver(tb_=tb):
+        s_ = make_solver(prob, time_block=tb_)
+        if with_probes:
+            s_.set_probes(probes)
+        return s_
+    s = solver()
+    Jref = torch.zeros((N, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    Pref = torch.zeros((N, 1, max(npb, 1), 3), dtype=torch.float64, device="cuda")
+    s.run(N, Jref, Pref[:, :, :npb] if with_probes else None)
+    s.close()
+    s = solver()
+    s.run(n1)
+    state = s.get_state()
+    s.close()
+    s = solver()
+    s.set_state(state)
+    assert s.info()["n"] == n1
+    J = torch.zeros((N - n1, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    P = torch.zeros((N - n1, 1, max(npb, 1), 3), dtype=torch.float64, device="cuda")
+    s.run(N - n1, J, P[:, :, :npb] if with_probes else None)
+    torch.cuda.synchronize()
+    assert torch.equal(J, Jref[n1:])
+    if with_probes:
+        assert torch.equal(P, Pref[n1:])
+    with pytest.raises(MotJvieError) as ei:
+        s.set_state(state[:-8])
+    assert ei.value.code == MJ_EINVAL
+    s.close()
+    other = solver(4 if tb != 4 else 8)
+    with pytest.raises(MotJvieError) as ei:
+        other.set_state(state)
+    assert ei.value.code == MJ_EINVAL
+    other.close()
+
+
 # ----------------------------------------------------------------------------- degenerate cases
 @pytest.mark.parametrize("UVW", [(1, 1, 1), (7, 1, 1), (1, 5, 2), (3, 3, 1)])
 def test_march_degenerate_grids(torch_cuda, UVW):
