@@ -9,7 +9,8 @@ Z_k -> Z_k + delta_k I of Sec. 6.1.  Z_0 is assembled as a sparse matrix and fac
 directly (scipy's sparse LU); the history sum is the direct triple sum of direct.c.
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use it.
 
-Units: h = 1, c dt = 1 (the configurations in workloads/ all use c dt = h).
+Units: the x edge of a voxel is 1; the voxel edges (1, hy, hz) and c dt <= min(edges) come from
+the Problem (the configurations in workloads/ use cubic voxels and c dt = h).
 Vectors are stored per component: J[a][w][v][u]  (the paper's eq:CurrentVector
 interleaves the three components per voxel; the two orders hold the same numbers).
 """
