@@ -32,6 +32,8 @@ WORKLOADS = {
           "plane wave sigma=8 dt delay 6 sigma, 17-tap binomial FIR delta=0.01",
     "C2": "32^3 sphere r=15h eps_r=12, c dt = h, x-pol +z Gaussian sigma=4 dt, 17-tap binomial FIR delta=0.01",
     "C1": "8^3 cube eps_r=4, c dt = h, x-pol +z Gaussian sigma=4 dt, no FIR",
+    "C5s": "C5 with c dt = h/2 (ell = 362)",
+    "C5p": "C5 on voxels 1 x 0.7 x 1.3 with c dt = 0.7 (ell = 266)",
 }
 
 

@@ -179,6 +179,16 @@ def config(name: str) -> Problem:
         k, p = XPOL_PLUS_Z
         return Problem("C5", U, U, U, eps, [gaussian_wave(U, U, U, k, p, 8.0)], 2000,
                        fir=binomial_highpass(17, FIR17_DELTA))
+    if name in ("C5s", "C5p"):
+        # C5 with a shorter step (c dt = h/2), or with voxels 1 x 0.7 x 1.3 and c dt = 0.7 (the
+        # shortest edge): the same 104^3 grid and material
+        p = config("C5")
+        if name == "C5s":
+            p.c_dt = 0.5
+        else:
+            p.hy, p.hz, p.c_dt = 0.7, 1.3, 0.7
+        p.name = name
+        return p
     raise KeyError(name)
 
 
