@@ -284,6 +284,11 @@ def main():
                      "kernel": kname, "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": launch_ms, "fp64": fp64, "convolution": conv},
     }
+    if warmup < ell + 1:
+        # the per-launch figures count every lag; before step ell + 1 a launch sums fewer
+        line["roofline"] = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                            "traffic": None, "kernel": kname,
+                            "note": "warmup %d < ell + 1: the timed launches do not sum all %d lags" % (warmup, ell)}
     solver.close()
     del solver
     torch.cuda.synchronize()
