@@ -5,7 +5,10 @@ A step is one pass of the whole hot path for one time step: forward FFT of the n
 current, spectral multiply-accumulate over all ell history lags, inverse FFT, right-hand
 side assembly (excitation, FIR, local terms) and the Z_0 solve.  The timed steps start
 after `warmup` steps; warmup defaults to more than ell so every timed step sums the full
-history.  Kernel generation and spectra are one-time setup and are reported separately.
+history.  The far part of the history sum runs once per time block (8 steps by default), so
+the timed window should be a whole number of blocks: the default 48 steps hold exactly 6 far
+launches, whatever the window's phase.  Kernel generation and spectra are one-time setup and
+are reported separately.
 
 Prints one JSON line (metric voxel*steps/s, FP64).
 """
@@ -159,7 +162,7 @@ def adjoint_ratio(n_steps: int = 800, ckpt: int = 50):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=48, help="timed steps; a multiple of the time block")
     ap.add_argument("--warmup", type=int, default=-1, help="default: ell + 8")
     ap.add_argument("--workload", default="C5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -212,6 +215,10 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = solver.stats()
+    if info["time_block"] > 1 and args.steps % info["time_block"]:
+        print("note: %d timed steps are not a whole number of %d-step time blocks; the far part's share "
+              "of the step time depends on where the window starts" % (args.steps, info["time_block"]),
+              file=sys.stderr, flush=True)
     M = prob.M
     value = M * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
