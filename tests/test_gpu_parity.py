@@ -554,6 +554,35 @@ def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt):
     s.close()
 
 
+def test_batched_adjoint_gradient_matches_oracle(torch_cuda):
+    """Three plane waves marched and transposed together (checkpoints every 9 steps): Phi sums
+    over the waves, so Phi and dPhi/deps equal the sums of the oracle's single-wave adjoints."""
+    from oracle import mot
+    torch = torch_cuda
+    prob, probes = _adjoint_case()
+    U, V, W = prob.U, prob.V, prob.W
+    prob.waves = _three_waves(U, V, W)
+    say("batched adjoint 5x4x3, 3 waves")
+    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    o = mot.Oracle(prob, K=K)
+    phi_ref, grad_ref = 0.0, np.zeros((W, V, U))
+    for r in range(3):
+        ph, gr, _ = o.probe_objective_gradient(prob.n_steps, probes, rhs=r)
+        phi_ref += ph
+        grad_ref += gr
+    s = make_solver(prob, time_block=8)
+    assert s.n_rhs == 3
+    s.set_probes(probes)
+    g = torch.zeros((W, V, U), dtype=torch.float64, device="cuda")
+    phi = s.adjoint_gradient(prob.n_steps, g, 9)
+    torch.cuda.synchronize()
+    e_phi = abs(phi - phi_ref) / abs(phi_ref)
+    e_g = _rel(g.cpu().numpy(), grad_ref)
+    say("  phi rel", e_phi, "grad rel L2", e_g)
+    assert e_phi <= 1e-10 and e_g <= 1e-8
+    s.close()
+
+
 def test_adjoint_gradient_finite_differences(torch_cuda):
     """Central differences (delta = 1e-6) of Phi from the GPU march at five voxels of a
     reduced version of the design problem (a 24^3 block eps_r = 10 with an 8^3 design
