@@ -3,12 +3,16 @@
 
 A step is one pass of the whole hot path for one time step: forward FFT of the newest
 current, spectral multiply-accumulate over all ell history lags, inverse FFT, right-hand
-side assembly (excitation, FIR, local terms) and the Z_0 solve.  The timed steps start
-after `warmup` steps; warmup defaults to more than ell so every timed step sums the full
-history.  The far part of the history sum runs once per time block (8 steps by default), so
-the timed window should be a whole number of blocks: the default 48 steps hold exactly 6 far
-launches, whatever the window's phase.  Kernel generation and spectra are one-time setup and
-are reported separately.
+side assembly (excitation, FIR, local terms) and the Z_0 solve.
+
+Set-up marches an untimed prefill of at least ell + 1 steps (reported as
+config.prefill_steps), so that every timed step sums the full history whatever the flags;
+the prefill ends where the `warmup` steps that follow end on a time-block boundary.  Then
+`warmup` untimed steps, then exactly `steps` timed steps.  The far part of the history sum
+runs once per time block (8 steps by default), at the first step of each block, so the timed
+window starts with one; a window that is a whole number of blocks (the default 48 steps hold
+6) weighs it exactly.  Kernel generation and spectra are one-time setup and are reported
+separately.
 
 Prints one JSON line (metric voxel*steps/s, FP64).
 """
@@ -163,7 +167,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=48, help="timed steps; a multiple of the time block")
-    ap.add_argument("--warmup", type=int, default=-1, help="default: ell + 8")
+    ap.add_argument("--warmup", type=int, default=8,
+                    help="untimed steps after the prefill of at least ell + 1 steps that set-up marches")
     ap.add_argument("--workload", default="C5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched (C3) and adjoint (C4) ratios")
@@ -202,11 +207,18 @@ def main():
     t_setup = time.perf_counter() - t_setup
     info = solver.info()
     ell = info["ell"]
-    warmup = args.warmup if args.warmup >= 0 else ell + 8
-    print("setup %.2f s (kernels %.0f ms, spectra %.0f ms), ell=%d, pads %dx%dx%d, %.1f GB" % (
+    warmup = max(0, args.warmup)
+    B = info["time_block"]
+    # prefill: at least ell + 1 steps, so that the ring holds ell sources and every far launch
+    # sums all ell lags; blocks start at steps 2, 2 + B, ..., and the step after prefill + warmup
+    # steps starts one when prefill + warmup = 1 mod B
+    prefill = ell + 1
+    while B > 1 and (prefill + warmup - 1) % B:
+        prefill += 1
+    print("setup %.2f s (kernels %.0f ms, spectra %.0f ms), ell=%d, pads %dx%dx%d, %.1f GB; prefill %d steps" % (
         t_setup, info["gen_ms"], info["spectra_ms"], ell, info["Nx"], info["Ny"], info["Nz"],
-        info["device_bytes"] / 1e9), file=sys.stderr, flush=True)
-
+        info["device_bytes"] / 1e9, prefill), file=sys.stderr, flush=True)
+    solver.run(prefill)
     if warmup:
         solver.run(warmup)
     torch.cuda.synchronize()
@@ -215,9 +227,10 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = solver.stats()
-    if info["time_block"] > 1 and args.steps % info["time_block"]:
-        print("note: %d timed steps are not a whole number of %d-step time blocks; the far part's share "
-              "of the step time depends on where the window starts" % (args.steps, info["time_block"]),
+    if B > 1 and args.steps % B:
+        print("note: %d timed steps are not a whole number of %d-step time blocks: the window starts with a "
+              "far launch and holds %d of them, %.3f per step against 1/%d" % (
+                  args.steps, B, st["far_launches"], st["far_launches"] / args.steps, B),
               file=sys.stderr, flush=True)
     M = prob.M
     value = M * args.steps / elapsed
@@ -231,7 +244,6 @@ def main():
     Hx = Nx // 2 + 1
     half = Hx * Ny * Nz                       # half-spectrum points
     octant = Hx * (Ny // 2 + 1) * (Nz // 2 + 1)
-    B = info["time_block"]
     if B > 1:
         # per launch: every one of the ell lags once (48 B of Jhat per point, 48 B of Khat per
         # octant point) and B partial sums written (48 B per point each)
@@ -280,7 +292,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
                    "grid": [prob.U, prob.V, prob.W], "voxels": M, "ell": ell, "pad": [Nx, Ny, Nz],
-                   "fir_taps": len(prob.fir), "setup_s": round(t_setup, 3),
+                   "fir_taps": len(prob.fir), "setup_s": round(t_setup, 3), "prefill_steps": prefill,
+                   "far_launches_timed": int(st["far_launches"]),
                    "phase_ms": {k: round(st[k], 4) for k in ("fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms",
                                                               "z0_ms")},
                    "cg_iters": round(st["cg_iters"], 2), "time_block": B,
@@ -291,11 +304,6 @@ def main():
                      "kernel": kname, "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": launch_ms, "fp64": fp64, "convolution": conv},
     }
-    if warmup < ell + 1:
-        # the per-launch figures count every lag; before step ell + 1 a launch sums fewer
-        line["roofline"] = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                            "traffic": None, "kernel": kname,
-                            "note": "warmup %d < ell + 1: the timed launches do not sum all %d lags" % (warmup, ell)}
     solver.close()
     del solver
     torch.cuda.synchronize()

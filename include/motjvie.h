@@ -66,7 +66,7 @@ typedef struct {
     const double *fir;        /* host taps delta_0..delta_{n_fir-1} (Sec. 6.1); may be NULL if n_fir == 0 */
     int32_t n_fir;            /* 0 = no regularisation */
     int32_t n_rhs;            /* number of right-hand sides (plane waves) marched together, >= 1 */
-    double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-12 */
+    double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-13 */
     int32_t cg_maxit;         /* <= 0 selects 200 */
     int32_t time_block;       /* steps per time block of the history MAC: 1 (none), 4, 8, 16 or 32; 0 selects the default */
     void *stream;             /* hipStream_t to enqueue on; NULL = the null stream */
@@ -111,7 +111,8 @@ int mj_info(const mj_solver *s, double *out, int32_t n);
  *   khat[n_rhs][3] (unit), pol[n_rhs][3], width[n_rhs] (> 0), ct0[n_rhs], amp[n_rhs],
  *   r_ref[n_rhs][3].  The paper's pulse (eq:GaussPlaneWave) is amp = 4 E0/(sigma sqrt(pi)),
  *   width = sigma/4.  The excitation E_n (eq:E) is chi_m times the voxel average of
- *   E^i at t_n, taken with an 8-point Gauss-Legendre rule per axis.
+ *   E^i at t_n, taken with an 8-point Gauss-Legendre rule per axis.  Every value must be
+ *   finite (else MJ_EINVAL and the previous waves stay).
  */
 int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, const double *width,
                        const double *ct0, const double *amp, const double *r_ref);
@@ -151,6 +152,24 @@ int mj_set_probes(mj_solver *s, int32_t n_probes, const double *pos);
 int mj_march(mj_solver *s, int32_t n_steps, double *J_hist, double *probe_hist);
 
 /*
+ * mj_step -- one step of eq:MOTInversion (n -> n + 1), the unit a caller's own time loop is
+ *   built from.  J_dev: device, nullable, [n_rhs][3][W][V][U] receives J_{n+1}.  probe: device,
+ *   nullable, [n_rhs][n_probes][3] receives E^s_p(n + 1) (probes set by mj_set_probes).  Errors as
+ *   mj_run; the history sum of the step is the same as inside mj_run (a march of mj_step calls
+ *   repeats mj_run bit for bit).
+ */
+int mj_step(mj_solver *s, double *J_dev, double *probe);
+
+/*
+ * mj_march_every -- mj_march with the current history thinned: J_hist (device, nullable)
+ *   [n_steps / j_every][n_rhs][3][W][V][U] receives J_n of every j_every-th step of the call
+ *   (the j_every-th, 2 j_every-th, ... step; j_every >= 1, else MJ_EINVAL).  probe_hist
+ *   (device, nullable) [n_steps][n_rhs][n_probes][3] still receives every step.  For long
+ *   marches at full size (2000 steps of 27 MB each at 104^3) the caller keeps a sample only.
+ */
+int mj_march_every(mj_solver *s, int32_t n_steps, int32_t j_every, double *J_hist, double *probe_hist);
+
+/*
  * mj_probe_kernel_values -- K_k(r_p - r_m') as the probe path generates it, for n host
  *   requests: probe[n] (index into the probes set by mj_set_probes), voxel[n][3] (u, v, w)
  *   and lag[n] (>= 0).  out (host) [n][6]: xx, yy, zz, xy, xz, yz.
@@ -162,6 +181,7 @@ int mj_probe_kernel_values(mj_solver *s, int32_t n, const int32_t *probe, const 
  * mj_set_eps -- new relative permittivities (host [W][V][U], >= 1, copied) for the same
  *   grid: chi, the local coefficients c_k, Z_0 and its preconditioner are rebuilt; the
  *   interaction kernels do not depend on eps and are kept.  Only at n = 0, else MJ_ESTATE.
+ *   Clears the solver's working vectors like mj_reset.
  */
 int mj_set_eps(mj_solver *s, const double *eps_r);
 
@@ -187,7 +207,11 @@ int mj_set_eps(mj_solver *s, const double *eps_r);
 int mj_adjoint_gradient(mj_solver *s, int32_t n_steps, int32_t ckpt_every, double *phi, double *dphi_deps,
                         double *probe_hist);
 
-/* mj_reset -- restart the march at n = 0 (all past currents zero). */
+/*
+ * mj_reset -- restart the march at n = 0 (all past currents zero).  Also clears the Z_0
+ *   solver's working vectors, so a handle whose march ended in MJ_EUNSTABLE on non-finite
+ *   values marches again from a clean state.
+ */
 int mj_reset(mj_solver *s);
 
 /*

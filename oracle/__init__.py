@@ -17,7 +17,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = [os.path.join(_HERE, "kquad.c"), os.path.join(_HERE, "direct.c"), os.path.join(_HERE, "pairs.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("kquad.c", "direct.c", "pairs.c", "klist.c")]
 _BUILD = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_BUILD, "liboracle.so")
 _lib = None
@@ -49,6 +49,8 @@ def lib():
                                         ctypes.c_double, ctypes.c_int, dp]
         L.or_kernel_table_h.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_int, dp]
+        L.or_kernel_list_h.argtypes = [ctypes.c_double, dp, ctypes.c_long, ctypes.POINTER(ctypes.c_int), dp,
+                                       ctypes.c_int, ctypes.c_int, dp]
         L.or_conv.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
                               ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
         L.or_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]

@@ -86,11 +86,22 @@ def incident_average(U, V, W, wave, n: int, nquad: int = 8, r: float = 1.0, hv=N
     """<E^i>_m(n dt) = (1/|V_m|) Int_{V_m} E^i(r, n dt) dV, [3][W][V][U].  Lengths in the unit of
     the voxel edges hv (default 1, 1, 1); t0 and width are c t0 and the pulse width as lengths;
     c n dt = n r."""
+    wz, wy, wx = np.meshgrid(np.arange(W), np.arange(V), np.arange(U), indexing="ij")
+    return _wave_average(wx, wy, wz, wave, n, nquad, r, hv)
+
+
+def incident_average_voxels(voxels, wave, n: int, nquad: int = 8, r: float = 1.0, hv=None) -> np.ndarray:
+    """<E^i>_m(n dt) as incident_average, at a list of voxels [nv][3] (u, v, w): [3][nv]."""
+    v = np.asarray(voxels, dtype=np.int64).reshape(-1, 3)
+    return _wave_average(v[:, 0], v[:, 1], v[:, 2], wave, n, nquad, r, hv)
+
+
+def _wave_average(wx, wy, wz, wave, n, nquad, r, hv):
+    """Voxel averages of the plane wave at voxel indices (wx, wy, wz) (arrays of one shape)."""
     hx, hy, hz = _edges(hv)
     x, w = np.polynomial.legendre.leggauss(nquad)
     x = 0.5 * x
     w = 0.5 * w
-    wz, wy, wx = np.meshgrid(np.arange(W), np.arange(V), np.arange(U), indexing="ij")
     k = np.asarray(wave.khat, float)
     p = np.asarray(wave.pol, float)
     rr = np.asarray(wave.r_ref, float)
@@ -105,6 +116,106 @@ def incident_average(U, V, W, wave, n: int, nquad: int = 8, r: float = 1.0, hv=N
                 avg += w[i] * w[j] * w[l] * np.exp(-((tc - s) / wave.width) ** 2)
     avg *= wave.amp
     return np.stack([avg * p[0], avg * p[1], avg * p[2]])
+
+
+def kernel_list(lags, offsets, ngl: int = 16, r: float = 1.0, hv=None, skip_outside: bool = True) -> np.ndarray:
+    """K_k(D) for a list of lags [n] and offsets [n][3] (voxel steps): [n][6]; entries outside
+    the Huygens support are exactly 0 when skip_outside (the dense table's rule)."""
+    k = np.ascontiguousarray(np.asarray(lags, dtype=np.int32))
+    D = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1, 3))
+    out = np.zeros((len(k), 6))
+    lib().or_kernel_list_h(r, dptr(_edges(hv)), len(k), iptr(k), dptr(D), int(ngl), 1 if skip_outside else 0,
+                           dptr(out))
+    return out
+
+
+def canonical_offsets(offsets) -> np.ndarray:
+    """Sorted absolute values of integer offsets [n][3]: the representative of each class of
+    offsets that the symmetries used by kernel_values_by_symmetry relate."""
+    return np.sort(np.abs(np.asarray(offsets, dtype=np.int64).reshape(-1, 3)), axis=1)
+
+
+def kernel_values_by_symmetry(lags, offsets, canon) -> np.ndarray:
+    """K_k(D) [n][6] for cubic voxels from values at canonical offsets (sorted |D|), by the
+    symmetries of eq:Z that the oracle's pins check on directly computed entries: K^aa is even in
+    every D_i, K^ab (a != b) is odd in D_a and in D_b and even in the third, and permuting the
+    axes of D permutes the components alike.  canon[k][C0][C1][C2][6] holds K_k at the
+    canonical offsets C0 <= C1 <= C2 (zero where not needed)."""
+    D = np.asarray(offsets, dtype=np.int64).reshape(-1, 3)
+    k = np.broadcast_to(np.asarray(lags, dtype=np.int64), (len(D),))
+    a = np.abs(D)
+    order = np.argsort(a, axis=1, kind="stable")      # canonical axis j is axis order[:, j] of D
+    C = np.take_along_axis(a, order, axis=1)
+    pos = np.argsort(order, axis=1)                   # axis x of D is canonical axis pos[:, x]
+    Kc = canon[k, C[:, 0], C[:, 1], C[:, 2]]          # [n][6]
+    sg = np.where(D < 0, -1.0, 1.0)
+    comp = np.array(COMP)
+    out = np.zeros((len(D), 6))
+    for x in range(3):
+        for y in range(x, 3):
+            v = np.take_along_axis(Kc, comp[pos[:, x], pos[:, y]][:, None], axis=1)[:, 0]
+            out[:, comp[x][y]] = v if x == y else v * sg[:, x] * sg[:, y]
+    return out
+
+
+def restricted_march(prob, voxels, n_steps: int, rhs: int = 0, ngl: int = 16) -> np.ndarray:
+    """The march of eq:MOTInversion on the unknowns of a list of voxels [nv][3] (u, v, w) that holds
+    every voxel with eps_r != 1.  Any other voxel has chi = 0: its row of every Z_k reduces to
+    c_k J(m) = E_n(m) = 0 (eq:E carries the factor chi), so its current vanishes at every step,
+    and its column multiplies that zero; dropping both leaves the listed voxels' currents
+    unchanged.  Z_k over the listed voxels is dense, c_k(m) on the diagonal minus
+    chi_m K_k(r_m - r_m') (eq:Z with Sec. 6.1's taps); the history sum of eq:PnMOT is one
+    dense product per lag and Z_0 is solved densely.  Returns J [n_steps][3][nv]."""
+    vox = np.asarray(voxels, dtype=np.int64).reshape(-1, 3)
+    nv = len(vox)
+    hv = problem_edges(prob)
+    assert prob.h == 1.0
+    r = float(prob.c_dt)
+    L = ell(prob.U, prob.V, prob.W, 1.0, r, hv[1], hv[2])
+    eps = prob.eps[vox[:, 2], vox[:, 1], vox[:, 0]]
+    chi = chi_of(eps)
+    assert np.all(np.delete(prob.eps.ravel(), vox[:, 0] + prob.U * (vox[:, 1] + prob.V * vox[:, 2])) == 1.0), \
+        "every voxel with eps_r != 1 must be listed"
+    fir = np.asarray(prob.fir, float)
+    # kernel values of every ordered pair and lag: offsets r_m - r_m' in voxel steps
+    D = (vox[:, None, :] - vox[None, :, :]).reshape(-1, 3)
+    uniq, inv = np.unique(D, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    lags = np.repeat(np.arange(L + 1), len(uniq))
+    Kv = kernel_list(lags, np.tile(uniq, (L + 1, 1)), ngl, r, hv).reshape(L + 1, len(uniq), 6)
+    comp = np.array(COMP)                                   # [b][a] -> stored component
+    Z = np.zeros((L + 1, 3, nv, 3, nv))
+    for k in range(L + 1):
+        Kk = Kv[k][inv].reshape(nv, nv, 6)                  # [m][m'][6]
+        ck = tbasis(k) / eps + (fir[k] if k < len(fir) else 0.0)
+        for b in range(3):
+            for a in range(3):
+                Z[k, b, :, a, :] = -chi[:, None] * Kk[:, :, comp[b][a]]
+            Z[k, b, np.arange(nv), b, np.arange(nv)] += ck
+    Z = Z.reshape(L + 1, 3 * nv, 3 * nv)
+    depth = max(L, len(fir) - 1, 1)
+    J = np.zeros((n_steps + 1, 3 * nv))
+    Z0inv_lu = scipy_lu_factor(Z[0])
+    for n in range(1, n_steps + 1):
+        P = np.zeros(3 * nv)
+        for k in range(1, min(depth, n - 1) + 1):
+            if k <= L:
+                P += Z[k] @ J[n - k]
+            else:   # a FIR tap beyond the kernel's support acts on the voxel's own current
+                P += fir[k] * J[n - k]
+        E = chi[None, :] * incident_average_voxels(vox, prob.waves[rhs], n, r=r, hv=hv)
+        J[n] = scipy_lu_solve(Z0inv_lu, E.ravel() - P)
+    return J[1:].reshape(n_steps, 3, nv)
+
+
+def scipy_lu_factor(A):
+    import scipy.linalg as sla
+    return sla.lu_factor(A)
+
+
+def scipy_lu_solve(lu, b):
+    import scipy.linalg as sla
+    return sla.lu_solve(lu, b)
 
 
 def conv(K: np.ndarray, Jh: np.ndarray, targets=None) -> np.ndarray:

@@ -57,7 +57,7 @@ struct mj_solver {
     int nrhs = 1, ell = 0;
     int Nx = 0, Ny = 0, Nz = 0, Hx = 0, Hp = 0;
     std::vector<double> fir;
-    double cg_rtol = 1e-12;
+    double cg_rtol = 1e-13;
     int cg_maxit = 200;
     int B = 1;
     int nquad = 16;
@@ -167,7 +167,8 @@ struct mj_solver {
     mj::AdjArg adj_arg() const;
     void step(const StepIO &io);
     void check_growth() const;
-    void run(int n_steps, double *Jout, double *Pout);
+    void run(int n_steps, double *Jout, double *Pout, int j_every = 1);
+    void restart();
     void adjoint_gradient(int n_steps, int ckpt_every, double *phi, double *grad_dev, double *probe_hist);
     size_t state_bytes() const;
     void get_state(void *buf) const;
@@ -206,7 +207,7 @@ void mj_solver::create(const mj_config &c)
     hz = c.hz > 0.0 ? c.hz : c.h;
     c_dt = c.c_dt;
     nrhs = c.n_rhs;
-    cg_rtol = c.cg_rtol > 0 ? c.cg_rtol : 1e-12;
+    cg_rtol = c.cg_rtol > 0 ? c.cg_rtol : 1e-13;
     cg_maxit = c.cg_maxit > 0 ? c.cg_maxit : 200;
     nquad = c.quad_order > 0 ? c.quad_order : 16;
     st = (hipStream_t)c.stream;
@@ -638,7 +639,9 @@ mj::AdjArg mj_solver::adj_arg() const
     return a;
 }
 
-void mj_solver::run(int n_steps, double *Jout, double *Pout)
+// J_n goes to Jout for every j_every-th step of the call (steps s = j_every - 1, 2 j_every - 1, ...
+// counted from 0), entry (s + 1) / j_every - 1; the probe field of every step goes to Pout.
+void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
 {
     if (!waves_set) throw std::logic_error("plane waves not set (mj_set_plane_waves)");
     events.ensure((size_t)7 * std::max(n_steps, 1));
@@ -648,7 +651,7 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout)
     for (int s = 0; s < n_steps; s++) {
         StepIO io;
         io.ev = &events.ev[(size_t)7 * s];
-        io.Jout = Jout ? Jout + (size_t)s * nrhs * 3 * M : nullptr;
+        io.Jout = (Jout && (s + 1) % j_every == 0) ? Jout + (size_t)((s + 1) / j_every - 1) * nrhs * 3 * M : nullptr;
         io.Pout = Pout ? Pout + (size_t)s * nrhs * np * 3 : nullptr;
         io.far_kind = &step_far[s];
         step(io);
@@ -690,6 +693,21 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout)
     stat[12] = nnear ? near_ms / nnear : 0.0;
     stat[13] = probe_ms / ns;
     if (noconv) throw std::range_error("Z_0 solve did not converge");
+}
+
+// Back to n = 0 with every past current zero.  The search directions p and q enter the first
+// iteration of each Z_0 solve multiplied by beta = 0, so they must be finite: a march that ended
+// on non-finite values (MJ_EUNSTABLE) would otherwise turn every later solve into NaN through
+// 0 * Inf.  They are cleared here, as at mj_create.
+void mj_solver::restart()
+{
+    const size_t v = sizeof(double) * (size_t)nrhs * 3 * M;
+    MJ_CHECK(hipMemsetAsync(p, 0, v, st));
+    MJ_CHECK(hipMemsetAsync(q, 0, v, st));
+    MJ_CHECK(hipMemsetAsync(y, 0, v, st));
+    MJ_CHECK(hipStreamSynchronize(st));
+    cg_guess = 8;
+    n = 0;
 }
 
 void mj_solver::history_sum(const double *Jh, int depth, double *P)
@@ -1263,7 +1281,10 @@ int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, cons
                 kn += khat[3 * i + c] * khat[3 * i + c];
             }
             if (!(std::fabs(kn - 1.0) < 1e-12)) throw ArgError("khat must be a unit vector");
-            if (!(width[i] > 0.0)) throw ArgError("width must be positive");
+            if (!(width[i] > 0.0) || !std::isfinite(width[i])) throw ArgError("width must be positive and finite");
+            bool fin = std::isfinite(ct0[i]) && std::isfinite(amp[i]);
+            for (int c = 0; c < 3; c++) fin = fin && std::isfinite(pol[3 * i + c]) && std::isfinite(r_ref[3 * i + c]);
+            if (!fin) throw ArgError("wave parameters must be finite");
             w[i].width = width[i];
             w[i].ct0 = ct0[i];
             w[i].amp = amp[i];
@@ -1288,12 +1309,27 @@ int mj_march(mj_solver *s, int32_t n_steps, double *J_hist, double *probe_hist)
     return guarded(s, [&] { s->run(n_steps, J_hist, probe_hist); });
 }
 
+int mj_step(mj_solver *s, double *J_dev, double *probe)
+{
+    if (!s) return MJ_EINVAL;
+    return guarded(s, [&] { s->run(1, J_dev, probe); });
+}
+
+int mj_march_every(mj_solver *s, int32_t n_steps, int32_t j_every, double *J_hist, double *probe_hist)
+{
+    if (!s) return MJ_EINVAL;
+    if (n_steps < 0) return fail(s, MJ_EINVAL, "n_steps < 0");
+    if (j_every < 1) return fail(s, MJ_EINVAL, "j_every < 1");
+    return guarded(s, [&] { s->run(n_steps, J_hist, probe_hist, j_every); });
+}
+
 int mj_set_eps(mj_solver *s, const double *eps_r)
 {
     if (!s || !eps_r) return MJ_EINVAL;
     return guarded(s, [&] {
         if (s->n != 0) throw std::logic_error("eps is changed at n = 0 (after mj_create or mj_reset)");
         s->set_material(eps_r);
+        s->restart();
     });
 }
 
@@ -1322,8 +1358,7 @@ int mj_probe_kernel_values(mj_solver *s, int32_t n, const int32_t *probe, const 
 int mj_reset(mj_solver *s)
 {
     if (!s) return MJ_EINVAL;
-    s->n = 0;
-    return MJ_OK;
+    return guarded(s, [&] { s->restart(); });
 }
 
 int mj_get_state(const mj_solver *s, void *buf, size_t *bytes)

@@ -69,6 +69,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_fft_roundtrip.argtypes = [vp, vp, vp, vp]
     L.mj_set_probes.argtypes = [vp, ctypes.c_int32, dp]
     L.mj_march.argtypes = [vp, ctypes.c_int32, vp, vp]
+    L.mj_step.argtypes = [vp, vp, vp]
+    L.mj_march_every.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
     L.mj_probe_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, ip, dp]
     L.mj_set_eps.argtypes = [vp, dp]
     L.mj_adjoint_gradient.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, vp, vp]
@@ -76,7 +78,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_set_state.argtypes = [vp, vp, ctypes.c_size_t]
     for f in ("mj_create", "mj_info", "mj_set_plane_waves", "mj_run", "mj_reset", "mj_history_sum",
               "mj_kernel_values", "mj_stats", "mj_fft_roundtrip", "mj_set_probes", "mj_march",
-              "mj_probe_kernel_values", "mj_set_eps", "mj_adjoint_gradient", "mj_get_state", "mj_set_state"):
+              "mj_probe_kernel_values", "mj_set_eps", "mj_adjoint_gradient", "mj_get_state", "mj_set_state",
+              "mj_step", "mj_march_every"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -180,17 +183,31 @@ class Solver:
         self.n_probes = len(pos)
         self._check(self._lib.mj_set_probes(self._h, len(pos), _dptr(pos) if len(pos) else None))
 
-    def run(self, n_steps: int, J_out=None, probes_out=None):
-        """March n_steps; J_out (optional) is a CUDA tensor [n_steps][n_rhs][3][W][V][U],
-        probes_out (optional) a CUDA tensor [n_steps][n_rhs][n_probes][3]."""
+    def run(self, n_steps: int, J_out=None, probes_out=None, j_every: int = 1):
+        """March n_steps; J_out (optional) is a CUDA tensor [n_steps // j_every][n_rhs][3][W][V][U]
+        receiving J of every j_every-th step, probes_out (optional) a CUDA tensor
+        [n_steps][n_rhs][n_probes][3]."""
         if J_out is not None:
-            assert J_out.numel() == n_steps * self.n_rhs * 3 * self.M
-        if probes_out is None:
+            assert J_out.numel() == (n_steps // j_every) * self.n_rhs * 3 * self.M
+        if probes_out is not None:
+            assert probes_out.numel() == n_steps * self.n_rhs * getattr(self, "n_probes", 0) * 3
+        if j_every != 1:
+            self._check(self._lib.mj_march_every(self._h, int(n_steps), int(j_every), _tptr(J_out, "J_out"),
+                                                 _tptr(probes_out, "probes_out")))
+        elif probes_out is None:
             self._check(self._lib.mj_run(self._h, int(n_steps), _tptr(J_out, "J_out")))
-            return
-        assert probes_out.numel() == n_steps * self.n_rhs * getattr(self, "n_probes", 0) * 3
-        self._check(self._lib.mj_march(self._h, int(n_steps), _tptr(J_out, "J_out"),
-                                       _tptr(probes_out, "probes_out")))
+        else:
+            self._check(self._lib.mj_march(self._h, int(n_steps), _tptr(J_out, "J_out"),
+                                           _tptr(probes_out, "probes_out")))
+
+    def step(self, J_out=None, probe_out=None):
+        """One step; J_out [n_rhs][3][W][V][U] and probe_out [n_rhs][n_probes][3] are optional
+        CUDA tensors."""
+        if J_out is not None:
+            assert J_out.numel() == self.n_rhs * 3 * self.M
+        if probe_out is not None:
+            assert probe_out.numel() == self.n_rhs * getattr(self, "n_probes", 0) * 3
+        self._check(self._lib.mj_step(self._h, _tptr(J_out, "J_out"), _tptr(probe_out, "probe_out")))
 
     def probe_kernel_values(self, probe, voxels, lags) -> np.ndarray:
         probe = np.ascontiguousarray(np.asarray(probe, dtype=np.int32))

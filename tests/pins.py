@@ -194,3 +194,49 @@ def axis_wave_voxel_average(tau_centre, width, hz=1.0):
     else:
         d = erf(a) - erf(b)
     return 0.5 * width * sqrt(pi) * d / hz
+
+
+def box_wave_average(tau0, c, width):
+    """Average over the box [0,1]^3 (coordinates eta) of exp(-((tau0 - sum_i c_i eta_i)/width)^2).
+
+    tau0 is the pulse's retarded argument at the box's lower corner and c_i = khat_i L_i the
+    change of the argument along edge i (L_i the edge).  Averaging over one uniform eta is a
+    backward difference of an antiderivative: (1/c) Int_0^c g(t - s) ds = (F(t) - F(t - c)) / c.
+    Three of them give the third difference of the third antiderivative of the Gaussian,
+    written with erf: with x = t / width,
+        F_1 = width (sqrt(pi)/2) erf x,
+        F_2 = width^2 (sqrt(pi)/2) (x erf x + exp(-x^2)/sqrt(pi)),
+        F_3 = width^3 (sqrt(pi)/2) ((x^2/2 + 1/4) erf x + x exp(-x^2)/(2 sqrt(pi))).
+    Edges with c_i = 0 drop out (the average over them is the identity).  Evaluated with 50
+    digits (mpmath), so that the differences of nearly equal values lose nothing in double."""
+    import mpmath as mp
+    with mp.workdps(50):
+        w = mp.mpf(width)
+        sp = mp.sqrt(mp.pi)
+
+        def F(order, t):
+            x = t / w
+            if order == 0:
+                return mp.exp(-x * x)
+            if order == 1:
+                return w * sp / 2 * mp.erf(x)
+            if order == 2:
+                return w ** 2 * sp / 2 * (x * mp.erf(x) + mp.exp(-x * x) / sp)
+            return w ** 3 * sp / 2 * ((x * x / 2 + mp.mpf(1) / 4) * mp.erf(x) + x * mp.exp(-x * x) / (2 * sp))
+
+        cs = [mp.mpf(ci) for ci in c if ci != 0.0]
+        m = len(cs)
+        tot = mp.mpf(0)
+        # sum over the 2^m corners of the difference stencil
+        for mask in range(1 << m):
+            shift = mp.mpf(0)
+            sign = 1
+            for i in range(m):
+                if mask >> i & 1:
+                    shift += cs[i]
+                    sign = -sign
+            tot += sign * F(m, mp.mpf(tau0) - shift)
+        den = mp.mpf(1)
+        for ci in cs:
+            den *= ci
+        return float(tot / den)

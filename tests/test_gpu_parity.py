@@ -21,6 +21,8 @@ def torch_cuda():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    from paper_2407_03323_amd import build
+    assert build.is_current(), "libmotjvie.so is older than its sources: run paper_2407_03323_amd/build.py"
     return torch
 
 
@@ -365,22 +367,22 @@ def test_stability_toolkit_matches_oracle(torch_cuda, delta):
         assert pd[-1] > 0.0          # D_L stays positive: the PDSA alone does not see this mode
 
 
-@pytest.mark.parametrize("name", ["C2", "C4"])
+@pytest.mark.parametrize("name", ["C2", "C4", "C5"])
 def test_workload_march_stays_bounded(torch_cuda, name):
     """The workloads' 17-tap FIR (delta = 0.01) keeps the march stable over the configuration's
-    full length: the current decays after the pulse instead of growing (with delta = 0.1 the
-    same filter fails the third requirement of Sec. 6.1 and the 32^3 sphere grows past 1e14 by
-    step 1000)."""
+    full length (2000 steps for the 104^3 cube): the current decays after the pulse instead of
+    growing (with delta = 0.1 the same filter fails the third requirement of Sec. 6.1 and the
+    32^3 sphere grows past 1e14 by step 1000).  The current is kept every 100th step."""
     torch = torch_cuda
     p = wl.config(name)
     say("bounded march", name, p.n_steps, "steps")
     s = make_solver(p)
     chunk, norms = 100, []
+    J = torch.zeros((1, 1, 3, p.W, p.V, p.U), dtype=torch.float64, device="cuda")
     for _ in range(p.n_steps // chunk):
-        J = torch.zeros((chunk, 1, 3, p.W, p.V, p.U), dtype=torch.float64, device="cuda")
-        s.run(chunk, J)
+        s.run(chunk, J, j_every=chunk)
         torch.cuda.synchronize()
-        norms.append(float(J[-1].norm()))
+        norms.append(float(J[0].norm()))
     s.close()
     say("  |J| every 100 steps", ["%.2e" % v for v in norms])
     peak = max(norms[:3])
@@ -625,6 +627,47 @@ def test_adjoint_gradient_finite_differences(torch_cuda):
     s.close()
 
 
+def test_adjoint_gradient_finite_differences_C4(torch_cuda):
+    """The design workload as configured: 48^3 with eps_r = 10 and the central 16^3 design block
+    of eps_r ~ U[1, 12] (seed 4), 32 probes on a sphere of radius 48 h, 800 steps, the 17-tap
+    FIR, checkpoints every 50 steps.  dPhi/deps_r from the transposed march against central
+    differences (delta = 1e-6) of Phi from forward marches, at 20 design voxels with
+    eps_r >= 1.01 drawn with seed 44."""
+    torch = torch_cuda
+    prob = wl.config("C4")
+    n = prob.n_steps
+    say("adjoint FD 48^3, %d steps" % n)
+    s = make_solver(prob, time_block=8, cg_rtol=1e-14)
+    s.set_probes(prob.probes)
+    g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    phi0 = s.adjoint_gradient(n, g, 50)
+    grad = g.cpu().numpy()
+    say("  Phi %.6e, %d segments" % (phi0, s.stats()["adjoint_segments"]))
+    rng = np.random.default_rng(44)
+    design = np.argwhere(prob.eps[16:32, 16:32, 16:32] >= 1.01) + 16
+    pick = design[rng.choice(len(design), 20, replace=False)]
+    Pt = torch.zeros((n, 1, len(prob.probes), 3), dtype=torch.float64, device="cuda")
+    gmax = np.abs(grad).max()
+    worst = 0.0
+    for (w, v, u) in pick:
+        vals = []
+        for sgn in (1.0, -1.0):
+            e2 = prob.eps.copy()
+            e2[w, v, u] += sgn * 1e-6
+            s.reset()
+            s.set_eps(e2)
+            s.run(n, None, Pt)
+            torch.cuda.synchronize()
+            vals.append(float((Pt.cpu().numpy() ** 2).sum()))
+        fd = (vals[0] - vals[1]) / 2e-6
+        err = abs(fd - grad[w, v, u]) / gmax
+        say("  voxel %s eps %.3f fd %.9e adjoint %.9e err/max %.2e" % ((u, v, w), prob.eps[w, v, u], fd,
+                                                                      grad[w, v, u], err))
+        worst = max(worst, err)
+    assert worst <= 1e-5
+    s.close()
+
+
 def test_probe_objective_autograd(torch_cuda, adjoint_oracle):
     """torch.autograd through ProbeObjective returns the oracle's gradient."""
     torch = torch_cuda
@@ -705,6 +748,131 @@ def test_full_size_104_sampled(torch_cuda):
     say("  kernels worst", worst)
     assert worst <= 3e-12
     s.close()
+
+
+def _golden_script(name):
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".py")
+    spec = importlib.util.spec_from_file_location(name, path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_C2_steps_satisfy_the_march_equation(torch_cuda):
+    """The 32^3 sphere workload as configured (eps_r 12 inside radius 15, 64^3 pads, ell = 57,
+    time block 8, the 17-tap FIR): at steps 60, 400 and 900 of the GPU march, the march
+    equation sum_{k=0}^{ell} Z_k J_{n-k} = E_n (eq:MOTInversion with eq:PnMOT) holds at 16
+    sampled sphere voxels (12 near the centre, 4 at the surface) when the oracle's Z_k and E_n
+    act on the GPU's own currents J_{n-ell}..J_n: that is, the GPU's J_n is the oracle's step
+    from the GPU's history.  The residual is at most 1e-10 of the right-hand side
+    E_n - P_{n-1} over the samples.  The oracle's kernels at the needed offsets come from
+    tests/golden/c2_kernels.npz (written by the script beside it from oracle/ alone), and the
+    GPU's currents vanish exactly outside the sphere."""
+    from oracle import mot
+    torch = torch_cuda
+    gk = _golden_script("make_c2_kernels")
+    p = wl.config("C2")
+    U, V, W = p.U, p.V, p.W
+    L = mot.ell(U, V, W)
+    targets = gk.spot_targets(p)
+    if not os.path.exists(gk.OUT):
+        say("C2 check: computing the oracle's kernels (no stored file)")
+        gk.main()
+    d = np.load(gk.OUT)
+    canon = np.zeros((L + 1, U, U, U, 6))
+    for key, val in zip(d["keys"], d["vals"]):
+        canon[key[0], key[1], key[2], key[3]] = val
+    nmax = 900
+    say("C2 check: GPU march of %d steps" % nmax)
+    s = make_solver(p)
+    assert s.ell == L
+    J = torch.zeros((nmax, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+    s.run(nmax, J)
+    Jh = J.cpu().numpy()[:, 0]
+    del J
+    s.close()
+    assert np.all(Jh[:, :, p.eps == 1.0] == 0.0)
+    src = np.argwhere(p.eps > 1.0)[:, ::-1]
+    chi = mot.chi_of(p.eps)
+    c = mot.local_coefficients(p.eps, p.fir, max(L, len(p.fir) - 1))
+    comp = np.array(mot.COMP)
+    worst = 0.0
+    for n in (60, 400, 900):
+        res = np.zeros((3, len(targets)))
+        rhs = np.zeros((3, len(targets)))
+        E = chi[None] * mot.incident_average(U, V, W, p.waves[0], n)
+        for it, t in enumerate(targets):
+            u, v, w = t
+            D = t[None, :] - src
+            lhs = np.zeros(3)
+            Z0J = np.zeros(3)
+            for k in range(0, min(L, n - 1) + 1):
+                Jk = Jh[n - 1 - k][:, src[:, 2], src[:, 1], src[:, 0]]        # [3][ns] = J_{n-k}
+                Kk = mot.kernel_values_by_symmetry(k, D, canon)                 # [ns][6]
+                conv = np.array([sum(Kk[:, comp[b][a]] @ Jk[a] for a in range(3)) for b in range(3)])
+                term = c[k][w, v, u] * Jh[n - 1 - k][:, w, v, u] - chi[w, v, u] * conv
+                lhs += term
+                if k == 0:
+                    Z0J = term
+            for k in range(L + 1, min(len(p.fir), n)):
+                lhs += c[k][w, v, u] * Jh[n - 1 - k][:, w, v, u]
+            res[:, it] = lhs - E[:, w, v, u]
+            rhs[:, it] = Z0J
+        e = np.abs(res).max() / np.abs(rhs).max()
+        say("  step %d: max |residual| / max |E_n - P_n-1| = %.3e" % (n, e))
+        worst = max(worst, e)
+    assert worst <= 1e-10
+
+
+def test_full_size_104_march_matches_oracle(torch_cuda):
+    """The march at full size in the configuration bench.py times: the 104^3 grid (208^3 pads,
+    ell = 182, time block 8, the 17-tap FIR with delta = 0.01, the 104^3 workload's plane wave),
+    with eps_r = 1 except four 2^3 blocks (eps_r 12, 6, 9, 4) 95 to 162 voxels apart.  400 steps:
+    the ring of 182 spectra wraps twice, every position in a time block recurs 50 times, and
+    the blocks couple through lags 93 to 165, which only the far part of the history sum
+    carries.  J(t) of the 32 block voxels over all steps against the oracle's dense march
+    restricted to them (exact, since chi = 0 elsewhere), and J exactly zero everywhere else."""
+    from oracle import mot
+    torch = torch_cuda
+    p = wl.config("C5")
+    U = p.U
+    eps = np.ones((U, U, U))
+    corners = [(3, 4, 2), (98, 3, 5), (10, 97, 96), (97, 95, 97)]
+    vox = []
+    for (u0, v0, w0), e in zip(corners, [12.0, 6.0, 9.0, 4.0]):
+        for dw in range(2):
+            for dv in range(2):
+                for du in range(2):
+                    eps[w0 + dw, v0 + dv, u0 + du] = e
+                    vox.append((u0 + du, v0 + dv, w0 + dw))
+    vox = np.array(vox)
+    p.eps = eps
+    n, chunk = 400, 50
+    say("104^3 march parity: create")
+    s = make_solver(p, time_block=8)
+    assert s.ell == 182 and s.info()["Nx"] == 208
+    J = torch.zeros((chunk, 1, 3, U, U, U), dtype=torch.float64, device="cuda")
+    iu, iv, iw = (torch.tensor(vox[:, i], device="cuda") for i in range(3))
+    got, outside = [], 0
+    for c in range(n // chunk):
+        s.run(chunk, J)
+        got.append(J[:, 0][:, :, iw, iv, iu].cpu().numpy())    # [chunk][3][32]
+        J[:, 0, :, iw, iv, iu] = 0.0
+        outside = max(outside, int(torch.count_nonzero(J)))
+        say("  steps %d..%d marched" % (c * chunk + 1, (c + 1) * chunk))
+    st = s.stats()
+    s.close()
+    got = np.concatenate(got)
+    say("104^3 march parity: oracle")
+    ref = mot.restricted_march(p, vox, n)
+    err = _rel(got, ref)
+    late = _rel(got[250:], ref[250:])
+    say("  J rel L2 all steps %.3e, steps 251-400 (coupled through the far part) %.3e, non-zero outside %d, cg %.1f it" % (
+        err, late, outside, st["cg_iters"]))
+    assert outside == 0
+    assert err <= 1e-8
+    assert late <= 1e-8
 
 
 # ----------------------------------------------------------------------------- c dt < h
@@ -1006,3 +1174,99 @@ def test_unbounded_growth_is_reported(torch_cuda):
     s.run(300)
     assert s.info()["n"] == 300
     s.close()
+
+
+def _small_problem(n=40):
+    U, V, W = 4, 3, 3
+    eps = wl.random_eps(U, V, W, 17, 2.0, 10.0)
+    k, p = wl.XPOL_PLUS_Z
+    return wl.Problem("small", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 3.0)], n,
+                      fir=wl.binomial_highpass(3, 0.1))
+
+
+def test_reset_after_nonfinite_march_matches_oracle(torch_cuda):
+    """A march resumed from a state whose real-space history holds NaN ends with MJ_EUNSTABLE at
+    its first step (the Z_0 right-hand side is not finite), leaving NaN in the solver's working
+    vectors.  mj_reset clears them: the same handle then marches the oracle's currents, and so
+    does it after mj_set_eps with another material."""
+    from oracle import mot
+    from paper_2407_03323_amd.motjvie import MJ_EUNSTABLE, MotJvieError
+    torch = torch_cuda
+    prob = _small_problem()
+    n = prob.n_steps
+    s = make_solver(prob, time_block=8)
+    s.run(10)
+    st = s.get_state()
+    jr = s.info()["real_depth"] * 3 * prob.M * 8
+    bad = st.copy()
+    bad[len(bad) - jr:] = np.frombuffer(np.full(jr // 8, np.nan).tobytes(), dtype=np.uint8)
+    s.set_state(bad)
+    with pytest.raises(MotJvieError) as ei:
+        s.run(5)
+    assert ei.value.code == MJ_EUNSTABLE
+    s.reset()
+    J = torch.zeros((n, 1, 3, prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    s.run(n, J)
+    ref = mot.Oracle(prob).run(n)
+    err = _rel(J.cpu().numpy()[:, 0], ref)
+    say("  after reset: rel L2", err)
+    assert err <= 1e-8
+    # the same again through mj_set_eps (which also clears the working vectors)
+    s.reset()
+    s.set_state(bad)
+    with pytest.raises(MotJvieError):
+        s.run(3)
+    s.reset()
+    eps2 = wl.random_eps(prob.U, prob.V, prob.W, 18, 2.0, 8.0)
+    s.set_eps(eps2)
+    s.run(n, J)
+    prob2 = wl.Problem("small2", prob.U, prob.V, prob.W, eps2, prob.waves, n, fir=prob.fir)
+    err = _rel(J.cpu().numpy()[:, 0], mot.Oracle(prob2).run(n))
+    say("  after set_eps: rel L2", err)
+    assert err <= 1e-8
+    s.close()
+
+
+def test_wave_parameters_must_be_finite(torch_cuda):
+    """mj_set_plane_waves refuses non-finite values (MJ_EINVAL) and keeps the previous waves."""
+    import dataclasses
+    from paper_2407_03323_amd.motjvie import MJ_EINVAL, MotJvieError
+    prob = _small_problem(10)
+    s = make_solver(prob)
+    for field, val in (("amp", float("nan")), ("t0", float("inf")), ("pol", (float("nan"), 0.0, 0.0)),
+                       ("r_ref", (0.0, float("inf"), 0.0)), ("width", float("inf"))):
+        with pytest.raises(MotJvieError) as ei:
+            s.set_plane_waves([dataclasses.replace(prob.waves[0], **{field: val})])
+        assert ei.value.code == MJ_EINVAL
+    s.run(10)
+    s.close()
+
+
+@pytest.mark.parametrize("tb", [1, 8])
+def test_step_and_thinned_march_repeat_run(torch_cuda, tb):
+    """mj_step called once per step, and mj_march_every keeping every 7th current, repeat mj_run
+    (with probes) bit for bit."""
+    torch = torch_cuda
+    prob = _small_problem(30)
+    n = prob.n_steps
+    probes = np.array([[2.0, 1.5, 6.0], [-3.0, 1.0, 1.5]])
+    a = make_solver(prob, time_block=tb)
+    a.set_probes(probes)
+    J = torch.zeros((n, 1, 3, prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    P = torch.zeros((n, 1, 2, 3), dtype=torch.float64, device="cuda")
+    a.run(n, J, P)
+    b = make_solver(prob, time_block=tb)
+    b.set_probes(probes)
+    Jb = torch.zeros_like(J)
+    Pb = torch.zeros_like(P)
+    for i in range(n):
+        b.step(Jb[i], Pb[i])
+    assert b.info()["n"] == n
+    assert torch.equal(J, Jb) and torch.equal(P, Pb)
+    b.reset()
+    Jt = torch.zeros((n // 7, 1, 3, prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+    Pt = torch.zeros_like(P)
+    b.run(n, Jt, Pt, j_every=7)
+    assert torch.equal(Jt, J[6::7][: n // 7]) and torch.equal(Pt, P)
+    a.close()
+    b.close()

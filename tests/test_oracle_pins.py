@@ -268,6 +268,68 @@ def test_excitation_axis_wave_closed_form():
             assert np.all(E[1:] == 0.0)
 
 
+def _perp(k, seed_vec):
+    """A unit vector orthogonal to k (Gram-Schmidt of seed_vec)."""
+    k = np.asarray(k, float)
+    v = np.asarray(seed_vec, float) - np.dot(seed_vec, k) * k
+    return tuple(v / np.linalg.norm(v))
+
+
+S2 = sqrt(2.0)
+OBLIQUE_CASES = [
+    # khat, polarisation seed, voxel edges, c dt, reference point of the pulse (None: the box
+    # corner the front reaches first, as the workloads choose it)
+    ((0.0, 0.6, 0.8), (1.0, 0.0, 0.0), (1.0, 1.0, 1.0), 1.0, None),
+    ((-0.48, 0.6, -0.64), (0.0, 0.0, 1.0), (1.0, 1.0, 1.0), 1.0, None),
+    ((-0.5, -0.5, -S2 / 2), (0.5, 0.5, -S2 / 2), (1.0, 0.7, 1.3), 0.7, (0.0, 0.0, 0.0)),   # the paper's sphere
+    ((2.0 / 3, -1.0 / 3, 2.0 / 3), (0.0, 1.0, 0.0), (1.0, 0.7, 1.3), 0.7, None),
+    ((0.6, 0.0, -0.8), (0.0, 1.0, 1.0), (1.0, 0.7, 1.3), 0.5, None),
+]
+
+
+@pytest.mark.parametrize("case", range(len(OBLIQUE_CASES)))
+def test_excitation_oblique_wave_closed_form(case):
+    """Voxel average of an obliquely incident Gaussian plane wave (eq:E with a pulse of the
+    eq:GaussPlaneWave form) against the exact box average of tests/pins.py: the retarded time
+    taken at each voxel's lower corner, the three edge projections khat_i L_i as differences of
+    the Gaussian's repeated antiderivatives.  Directions with negative components, one with a
+    zero component and the paper's (-1, -1, -sqrt 2)/2; cubic and 1 x 0.7 x 1.3 voxels;
+    polarisations along no axis.  Every component of every voxel to 1e-12 of the largest."""
+    khat, pseed, hv, r, rref = OBLIQUE_CASES[case]
+    U, V, W = 4, 3, 5
+    pol = _perp(khat, pseed)
+    if rref is None:
+        # the box corner with the smallest r.khat
+        rref = tuple(0.0 if khat[i] >= 0 else (U, V, W)[i] * hv[i] for i in range(3))
+    wave = wl.PlaneWave(khat=khat, pol=pol, width=S2 * 3.0, t0=18.0, amp=1.7, r_ref=rref)
+    worst = 0.0
+    for n in (4, 19, 27, 33, 41):
+        got = mot.incident_average(U, V, W, wave, n, r=r, hv=hv)
+        ref = np.zeros_like(got)
+        for w in range(W):
+            for v in range(V):
+                for u in range(U):
+                    lo = (u * hv[0], v * hv[1], w * hv[2])
+                    tau0 = n * r - wave.t0 - sum((lo[i] - rref[i]) * khat[i] for i in range(3))
+                    c = tuple(khat[i] * hv[i] for i in range(3))
+                    a = wave.amp * pins.box_wave_average(tau0, c, wave.width)
+                    ref[:, w, v, u] = a * np.asarray(pol)
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    assert worst <= 1e-12, worst
+
+
+def test_workload_wave_reference_corner():
+    """The workloads' pulse reaches its reference point first: over the box corners,
+    min (r - r_ref).khat = 0 for every direction, so every voxel sees the pulse peak at or
+    after t0 (the excitation arrives after t = 0, Sec. 2.1)."""
+    U, V, W = 5, 4, 3
+    for k, p in wl.random_directions(12, 7) + [((-0.5, -0.5, -S2 / 2), (0.5, 0.5, -S2 / 2))]:
+        wave = wl.gaussian_wave(U, V, W, k, p, 2.0)
+        corners = [np.array([x, y, z], float) for x in (0, U) for y in (0, V) for z in (0, W)]
+        proj = [np.dot(c - np.asarray(wave.r_ref), k) for c in corners]
+        assert abs(min(proj)) < 1e-12
+
+
 # ----------------------------------------------------------------------------- FIR
 def _paper_taps():
     taps = {}
@@ -823,3 +885,51 @@ def test_prism_one_voxel_static_limit(axis):
     chi = (eps - 1) / eps
     N = pins.newell_tensor_h((0, 0, 0), HV)[axis]
     assert abs(J[-1, axis, 0, 0, 0] - chi / (1 / eps + chi * N)) < 1e-12
+
+
+# ----------------------------------------------------------------------------- restricted march
+def test_restricted_march_matches_full_oracle():
+    """The oracle's dense march on the listed voxels (every voxel with eps_r != 1) gives the
+    full-grid oracle march's currents there, and the full march's currents vanish exactly at
+    every other voxel (chi = 0): dropping the vacuum voxels from the system is exact.  Oblique
+    wave, 3-tap FIR, scatterer voxels far apart and adjacent."""
+    from conftest import oracle_kernel_table
+    U, V, W, n = 6, 5, 4, 60
+    eps = np.ones((W, V, U))
+    vox = np.array([[0, 0, 0], [1, 0, 0], [5, 4, 3], [2, 3, 1], [4, 1, 3]])   # (u, v, w)
+    for i, (u, v, w) in enumerate(vox):
+        eps[w, v, u] = 2.0 + 2.5 * i
+    k = (0.48, -0.6, 0.64)
+    wave = wl.gaussian_wave(U, V, W, k, _perp(k, (1.0, 0.0, 0.0)), 2.0)
+    prob = wl.Problem("restricted", U, V, W, eps, [wave], n, fir=wl.binomial_highpass(3, 0.1))
+    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    J = mot.Oracle(prob, K=K).run(n)
+    Jr = mot.restricted_march(prob, vox, n)
+    got = J[:, :, vox[:, 2], vox[:, 1], vox[:, 0]]
+    assert np.abs(got - Jr).max() <= 1e-12 * np.abs(got).max()
+    mask = np.ones((W, V, U), bool)
+    mask[vox[:, 2], vox[:, 1], vox[:, 0]] = False
+    assert np.all(J[:, :, mask] == 0.0)
+
+
+def test_kernel_values_by_symmetry_match_direct_entries():
+    """kernel_values_by_symmetry, fed canonical entries only, reproduces directly computed
+    entries at offsets with every sign pattern and axis order."""
+    rng = np.random.default_rng(77)
+    offs = [np.array(d) for d in ([3, -1, 2], [-2, 0, 5], [0, 4, -4], [-1, -3, 0], [2, 2, -1])]
+    lags, D = [], []
+    for d in offs:
+        for k in (int(np.linalg.norm(d)), int(np.linalg.norm(d)) + 1):
+            for perm in ([0, 1, 2], [2, 0, 1], [1, 2, 0]):
+                lags.append(k)
+                D.append(d[perm] * rng.choice([-1, 1], 3))
+    D = np.array(D)
+    C = mot.canonical_offsets(D)
+    uniq = sorted(set((k,) + tuple(c) for k, c in zip(lags, C)))
+    vals = mot.kernel_list([u[0] for u in uniq], [u[1:] for u in uniq])
+    canon = np.zeros((max(lags) + 1, 6, 6, 6, 6))
+    for u, v in zip(uniq, vals):
+        canon[u] = v
+    got = mot.kernel_values_by_symmetry(lags, D, canon)
+    ref = mot.kernel_list(lags, D, skip_outside=False)
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
