@@ -160,7 +160,8 @@ def adjoint_ratio(n_steps: int = 800, ckpt: int = 50):
             "steps": n_steps, "ckpt_every": ckpt, "segments": int(st["adjoint_segments"]),
             "forward_s": t_fwd, "gradient_s": t_adj, "gradient_over_forward": t_adj / t_fwd,
             "gradient_forward_pass_ms": st["adjoint_forward_ms"],
-            "gradient_backward_pass_ms": st["adjoint_backward_ms"], "probe_table_s": t_table}
+            "gradient_backward_pass_ms": st["adjoint_backward_ms"], "probe_table_s": t_table,
+            "checkpoint_bytes": int(st["adjoint_checkpoint_bytes"])}
 
 
 def main():

@@ -76,6 +76,15 @@ typedef struct {
                                  The transforms are bit-identical for every choice. < 0: MJ_EINVAL */
     double hy, hz;            /* voxel edges along y and z; 0 selects h.  Zero-initialise a config
                                  written for cubic voxels and these keep it cubic */
+    /* Optional device allocator for every buffer the solver holds or uses for a while (e.g.
+       PyTorch's caching allocator, so that one pool serves the caller and the library):
+       alloc(bytes, alloc_ctx) returns device memory of the current device, aligned to at
+       least 256 bytes, or NULL (the call then fails with MJ_ENOMEM); free_(ptr, alloc_ctx)
+       releases it.  Both or neither (else MJ_EINVAL); NULL selects hipMalloc / hipFree.  The
+       buffers are used on `stream` only, and mj_destroy releases all of them. */
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free_)(void *ptr, void *ctx);
+    void *alloc_ctx;
 } mj_config;
 
 /*
@@ -198,8 +207,11 @@ int mj_set_eps(mj_solver *s, const double *eps_r);
  *   Checkpointing: the forward march is run once, keeping the real-space history needed to
  *   restart it every ckpt_every steps (rounded up to a multiple of the time block; <= 0:
  *   one segment, nothing recomputed); the backward pass recomputes each segment from its
- *   checkpoint before marching back through it.  Memory: (segments - 1) (ell + 1) plus one
- *   segment of 3 M n_rhs values, and a second set of rings for the adjoint march.
+ *   checkpoint before marching back through it.  Memory: every current a restart reads
+ *   (the ell + 1 steps before each segment start) is kept once, so at most
+ *   min(n_steps, (segments - 1)(ell + 1)) currents of 3 M n_rhs values (mj_stats entry 17
+ *   gives the bytes), plus one segment of gradient terms and a second set of rings for the
+ *   adjoint march.
  *   phi: host, nullable.  dphi_deps: device [W][V][U] (overwritten).  probe_hist: device,
  *   nullable, [n_steps][n_rhs][n_probes][3] receives the forward probe field.  Starts at
  *   n = 0 (else MJ_ESTATE) and leaves the march at n = 0.
@@ -254,13 +266,13 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
 
 /*
  * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
- *   in ms per step, and CG statistics.  out (host, n <= 17): [0] forward FFT  [1] history
+ *   in ms per step, and CG statistics.  out (host, n <= 18): [0] forward FFT  [1] history
  *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total
  *   [6] mean CG iterations  [7] max final relative residual  [8] steps timed
  *   [9] max CG iterations  [10] mean duration of one far-part MAC launch (time-blocked,
  *   once per block)  [11] far-part launches  [12] mean duration of one near-part launch
  *   [13] probes.  [5] includes [13].  After mj_adjoint_gradient: [14] forward pass (ms,
- *   whole run)  [15] backward pass with recomputation (ms)  [16] segments.
+ *   whole run)  [15] backward pass with recomputation (ms)  [16] segments  [17] checkpoint bytes.
  */
 int mj_stats(const mj_solver *s, double *out, int32_t n);
 

@@ -68,6 +68,7 @@ struct mj_solver {
     // the rounding noise of the history)
     int guess_deg = 6;
     // device state
+    mj::DevAlloc da;                // hipMalloc, or the caller's allocator (mj_config.alloc)
     size_t bytes = 0;
     std::vector<void *> allocs;
     double *chi = nullptr, *schi = nullptr, *inv_eps = nullptr, *c0 = nullptr;
@@ -104,19 +105,15 @@ struct mj_solver {
     double *Lr = nullptr, *bq = nullptr;
     // statistics of the last run
     double t_gen_ms = 0, t_spec_ms = 0, t_probe_ms = 0;
-    double stat[17] = {};
+    double stat[18] = {};
     Events events;
 
     template <class T>
     T *dalloc(size_t count, const char *what)
     {
-        void *ptr = nullptr;
         size_t b = count * sizeof(T);
         if (b == 0) b = sizeof(T);
-        if (hipMalloc(&ptr, b) != hipSuccess) {
-            (void)hipGetLastError();
-            throw MemError(std::string("device allocation failed: ") + what + " (" + std::to_string(b) + " bytes)");
-        }
+        void *ptr = da.get(b, what);
         allocs.push_back(ptr);
         bytes += b;
         return (T *)ptr;
@@ -126,8 +123,8 @@ struct mj_solver {
     {
         if (st) (void)hipStreamSynchronize(st);
         mj::fft3d_free(fft);
-        if (gen.moments) (void)hipFree(gen.moments);
-        for (void *a : allocs) (void)hipFree(a);
+        da.put(gen.moments);
+        for (void *a : allocs) da.put(a);
         if (cgstat_h) (void)hipHostFree(cgstat_h);
     }
 
@@ -139,7 +136,7 @@ struct mj_solver {
                 allocs.erase(allocs.begin() + (long)i);
                 break;
             }
-        (void)hipFree(ptr);
+        da.put(ptr);
         ptr = nullptr;
     }
 
@@ -198,6 +195,10 @@ void mj_solver::create(const mj_config &c)
     if (c.n_fir > mj::kMaxLocal) throw ArgError("at most 64 FIR taps");
     if (c.n_rhs < 1 || c.n_rhs > 64) throw ArgError("n_rhs must be in [1, 64]");
     if (c.fft_pencils < 0) throw ArgError("fft_pencils must be >= 0 (0: autotune)");
+    if ((c.alloc == nullptr) != (c.free_ == nullptr)) throw ArgError("alloc and free_ are given together or not at all");
+    da.fn_alloc = c.alloc;
+    da.fn_free = c.free_;
+    da.ctx = c.alloc_ctx;
     U = c.U;
     V = c.V;
     W = c.W;
@@ -269,7 +270,7 @@ void mj_solver::create(const mj_config &c)
     cgstat = dalloc<mj::CgStatus>(nrhs, "cg status");
     waves_d = dalloc<mj::WaveArg>(nrhs, "waves");
     MJ_CHECK(hipHostMalloc((void **)&cgstat_h, sizeof(mj::CgStatus) * nrhs, hipHostMallocDefault));
-    mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz);
+    mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz, da);
     bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hp + (size_t)3 * nrhs * W * Ny * Hp);
     if (c.fft_pencils > 0) mj::fft3d_set_pencils(fft, c.fft_pencils);
     else mj::fft3d_autotune(fft, st);
@@ -304,7 +305,7 @@ void mj_solver::build_spectra()
     {
         // generator units: the x edge
         const double hv[3] = {1.0, hy / h, hz / h};
-        mj::gen_moments(gen, U, V, W, c_dt / h, hv, nquad, st);
+        mj::gen_moments(gen, U, V, W, c_dt / h, hv, nquad, da, st);
     }
     bytes += (size_t)M * gen.ms * mj::kMoments * sizeof(double);
     MJ_CHECK(hipStreamSynchronize(st));
@@ -322,19 +323,16 @@ void mj_solver::build_spectra()
                     off[3 * o + 1] = (V > 1 || dy == 0) ? dy : 0;
                     off[3 * o + 2] = (W > 1 || dz == 0) ? dz : 0;
                 }
-        int *lag_d, *off_d;
-        double *out_d;
-        MJ_CHECK(hipMalloc(&lag_d, 27 * sizeof(int)));
-        MJ_CHECK(hipMalloc(&off_d, 81 * sizeof(int)));
-        MJ_CHECK(hipMalloc(&out_d, 162 * sizeof(double)));
+        mj::DevTemp tl(da, 27 * sizeof(int), "stencil request");
+        mj::DevTemp to(da, 81 * sizeof(int), "stencil request");
+        mj::DevTemp tv(da, 162 * sizeof(double), "stencil values");
+        int *lag_d = tl.as<int>(), *off_d = to.as<int>();
+        double *out_d = tv.as<double>();
         MJ_CHECK(hipMemcpy(lag_d, lag.data(), 27 * sizeof(int), hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(off_d, off.data(), 81 * sizeof(int), hipMemcpyHostToDevice));
         mj::gen_kernel_values(gen, 27, lag_d, off_d, out_d, st);
         MJ_CHECK(hipMemcpyAsync(K0_27, out_d, 162 * sizeof(double), hipMemcpyDeviceToHost, st));
         MJ_CHECK(hipStreamSynchronize(st));
-        (void)hipFree(lag_d);
-        (void)hipFree(off_d);
-        (void)hipFree(out_d);
         // offsets that fall outside a one-voxel-thick axis do not couple
         o = 0;
         for (int dz = -1; dz <= 1; dz++)
@@ -353,9 +351,9 @@ void mj_solver::build_spectra()
     double2 *X = nullptr;
     const size_t ng = (size_t)Nx * Ny * Nz;
     try {
-        mj::fft3d_init(kf, Nx, Ny, Nz, 6, Nx, Ny, Nz);
-        if (hipMalloc(&grid, 6 * ng * sizeof(double)) != hipSuccess) throw MemError("kernel grid");
-        if (hipMalloc(&X, 6 * (size_t)Nz * Ny * Hp * sizeof(double2)) != hipSuccess) throw MemError("kernel spectrum");
+        mj::fft3d_init(kf, Nx, Ny, Nz, 6, Nx, Ny, Nz, da);
+        grid = (double *)da.get(6 * ng * sizeof(double), "kernel grid");
+        X = (double2 *)da.get(6 * (size_t)Nz * Ny * Hp * sizeof(double2), "kernel spectrum");
         const double scale = 1.0 / ((double)Nx * Ny * Nz);
         for (int k = 1; k <= ell; k++) {
             mj::gen_kernel_grid(gen, k, Nx, Ny, Nz, grid, st);
@@ -367,13 +365,13 @@ void mj_solver::build_spectra()
         MJ_CHECK(hipStreamSynchronize(st));
     } catch (...) {
         mj::fft3d_free(kf);
-        if (grid) (void)hipFree(grid);
-        if (X) (void)hipFree(X);
+        da.put(grid);
+        da.put(X);
         throw;
     }
     mj::fft3d_free(kf);
-    (void)hipFree(grid);
-    (void)hipFree(X);
+    da.put(grid);
+    da.put(X);
     auto t2 = std::chrono::steady_clock::now();
     t_spec_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
 }
@@ -931,10 +929,10 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
     int *d_p = nullptr, *d_v = nullptr, *d_k = nullptr;
     double *d_o = nullptr;
     try {
-        MJ_CHECK(hipMalloc(&d_p, sizeof(int) * cnt));
-        MJ_CHECK(hipMalloc(&d_v, sizeof(int) * cnt));
-        MJ_CHECK(hipMalloc(&d_k, sizeof(int) * cnt));
-        MJ_CHECK(hipMalloc(&d_o, sizeof(double) * 6 * cnt));
+        d_p = (int *)da.get(sizeof(int) * cnt, "probe request");
+        d_v = (int *)da.get(sizeof(int) * cnt, "probe request");
+        d_k = (int *)da.get(sizeof(int) * cnt, "probe request");
+        d_o = (double *)da.get(sizeof(double) * 6 * cnt, "probe values");
         MJ_CHECK(hipMemcpy(d_p, pp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(d_v, pv.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(d_k, pk.data(), sizeof(int) * cnt, hipMemcpyHostToDevice));
@@ -942,16 +940,16 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
         MJ_CHECK(hipStreamSynchronize(st));
         MJ_CHECK(hipMemcpy(out, d_o, sizeof(double) * 6 * cnt, hipMemcpyDeviceToHost));
     } catch (...) {
-        (void)hipFree(d_p);
-        (void)hipFree(d_v);
-        (void)hipFree(d_k);
-        (void)hipFree(d_o);
+        da.put(d_p);
+        da.put(d_v);
+        da.put(d_k);
+        da.put(d_o);
         throw;
     }
-    (void)hipFree(d_p);
-    (void)hipFree(d_v);
-    (void)hipFree(d_k);
-    (void)hipFree(d_o);
+    da.put(d_p);
+    da.put(d_v);
+    da.put(d_k);
+    da.put(d_o);
 }
 
 // March state: a fixed header, then the spectral ring, the time block's far sums and the
@@ -1055,21 +1053,30 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
     int maxseg = 0;
     for (int c = 0; c < C; c++) maxseg = std::max(maxseg, seg_end(c) - starts[c] + 1);
     const size_t vec = (size_t)nrhs * 3 * M;
-    const size_t win = (size_t)ell + 1;
+    // every step j that a restart reads (j = s0 - 1 - ell .. s0 - 1 for a segment start s0 > 1)
+    // is kept once, in one pool indexed through pool_of[j], however the windows overlap
+    std::vector<long> pool_of((size_t)N + 1, -1);
+    long npool = 0;
+    for (int c = 1; c < C; c++)
+        for (int j = std::max(1, starts[c] - 1 - ell); j <= starts[c] - 1; j++)
+            if (pool_of[(size_t)j] < 0) pool_of[(size_t)j] = 1;
+    for (int j = 1; j <= N; j++)
+        if (pool_of[(size_t)j] > 0) pool_of[(size_t)j] = npool++;
     const long sp = spec_plane();
     std::vector<void *> tmp;
     auto talloc = [&](size_t bytes, const char *what) {
         void *ptr = nullptr;
-        if (hipMalloc(&ptr, std::max<size_t>(bytes, 8)) != hipSuccess) {
-            (void)hipGetLastError();
-            for (void *q : tmp) (void)hipFree(q);
-            throw MemError(std::string("device allocation failed: ") + what);
+        try {
+            ptr = da.get(std::max<size_t>(bytes, 8), what);
+        } catch (...) {
+            for (void *q : tmp) da.put(q);
+            throw;
         }
         tmp.push_back(ptr);
         return ptr;
     };
     double *Ehist = (double *)talloc(sizeof(double) * (size_t)N * nrhs * np * 3, "probe history");
-    double *ckpt = (double *)talloc(sizeof(double) * (size_t)std::max(C - 1, 1) * win * vec, "checkpoints");
+    double *ckpt = (double *)talloc(sizeof(double) * (size_t)std::max<long>(npool, 1) * vec, "checkpoints");
     double *Bbuf = (double *)talloc(sizeof(double) * (size_t)maxseg * vec, "gradient terms");
     double *G = (double *)talloc(sizeof(double) * vec, "adjoint source");
     double *bqb = (double *)talloc(sizeof(double) * vec, "adjoint rhs");
@@ -1091,7 +1098,6 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
     try {
         // 1. forward
         const int last0 = starts[C - 1];
-        int next_ck = 1;
         for (int t = 1; t <= N; t++) {
             StepIO io;
             io.Pout = Ehist + (size_t)(t - 1) * nrhs * np * 3;
@@ -1099,14 +1105,9 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             step(io);
             check_growth();
             check_cg();
-            if (next_ck < C && t + 1 == starts[next_ck]) {
-                // J_j for j = t - ell .. t (those with j >= 1) from the real-space ring
-                for (int j = std::max(1, t - ell); j <= t; j++)
-                    MJ_CHECK(hipMemcpyAsync(ckpt + ((size_t)(next_ck - 1) * win + (size_t)(j - (t - ell))) * vec,
-                                            Jr + (size_t)slotR(j) * vec, sizeof(double) * vec,
-                                            hipMemcpyDeviceToDevice, st));
-                next_ck++;
-            }
+            if (pool_of[(size_t)t] >= 0)
+                MJ_CHECK(hipMemcpyAsync(ckpt + (size_t)pool_of[(size_t)t] * vec, Jr + (size_t)slotR(t) * vec,
+                                        sizeof(double) * vec, hipMemcpyDeviceToDevice, st));
         }
         if (probe_hist)
             MJ_CHECK(hipMemcpyAsync(probe_hist, Ehist, sizeof(double) * (size_t)N * nrhs * np * 3,
@@ -1128,7 +1129,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
                 if (c > 0) {
                     const int j0 = s0 - 1 - ell;   // first stored step
                     for (int j = std::max(1, j0); j <= s0 - 1; j++) {
-                        const double *src = ckpt + ((size_t)(c - 1) * win + (size_t)(j - j0)) * vec;
+                        const double *src = ckpt + (size_t)pool_of[(size_t)j] * vec;
                         MJ_CHECK(hipMemcpyAsync(Jr + (size_t)slotR(j) * vec, src, sizeof(double) * vec,
                                                 hipMemcpyDeviceToDevice, st));
                         if (j <= s0 - 2)
@@ -1181,7 +1182,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
         Jr = Jr_f;
         Lr = nullptr;
         bq = nullptr;
-        for (void *q : tmp) (void)hipFree(q);
+        for (void *q : tmp) da.put(q);
         for (auto &tv : tev) (void)hipEventDestroy(tv);
         n = 0;
         throw;
@@ -1192,7 +1193,8 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
     stat[14] = f_ms;
     stat[15] = b_ms;
     stat[16] = C;
-    for (void *q : tmp) (void)hipFree(q);
+    stat[17] = (double)npool * vec * sizeof(double);
+    for (void *q : tmp) da.put(q);
     for (auto &tv : tev) (void)hipEventDestroy(tv);
     n = 0;
     if (noconv) throw std::range_error("Z_0 solve did not converge");
@@ -1401,26 +1403,23 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
                 throw ArgError("offset out of range");
         }
         if (n == 0) return;
-        int *lag_d = nullptr, *off_d = nullptr;
-        double *out_d = nullptr;
-        MJ_CHECK(hipMalloc(&lag_d, sizeof(int) * n));
-        MJ_CHECK(hipMalloc(&off_d, sizeof(int) * 3 * n));
-        MJ_CHECK(hipMalloc(&out_d, sizeof(double) * 6 * n));
+        mj::DevTemp tl(s->da, sizeof(int) * n, "kernel value request");
+        mj::DevTemp to(s->da, sizeof(int) * 3 * n, "kernel value request");
+        mj::DevTemp tv(s->da, sizeof(double) * 6 * n, "kernel values");
+        int *lag_d = tl.as<int>(), *off_d = to.as<int>();
+        double *out_d = tv.as<double>();
         MJ_CHECK(hipMemcpy(lag_d, lag, sizeof(int) * n, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(off_d, offset, sizeof(int) * 3 * n, hipMemcpyHostToDevice));
         mj::gen_kernel_values(s->gen, n, lag_d, off_d, out_d, s->st);
         MJ_CHECK(hipMemcpyAsync(out, out_d, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, s->st));
         MJ_CHECK(hipStreamSynchronize(s->st));
-        (void)hipFree(lag_d);
-        (void)hipFree(off_d);
-        (void)hipFree(out_d);
     });
 }
 
 int mj_stats(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    for (int i = 0; i < n && i < 17; i++) out[i] = s->stat[i];
+    for (int i = 0; i < n && i < 18; i++) out[i] = s->stat[i];
     return MJ_OK;
 }
 

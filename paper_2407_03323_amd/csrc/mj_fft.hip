@@ -399,7 +399,7 @@ int fft_pick_size(int nmin)
     throw ArgError("grid too large for the FFT (padded size above " + std::to_string(kMaxFftN) + ")");
 }
 
-void fft_plan_init(FftPlan1D &p, int N)
+void fft_plan_init(FftPlan1D &p, int N, const DevAlloc &da)
 {
     std::vector<int> f;
     if (!fft_size_ok(N) || !factor(N, f)) throw ArgError("unsupported FFT size " + std::to_string(N));
@@ -412,7 +412,7 @@ void fft_plan_init(FftPlan1D &p, int N)
         long double ang = -2.0L * pi * (long double)m / (long double)N;
         h[m] = make_double2((double)cosl(ang), (double)sinl(ang));
     }
-    MJ_CHECK(hipMalloc(&p.tw, sizeof(double2) * N));
+    p.tw = (double2 *)da.get(sizeof(double2) * N, "FFT twiddles");
     MJ_CHECK(hipMemcpy(p.tw, h.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
     // the odd-radix constants, rounded the same way (cheap; repeated for every plan so that
     // the device current at plan creation has them)
@@ -426,35 +426,36 @@ void fft_plan_init(FftPlan1D &p, int N)
     MJ_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_odd_cs), cs, sizeof(cs)));
 }
 
-void fft_plan_free(FftPlan1D &p)
+void fft_plan_free(FftPlan1D &p, const DevAlloc &da)
 {
-    if (p.tw) (void)hipFree(p.tw);
+    da.put(p.tw);
     p.tw = nullptr;
 }
 
-void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz)
+void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz, const DevAlloc &da)
 {
+    f.da = da;
     f.U = U; f.V = V; f.W = W;
     f.Nx = Nx; f.Ny = Ny; f.Nz = Nz;
     f.Hx = Nx / 2 + 1;
     f.Hp = spectrum_pitch(f.Hx);
     f.ncomp = ncomp;
-    fft_plan_init(f.px, Nx);
-    fft_plan_init(f.py, Ny);
-    fft_plan_init(f.pz, Nz);
+    fft_plan_init(f.px, Nx, da);
+    fft_plan_init(f.py, Ny, da);
+    fft_plan_init(f.pz, Nz, da);
     fft3d_set_pencils(f, 1 << 30);
     size_t na = (size_t)ncomp * W * V * f.Hp, nb = (size_t)ncomp * W * Ny * f.Hp;
-    if (hipMalloc(&f.bufA, sizeof(double2) * na) != hipSuccess) throw MemError("FFT scratch A");
-    if (hipMalloc(&f.bufB, sizeof(double2) * nb) != hipSuccess) throw MemError("FFT scratch B");
+    f.bufA = (double2 *)da.get(sizeof(double2) * na, "FFT scratch A");
+    f.bufB = (double2 *)da.get(sizeof(double2) * nb, "FFT scratch B");
 }
 
 void fft3d_free(Fft3D &f)
 {
-    fft_plan_free(f.px);
-    fft_plan_free(f.py);
-    fft_plan_free(f.pz);
-    if (f.bufA) (void)hipFree(f.bufA);
-    if (f.bufB) (void)hipFree(f.bufB);
+    fft_plan_free(f.px, f.da);
+    fft_plan_free(f.py, f.da);
+    fft_plan_free(f.pz, f.da);
+    f.da.put(f.bufA);
+    f.da.put(f.bufB);
     f.bufA = f.bufB = nullptr;
 }
 
@@ -592,11 +593,7 @@ void fft3d_set_pencils(Fft3D &f, int cap)
 void fft3d_autotune(Fft3D &f, hipStream_t st)
 {
     const size_t nX = (size_t)f.ncomp * f.Nz * f.Ny * f.Hp;
-    double2 *X = nullptr;
-    if (hipMalloc(&X, sizeof(double2) * nX) != hipSuccess) {
-        (void)hipGetLastError();
-        throw MemError("FFT autotune scratch");
-    }
+    double2 *X = (double2 *)f.da.get(sizeof(double2) * nX, "FFT autotune scratch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     try {
         const size_t na = (size_t)f.ncomp * f.W * f.V * f.Hp, nb = (size_t)f.ncomp * f.W * f.Ny * f.Hp;
@@ -651,12 +648,12 @@ void fft3d_autotune(Fft3D &f, hipStream_t st)
         (void)hipStreamSynchronize(st);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        (void)hipFree(X);
+        f.da.put(X);
         throw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(X);
+    f.da.put(X);
 }
 
 }  // namespace mj

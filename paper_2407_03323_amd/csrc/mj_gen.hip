@@ -589,7 +589,8 @@ static void check_geometry(double r, const double hv[3])
     if (shells_per_offset(r, hv) > kShellCap) throw ArgError("too many kernel shells per voxel pair");
 }
 
-void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3], int nquad, hipStream_t st)
+void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3], int nquad, const DevAlloc &da,
+                 hipStream_t st)
 {
     if (nquad < 4 || nquad > kMaxQ) throw ArgError("quad_order must be in [4, 24]");
     check_geometry(r, hv);
@@ -614,7 +615,7 @@ void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3]
     g.r = r;
     size_t noff = (size_t)U * V * W;
     size_t bytes = noff * g.ms * kMoments * sizeof(double);
-    if (hipMalloc(&g.moments, bytes) != hipSuccess) throw MemError("kernel moments");
+    g.moments = (double *)da.get(bytes, "kernel moments");
     MJ_CHECK(hipMemsetAsync(g.moments, 0, bytes, st));
     if (hv[1] != 1.0 || hv[2] != 1.0)
         hipLaunchKernelGGL(k_gen_moments<true>, dim3((unsigned)noff), dim3(kGenThreads), 0, st, g.moments, ga);

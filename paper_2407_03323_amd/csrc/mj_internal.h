@@ -30,6 +30,48 @@ struct MemError : std::runtime_error {
     using std::runtime_error::runtime_error;
 };
 
+// ---------------------------------------------------------------------------- device memory
+// Every device buffer of a solver comes from here: hipMalloc/hipFree, or the caller's allocator
+// (mj_config.alloc / free_, e.g. PyTorch's caching allocator) when one is given.
+struct DevAlloc {
+    void *(*fn_alloc)(size_t, void *) = nullptr;
+    void (*fn_free)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+
+    void *get(size_t bytes, const char *what) const
+    {
+        if (bytes == 0) bytes = 8;
+        void *p = nullptr;
+        if (fn_alloc) {
+            p = fn_alloc(bytes, ctx);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        if (!p)
+            throw MemError(std::string("device allocation failed: ") + what + " (" + std::to_string(bytes) + " bytes)");
+        return p;
+    }
+    void put(void *p) const
+    {
+        if (!p) return;
+        if (fn_free) fn_free(p, ctx);
+        else (void)hipFree(p);
+    }
+};
+
+// A temporary device buffer released when it goes out of scope (also on an exception).
+struct DevTemp {
+    const DevAlloc &da;
+    void *p;
+    DevTemp(const DevAlloc &a, size_t bytes, const char *what) : da(a), p(a.get(bytes, what)) {}
+    ~DevTemp() { da.put(p); }
+    DevTemp(const DevTemp &) = delete;
+    DevTemp &operator=(const DevTemp &) = delete;
+    template <class T>
+    T *as() const { return (T *)p; }
+};
+
 // ---------------------------------------------------------------------------- complex
 __host__ __device__ inline double2 cmul(double2 a, double2 b)
 {
@@ -64,8 +106,8 @@ struct FftPlan1D {
 };
 
 // Builds the radix plan and uploads the correctly rounded twiddle table.
-void fft_plan_init(FftPlan1D &p, int N);
-void fft_plan_free(FftPlan1D &p);
+void fft_plan_init(FftPlan1D &p, int N, const DevAlloc &da);
+void fft_plan_free(FftPlan1D &p, const DevAlloc &da);
 bool fft_size_ok(int N);
 int fft_pick_size(int nmin);  // smallest even N >= nmin whose factors are all supported radices
 
@@ -83,9 +125,10 @@ struct Fft3D {
     double2 *bufA = nullptr, *bufB = nullptr;
     int ncomp = 0;
     int Px = 1, Py = 1, Pz = 1;  // pencils per block of the x, y and z passes
+    DevAlloc da;                 // where the twiddles and scratch came from
 };
 
-void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz);
+void fft3d_init(Fft3D &f, int U, int V, int W, int ncomp, int Nx, int Ny, int Nz, const DevAlloc &da);
 void fft3d_free(Fft3D &f);
 // pencils per block of every pass: at most cap, and at most what one tile holds
 void fft3d_set_pencils(Fft3D &f, int cap);
@@ -112,7 +155,8 @@ struct GenResult {
 };
 
 // r = c dt and hv = voxel edges, both in units of the x edge (hv[0] = 1)
-void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3], int nquad, hipStream_t st);
+void gen_moments(GenResult &g, int U, int V, int W, double r, const double hv[3], int nquad, const DevAlloc &da,
+                 hipStream_t st);
 // K_k on the full periodic grid [6][Nz][Ny][Nx] (real), from the octant moments
 void gen_kernel_grid(const GenResult &g, int k, int Nx, int Ny, int Nz, double *grid, hipStream_t st);
 // K_k(D) for a list of (k, D): out[n][6]

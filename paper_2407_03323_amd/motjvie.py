@@ -26,6 +26,11 @@ class MotJvieError(RuntimeError):
         self.code = code
 
 
+# device allocator callbacks of mj_config (alloc(bytes, ctx) -> ptr, free_(ptr, ctx))
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class mj_config(ctypes.Structure):
     _fields_ = [
         ("U", ctypes.c_int32), ("V", ctypes.c_int32), ("W", ctypes.c_int32),
@@ -39,6 +44,7 @@ class mj_config(ctypes.Structure):
         ("quad_order", ctypes.c_int32),
         ("fft_pencils", ctypes.c_int32),
         ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+        ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
     ]
 
 
@@ -104,11 +110,37 @@ def _current_stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def torch_allocator(stream=None):
+    """alloc / free_ callbacks that take the library's device memory from PyTorch's caching
+    allocator on `stream` (a raw stream handle; default torch's current stream).  The returned
+    pair must stay referenced for as long as the solver lives."""
+    import torch
+    dev = torch.cuda.current_device()
+    handle = int(stream.value if isinstance(stream, ctypes.c_void_p) else
+                 (stream if stream is not None else torch.cuda.current_stream().cuda_stream))
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, handle)
+        except Exception:
+            return None   # NULL: the library reports MJ_ENOMEM
+
+    def _free(ptr, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
 class Solver:
     """One MOT-JVIE march on the device (see include/motjvie.h for the exact semantics)."""
 
     def __init__(self, U, V, W, eps, fir=None, h=1.0, c_dt=None, n_rhs=1, cg_rtol=0.0, cg_maxit=0,
-                 time_block=0, quad_order=0, stream=None, fft_pencils=0, hy=0.0, hz=0.0):
+                 time_block=0, quad_order=0, stream=None, fft_pencils=0, hy=0.0, hz=0.0, allocator=None):
+        """allocator: None (the library's hipMalloc) or "torch" (PyTorch's caching allocator,
+        through mj_config.alloc / free_)."""
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(W, V, U))
@@ -130,6 +162,12 @@ class Solver:
         cfg.quad_order = int(quad_order)
         cfg.fft_pencils = int(fft_pencils)
         cfg.hy, cfg.hz = float(hy), float(hz)
+        self._alloc_fns = None
+        if allocator == "torch":
+            self._alloc_fns = torch_allocator(cfg.stream)
+            cfg.alloc, cfg.free_ = self._alloc_fns
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
         self._keep = (eps, fir)
         rc = self._lib.mj_create(ctypes.byref(cfg), ctypes.byref(self._h))
         if rc != MJ_OK:
@@ -266,11 +304,12 @@ class Solver:
         return phi.value
 
     def stats(self) -> dict:
-        out = np.zeros(17)
-        self._check(self._lib.mj_stats(self._h, _dptr(out), 17))
+        out = np.zeros(18)
+        self._check(self._lib.mj_stats(self._h, _dptr(out), 18))
         keys = ["fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms", "z0_ms", "step_ms", "cg_iters",
                 "cg_res_max", "steps", "cg_iters_max", "far_launch_ms", "far_launches", "near_launch_ms",
-                "probe_ms", "adjoint_forward_ms", "adjoint_backward_ms", "adjoint_segments"]
+                "probe_ms", "adjoint_forward_ms", "adjoint_backward_ms", "adjoint_segments",
+                "adjoint_checkpoint_bytes"]
         return dict(zip(keys, out.tolist()))
 
     def fft_roundtrip(self, x, X=None, y=None):

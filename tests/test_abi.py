@@ -65,6 +65,11 @@ def test_binding_config_matches_header():
         decl = " ".join(decl.split())
         if not decl:
             continue
+        fp = re.match(r"(void \*|void) ?\(\*(\w+)\)\((.*)\)", decl)
+        if fp:
+            # function pointer: the ctypes field must be a CFUNCTYPE
+            fields.append((fp.group(2), "fn"))
+            continue
         m = re.match(r"(const )?(int32_t|double|void) (\*?)(.+)", decl)
         assert m, decl
         ctype = m.group(2) + ("*" if m.group(3) else "")
@@ -74,14 +79,16 @@ def test_binding_config_matches_header():
     want = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
     assert [f[0] for f in fields] == [f[0] for f in mj_config._fields_]
     for (name, ctype), (_, ct) in zip(fields, mj_config._fields_):
-        if ctype.endswith("*"):
+        if ctype == "fn":
+            assert issubclass(ct, ctypes._CFuncPtr), name
+        elif ctype.endswith("*"):
             assert ct is ctypes.c_void_p or issubclass(ct, ctypes._Pointer), name
         else:
             assert ct is want[ctype], name
 
 
 @pytest.mark.parametrize("case", ["grid", "cdt", "cdt_small", "edge_short", "edge_long", "eps", "rhs", "pencils",
-                                  "null"])
+                                  "alloc_only", "null"])
 def test_create_rejects_invalid_arguments(lib, case):
     from paper_2407_03323_amd.motjvie import MJ_EINVAL
     h = ctypes.c_void_p()
@@ -105,6 +112,12 @@ def test_create_rejects_invalid_arguments(lib, case):
     elif case == "pencils":
         c, keep = _cfg()
         c.fft_pencils = -1
+    elif case == "alloc_only":
+        from paper_2407_03323_amd.motjvie import ALLOC_FN
+        c, keep = _cfg()
+        fn = ALLOC_FN(lambda nbytes, ctx: None)     # an allocator without its free_
+        c.alloc = fn
+        keep = (keep, fn)
     else:
         c, keep = _cfg(n_rhs=0)
     assert lib.mj_create(ctypes.byref(c), ctypes.byref(h)) == MJ_EINVAL

@@ -550,9 +550,13 @@ def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt):
     st = s.stats()
     e_phi = abs(phi - phi_ref) / abs(phi_ref)
     e_g = _rel(grad, grad_ref)
-    say("  phi rel", e_phi, "grad rel L2", e_g, "segments", st["adjoint_segments"])
+    say("  phi rel", e_phi, "grad rel L2", e_g, "segments", st["adjoint_segments"], "checkpoint bytes",
+        st["adjoint_checkpoint_bytes"])
     assert e_phi <= 1e-10
     assert e_g <= 1e-8
+    # each current a restart reads is stored once, however the segments' windows overlap
+    ell, segs = s.ell, int(st["adjoint_segments"])
+    assert st["adjoint_checkpoint_bytes"] <= min(prob.n_steps, (segs - 1) * (ell + 1)) * 3 * prob.M * 8
     s.close()
 
 
@@ -632,7 +636,12 @@ def test_adjoint_gradient_finite_differences_C4(torch_cuda):
     of eps_r ~ U[1, 12] (seed 4), 32 probes on a sphere of radius 48 h, 800 steps, the 17-tap
     FIR, checkpoints every 50 steps.  dPhi/deps_r from the transposed march against central
     differences (delta = 1e-6) of Phi from forward marches, at 20 design voxels with
-    eps_r >= 1.01 drawn with seed 44."""
+    eps_r >= 1.01 drawn with seed 44.
+
+    At delta = 1e-6 the differences resolve Phi(eps +- delta) only to its last few bits: one
+    unit in the last place of Phi (1.4e-14 at Phi ~ 81) moves the difference quotient by
+    7e-9, about 1e-5 of the largest gradient entry.  The bar is 16 such units, plus 1e-6 of
+    the entry itself."""
     torch = torch_cuda
     prob = wl.config("C4")
     n = prob.n_steps
@@ -648,6 +657,7 @@ def test_adjoint_gradient_finite_differences_C4(torch_cuda):
     pick = design[rng.choice(len(design), 20, replace=False)]
     Pt = torch.zeros((n, 1, len(prob.probes), 3), dtype=torch.float64, device="cuda")
     gmax = np.abs(grad).max()
+    ulp = np.spacing(phi0)
     worst = 0.0
     for (w, v, u) in pick:
         vals = []
@@ -660,11 +670,12 @@ def test_adjoint_gradient_finite_differences_C4(torch_cuda):
             torch.cuda.synchronize()
             vals.append(float((Pt.cpu().numpy() ** 2).sum()))
         fd = (vals[0] - vals[1]) / 2e-6
-        err = abs(fd - grad[w, v, u]) / gmax
-        say("  voxel %s eps %.3f fd %.9e adjoint %.9e err/max %.2e" % ((u, v, w), prob.eps[w, v, u], fd,
-                                                                      grad[w, v, u], err))
+        bar = 16 * ulp / 2e-6 + 1e-6 * abs(grad[w, v, u])
+        err = abs(fd - grad[w, v, u]) / bar
+        say("  voxel %s eps %.3f fd %.9e adjoint %.9e |diff|/max %.2e |diff|/bar %.2f" % (
+            (int(u), int(v), int(w)), prob.eps[w, v, u], fd, grad[w, v, u], abs(fd - grad[w, v, u]) / gmax, err))
         worst = max(worst, err)
-    assert worst <= 1e-5
+    assert worst <= 1.0
     s.close()
 
 
@@ -748,6 +759,45 @@ def test_full_size_104_sampled(torch_cuda):
     say("  kernels worst", worst)
     assert worst <= 3e-12
     s.close()
+
+
+def test_torch_allocator_serves_the_solver(torch_cuda):
+    """With mj_config.alloc / free_ wired to PyTorch's caching allocator, every device buffer of
+    the solver comes from torch's pool (torch.cuda.memory_allocated grows by the bytes mj_info
+    reports and returns when the solver is destroyed), and the march, the probes and the
+    gradient are bit-identical to those of the library's own allocations."""
+    torch = torch_cuda
+    prob = _small_problem(40)
+    n = prob.n_steps
+    probes = np.array([[2.0, 1.5, 6.0], [-3.0, 1.0, 1.5]])
+    out = {}
+    for alloc in (None, "torch"):
+        J = torch.zeros((n, 1, 3, prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+        P = torch.zeros((n, 1, 2, 3), dtype=torch.float64, device="cuda")
+        g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        before = torch.cuda.memory_allocated()
+        s = make_solver(prob, time_block=8, allocator=alloc)
+        s.set_probes(probes)
+        torch.cuda.synchronize()
+        grown = torch.cuda.memory_allocated() - before
+        s.run(n, J, P)
+        s.reset()
+        phi = s.adjoint_gradient(n, g, 16)
+        held = s.info()["device_bytes"]
+        s.close()
+        torch.cuda.synchronize()
+        after = torch.cuda.memory_allocated() - before
+        say("  allocator %s: torch pool grew %d B at create (library reports %d B), %d B left after destroy" % (
+            alloc, grown, held, after))
+        if alloc == "torch":
+            assert grown >= held
+            assert after == 0
+        else:
+            assert grown == 0
+        out[alloc] = (J, P, g, phi)
+    a, b = out[None], out["torch"]
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]) and a[3] == b[3]
 
 
 def _golden_script(name):
