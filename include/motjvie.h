@@ -265,6 +265,18 @@ int mj_history_sum(mj_solver *s, const double *J_hist, int32_t depth, double *P)
 int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t *offset, double *out);
 
 /*
+ * mj_kernel_values_noalloc -- mj_kernel_values for callers that cannot allocate device memory
+ *   (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ *   same arguments and results, with the requests and results staged through a fixed device
+ *   array built into the library (4 MiB, one per GPU, held until the process ends) instead
+ *   of buffers allocated per call.  At most 65536 requests per call (else MJ_EINVAL); the
+ *   solver's device must be current (else MJ_EINVAL).  The call allocates nothing.  All calls
+ *   on one GPU share the array: calls from one process take turns (each synchronises its
+ *   stream before it returns); calls that overlap on one GPU from outside that order race.
+ */
+int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const int32_t *offset, double *out);
+
+/*
  * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
  *   in ms per step, and CG statistics.  out (host, n <= 18): [0] forward FFT  [1] history
  *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total

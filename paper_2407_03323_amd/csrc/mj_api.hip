@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,36 @@ using mj::UnstableError;
 namespace {
 
 thread_local std::string g_err;
+
+// ---------------------------------------------------------------------------- static staging
+// mj_kernel_values_noalloc stages its requests and results through this file-scope array
+// instead of allocating: kNoAllocMax requests, laid out as results [max][6] doubles, then
+// lags [max] and offsets [max][3] as int32.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the name `scratch` is only a stand-in: the array's
+// device address is looked up per device with hipGetSymbolAddress (with that device
+// current) and kept in g_scratch; host code passes that address, never the name.
+constexpr int kNoAllocMax = 65536;
+constexpr size_t kNoAllocBytes = (size_t)kNoAllocMax * (6 * sizeof(double) + 4 * sizeof(int32_t));
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;                 // guards g_scratch
+std::vector<unsigned char *> g_scratch;  // device address of `scratch` per device id (null: not looked up)
+std::mutex g_noalloc_mu;                 // calls of one process take turns on the staging array
+
+// Address of this device's copy of `scratch`; dev must be the current device.
+unsigned char *scratch_ptr(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch[(size_t)dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw HipError(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[(size_t)dev] = (unsigned char *)ptr;
+    }
+    return g_scratch[(size_t)dev];
+}
 
 __global__ void k_extract_octant(const double2 *__restrict__ X, int Hx, int Hp, int Ny, int Nz, double scale,
                                  double *__restrict__ out)
@@ -90,6 +121,7 @@ struct mj_solver {
     double K0_27[27 * 6] = {};
     int nblk = 1;
     int n = 0;
+    int dev = 0;                    // device current at mj_create
     std::string err;
     // probes: scattered field at test voxels centred at arbitrary points
     std::vector<double> eps_h;
@@ -234,6 +266,8 @@ void mj_solver::create(const mj_config &c)
     nloc = std::max(guess_deg + 1, (int)fir.size() - 1);   // the initial guess uses guess_deg + 1 steps
     rdepth = nloc + 1;
 
+    MJ_CHECK(hipGetDevice(&dev));
+    (void)scratch_ptr(dev);   // this device's staging array (mj_kernel_values_noalloc)
     chi = dalloc<double>(M, "chi");
     schi = dalloc<double>(M, "sqrt chi");
     inv_eps = dalloc<double>(M, "1/eps");
@@ -1410,6 +1444,36 @@ int mj_kernel_values(mj_solver *s, int32_t n, const int32_t *lag, const int32_t 
         double *out_d = tv.as<double>();
         MJ_CHECK(hipMemcpy(lag_d, lag, sizeof(int) * n, hipMemcpyHostToDevice));
         MJ_CHECK(hipMemcpy(off_d, offset, sizeof(int) * 3 * n, hipMemcpyHostToDevice));
+        mj::gen_kernel_values(s->gen, n, lag_d, off_d, out_d, s->st);
+        MJ_CHECK(hipMemcpyAsync(out, out_d, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, s->st));
+        MJ_CHECK(hipStreamSynchronize(s->st));
+    });
+}
+
+int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const int32_t *offset, double *out)
+{
+    if (!s) return MJ_EINVAL;
+    if (n < 0 || (n > 0 && (!lag || !offset || !out))) return fail(s, MJ_EINVAL, "bad kernel value request");
+    if (n > kNoAllocMax)
+        return fail(s, MJ_EINVAL, "at most " + std::to_string(kNoAllocMax) + " requests per call (staging array size)");
+    return guarded(s, [&] {
+        for (int i = 0; i < n; i++) {
+            if (lag[i] < 0 || lag[i] > s->ell) throw ArgError("lag out of range");
+            if (std::abs(offset[3 * i]) >= s->U || std::abs(offset[3 * i + 1]) >= s->V ||
+                std::abs(offset[3 * i + 2]) >= s->W)
+                throw ArgError("offset out of range");
+        }
+        if (n == 0) return;
+        int cur = -1;
+        MJ_CHECK(hipGetDevice(&cur));
+        if (cur != s->dev) throw ArgError("call with the solver's device current");
+        unsigned char *base = scratch_ptr(cur);
+        double *out_d = (double *)base;
+        int32_t *lag_d = (int32_t *)(base + (size_t)kNoAllocMax * 6 * sizeof(double));
+        int32_t *off_d = lag_d + kNoAllocMax;
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        MJ_CHECK(hipMemcpyAsync(lag_d, lag, sizeof(int32_t) * n, hipMemcpyHostToDevice, s->st));
+        MJ_CHECK(hipMemcpyAsync(off_d, offset, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, s->st));
         mj::gen_kernel_values(s->gen, n, lag_d, off_d, out_d, s->st);
         MJ_CHECK(hipMemcpyAsync(out, out_d, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, s->st));
         MJ_CHECK(hipStreamSynchronize(s->st));

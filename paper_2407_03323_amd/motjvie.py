@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH):
     L.mj_reset.argtypes = [vp]
     L.mj_history_sum.argtypes = [vp, vp, ctypes.c_int32, vp]
     L.mj_kernel_values.argtypes = [vp, ctypes.c_int32, ip, ip, dp]
+    L.mj_kernel_values_noalloc.argtypes = [vp, ctypes.c_int32, ip, ip, dp]
     L.mj_stats.argtypes = [vp, dp, ctypes.c_int32]
     L.mj_fft_roundtrip.argtypes = [vp, vp, vp, vp]
     L.mj_set_probes.argtypes = [vp, ctypes.c_int32, dp]
@@ -85,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     for f in ("mj_create", "mj_info", "mj_set_plane_waves", "mj_run", "mj_reset", "mj_history_sum",
               "mj_kernel_values", "mj_stats", "mj_fft_roundtrip", "mj_set_probes", "mj_march",
               "mj_probe_kernel_values", "mj_set_eps", "mj_adjoint_gradient", "mj_get_state", "mj_set_state",
-              "mj_step", "mj_march_every"):
+              "mj_step", "mj_march_every", "mj_kernel_values_noalloc"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -286,6 +287,16 @@ class Solver:
         ip = ctypes.POINTER(ctypes.c_int32)
         self._check(self._lib.mj_kernel_values(self._h, len(lags), lags.ctypes.data_as(ip),
                                                offs.ctypes.data_as(ip), _dptr(out)))
+        return out
+
+    def kernel_values_noalloc(self, lags, offsets) -> np.ndarray:
+        """kernel_values through the library's fixed staging array (no device allocation)."""
+        lags = np.ascontiguousarray(np.asarray(lags, dtype=np.int32))
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+        out = np.zeros((len(lags), 6))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        self._check(self._lib.mj_kernel_values_noalloc(self._h, len(lags), lags.ctypes.data_as(ip),
+                                                       offs.ctypes.data_as(ip), _dptr(out)))
         return out
 
     def set_eps(self, eps):
