@@ -39,6 +39,8 @@ WORKLOADS = {
           "plane wave sigma=8 dt delay 6 sigma, 17-tap binomial FIR delta=0.01",
     "C2": "32^3 sphere r=15h eps_r=12, c dt = h, x-pol +z Gaussian sigma=4 dt, 17-tap binomial FIR delta=0.01",
     "C1": "8^3 cube eps_r=4, c dt = h, x-pol +z Gaussian sigma=4 dt, no FIR",
+    "C3": "64^3 eps_r box-smoothed U[2,20], 16 plane waves sigma=6 dt, 17-tap binomial FIR delta=0.01",
+    "C4": "48^3 eps_r=10 with a 16^3 design region U[1,12], x-pol +z Gaussian sigma=4 dt, 17-tap FIR delta=0.01",
     "C5s": "C5 with c dt = h/2 (ell = 362)",
     "C5p": "C5 on voxels 1 x 0.7 x 1.3 with c dt = 0.7 (ell = 266)",
 }
@@ -174,6 +176,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched (C3) and adjoint (C4) ratios")
     ap.add_argument("--time-block", type=int, default=0, help="steps per time block (0 = library default)")
+    ap.add_argument("--outer-block", type=int, default=0, help="steps per outer time block (three levels; 0 = two)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -203,18 +206,19 @@ def main():
 
     prob = wl.config(args.workload)
     t_setup = time.perf_counter()
-    solver = motjvie.solver_for(prob, time_block=args.time_block)
+    solver = motjvie.solver_for(prob, time_block=args.time_block, outer_block=args.outer_block)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     info = solver.info()
     ell = info["ell"]
     warmup = max(0, args.warmup)
     B = info["time_block"]
+    period = info["outer_block"] or B   # steps between far launches
     # prefill: at least ell + 1 steps, so that the ring holds ell sources and every far launch
-    # sums all ell lags; blocks start at steps 2, 2 + B, ..., and the step after prefill + warmup
-    # steps starts one when prefill + warmup = 1 mod B
+    # sums all ell lags; blocks start at steps 2, 2 + period, ..., and the step after
+    # prefill + warmup steps starts one when prefill + warmup = 1 mod period
     prefill = ell + 1
-    while B > 1 and (prefill + warmup - 1) % B:
+    while period > 1 and (prefill + warmup - 1) % period:
         prefill += 1
     print("setup %.2f s (kernels %.0f ms, spectra %.0f ms), ell=%d, pads %dx%dx%d, %.1f GB; prefill %d steps" % (
         t_setup, info["gen_ms"], info["spectra_ms"], ell, info["Nx"], info["Ny"], info["Nz"],
@@ -228,10 +232,10 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = solver.stats()
-    if B > 1 and args.steps % B:
+    if period > 1 and args.steps % period:
         print("note: %d timed steps are not a whole number of %d-step time blocks: the window starts with a "
               "far launch and holds %d of them, %.3f per step against 1/%d" % (
-                  args.steps, B, st["far_launches"], st["far_launches"] / args.steps, B),
+                  args.steps, period, st["far_launches"], st["far_launches"] / args.steps, period),
               file=sys.stderr, flush=True)
     M = prob.M
     value = M * args.steps / elapsed
@@ -240,37 +244,48 @@ def main():
         st["fft_fwd_ms"], st["mac_ms"], st["fft_inv_ms"], st["epilogue_ms"], st["z0_ms"], st["cg_iters"]),
         file=sys.stderr, flush=True)
 
-    # roofline of the far-part MAC kernel (k_mac_far): algorithmic bytes per launch
+    # roofline of the far-part MAC kernel: algorithmic bytes per launch
     Nx, Ny, Nz = info["Nx"], info["Ny"], info["Nz"]
     Hx = Nx // 2 + 1
     half = Hx * Ny * Nz                       # half-spectrum points
     octant = Hx * (Ny // 2 + 1) * (Nz // 2 + 1)
+    R = info["n_rhs"]
+    # bytes of the Jhat spectra of one step (all right-hand sides) and of one (octant) Khat lag,
+    # which the right-hand sides share
+    SJ, SK = 48.0 * half * R, 48.0 * octant
+    B2 = info["outer_block"]
+    TB = B2 if B2 else B                      # targets of one far launch
     if B > 1:
-        # per launch: every one of the ell lags once (48 B of Jhat per point, 48 B of Khat per
-        # octant point) and B partial sums written (48 B per point each)
-        bytes_launch = ell * (48.0 * half + 48.0 * octant) + B * 48.0 * half
+        # per launch: every one of the ell lags once (Jhat and Khat) and TB partial sums written
+        bytes_launch = ell * (SJ + SK) + TB * SJ
         launch_ms = st["far_launch_ms"]
-        kname = "k_mac_far<%d> (time-blocked history MAC, far part)" % B
+        kname = ("k_mac_win<%d> (outer level of three, history MAC)" % TB if B2 else
+                 "k_mac_win<%d> (time-blocked history MAC, far part)" % TB)
     else:
-        bytes_launch = ell * (48.0 * half + 48.0 * octant) + 48.0 * half
+        bytes_launch = ell * (SJ + SK) + SJ
         launch_ms = st["mac_ms"]
         kname = "k_mac (history MAC, all lags every step)"
     achieved = bytes_launch / (launch_ms / 1e3) / 1e9
     # FP64 work of the same launch: a real symmetric 3x3 times a complex 3-vector is 36 FLOP per
     # (lag, half-spectrum point, target); target t of a block sums lags t + 1 .. ell
-    flop_launch = 36.0 * half * (sum(ell - t for t in range(B)) if B > 1 else ell)
+    flop_launch = 36.0 * half * R * (sum(ell - t for t in range(TB)) if B > 1 else ell)
     tflops = flop_launch / (launch_ms / 1e3) / 1e12
     fp64 = {"flop_per_launch": flop_launch, "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tflops / FP64_PEAK_TFLOPS}
     traffic = mac_traffic(args.workload)
-    # the whole FFT convolution of a step (forward FFT, far + near MAC, inverse FFT): algorithmic
-    # bytes per step over the measured time of those three phases
+    # the whole FFT convolution of a step (forward FFT, MAC at every level, inverse FFT):
+    # algorithmic bytes per step over the measured time of those three phases
     U, V, W = prob.U, prob.V, prob.W
-    Hx_ = Nx // 2 + 1
-    fft_bytes = 8.0 * 3 * M + 16.0 * 3 * (Hx_ * V * W + Hx_ * V * W + Hx_ * Ny * W + Hx_ * Ny * W + half)
+    fft_bytes = R * (8.0 * 3 * M + 16.0 * 3 * (Hx * V * W + Hx * V * W + Hx * Ny * W + Hx * Ny * W + half))
     if B > 1:
-        near_bytes = sum(2 * 48.0 * half + t * (48.0 * half + 48.0 * octant) for t in range(1, B)) / B
-        mac_step = bytes_launch / B + near_bytes
+        # near part of the step at position t of an inner block: read and write F[t], t lags
+        near_bytes = sum(2 * SJ + t * (SJ + SK) for t in range(1, B)) / B
+        mac_step = bytes_launch / TB + near_bytes
+        if B2:
+            # middle part at the start of inner block q > 0: its B sums start from the outer ones,
+            # q B sources of the outer block, lags up to q B + B - 1, B sums written
+            mid = sum(B * SJ + q * B * SJ + (q * B + B - 1) * SK + B * SJ for q in range(1, B2 // B))
+            mac_step += mid / B2
     else:
         mac_step = bytes_launch
     conv_bytes = 2 * fft_bytes + mac_step
@@ -297,7 +312,8 @@ def main():
                    "far_launches_timed": int(st["far_launches"]),
                    "phase_ms": {k: round(st[k], 4) for k in ("fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms",
                                                               "z0_ms")},
-                   "cg_iters": round(st["cg_iters"], 2), "time_block": B,
+                   "cg_iters": round(st["cg_iters"], 2), "time_block": B, "outer_block": B2,
+                   "mid_launch_ms": round(st["mid_launch_ms"], 4),
                    "fft_pencils": [info["fft_pencils_x"], info["fft_pencils_y"], info["fft_pencils_z"]],
                    "far_launch_ms": round(st["far_launch_ms"], 4), "near_launch_ms": round(st["near_launch_ms"], 4)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

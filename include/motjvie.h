@@ -68,7 +68,12 @@ typedef struct {
     int32_t n_rhs;            /* number of right-hand sides (plane waves) marched together, >= 1 */
     double cg_rtol;           /* relative residual of the Z_0 solve; <= 0 selects 1e-13 */
     int32_t cg_maxit;         /* <= 0 selects 200 */
-    int32_t time_block;       /* steps per time block of the history MAC: 1 (none), 4, 8, 16 or 32; 0 selects the default */
+    int32_t time_block;       /* steps per time block of the history MAC (Sec. 4.1): 1 (none), 4, 8, 10, 12,
+                                 14, 16 or 32.  0 (with outer_block 0): the default, blocks of 4 inside
+                                 outer blocks of 16 when ell >= 64, else blocks of 8.  < 0: chosen at
+                                 mj_create by timing one period of the MAC for each of (8), (12), (16),
+                                 (4 in 8), (4 in 12), (4 in 16), (8 in 16); the choices group the terms
+                                 of eq:PnMOT differently, so results then vary with it at rounding level */
     void *stream;             /* hipStream_t to enqueue on; NULL = the null stream */
     int32_t quad_order;       /* Gauss-Legendre points per cell of the kernel quadrature; 0 selects 16 */
     int32_t fft_pencils;      /* pencils per block of the FFT passes: 0 = pick per pass by timing at
@@ -85,6 +90,9 @@ typedef struct {
     void *(*alloc)(size_t bytes, void *ctx);
     void (*free_)(void *ptr, void *ctx);
     void *alloc_ctx;
+    int32_t outer_block;      /* a third level of the time division (Sec. 4.1 applied twice): steps per
+                                 outer block, a multiple of time_block (which must then be 4 or 8), even,
+                                 in 8 .. 16.  0 or 1: two levels (or the default, see time_block) */
 } mj_config;
 
 /*
@@ -104,13 +112,13 @@ void mj_destroy(mj_solver *s);
 const char *mj_last_error(const mj_solver *s);
 
 /*
- * mj_info -- sizes of the solver.  out (host, n entries used, n <= 19):
+ * mj_info -- sizes of the solver.  out (host, n entries used, n <= 20):
  *   [0] ell  [1] Nx [2] Ny [3] Nz (padded FFT sizes)  [4] time block B
  *   [5] history depth kept in real space  [6] n_rhs  [7] current step n
  *   [8] device bytes allocated  [9] kernel generation time (ms)  [10] spectra time (ms)
  *   [11] number of FIR taps  [12] probes  [13] lag window per probe pair
  *   [14] probe pairs  [15] probe kernel generation time (ms)
- *   [16] [17] [18] pencils per block of the x, y and z FFT passes
+ *   [16] [17] [18] pencils per block of the x, y and z FFT passes  [19] outer time block (0: none)
  */
 int mj_info(const mj_solver *s, double *out, int32_t n);
 
@@ -278,13 +286,15 @@ int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const 
 
 /*
  * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
- *   in ms per step, and CG statistics.  out (host, n <= 18): [0] forward FFT  [1] history
+ *   in ms per step, and CG statistics.  out (host, n <= 19): [0] forward FFT  [1] history
  *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total
  *   [6] mean CG iterations  [7] max final relative residual  [8] steps timed
  *   [9] max CG iterations  [10] mean duration of one far-part MAC launch (time-blocked,
  *   once per block)  [11] far-part launches  [12] mean duration of one near-part launch
  *   [13] probes.  [5] includes [13].  After mj_adjoint_gradient: [14] forward pass (ms,
  *   whole run)  [15] backward pass with recomputation (ms)  [16] segments  [17] checkpoint bytes.
+ *   [18] mean duration of one middle-level MAC launch (three time levels).  With three levels,
+ *   [10] and [11] describe the outer launches.
  */
 int mj_stats(const mj_solver *s, double *out, int32_t n);
 

@@ -16,7 +16,7 @@ SOURCES = ["mj_fft.hip", "mj_gen.hip", "mj_march.hip", "mj_api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC",
+    "-O3", "-std=c++20", "-fPIC",
     "--offload-arch=" + ARCH,
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

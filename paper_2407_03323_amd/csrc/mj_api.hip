@@ -90,7 +90,8 @@ struct mj_solver {
     std::vector<double> fir;
     double cg_rtol = 1e-13;
     int cg_maxit = 200;
-    int B = 1;
+    int B = 1;                      // steps per (inner) time block
+    int B2 = 0;                     // steps per outer time block (three levels), 0: two levels
     int nquad = 16;
     hipStream_t st = nullptr;
     int nloc = 5, rdepth = 6;
@@ -106,6 +107,7 @@ struct mj_solver {
     double *fir_d = nullptr;
     double *Khat = nullptr;
     double2 *ring = nullptr, *Shat = nullptr, *farbuf = nullptr;
+    double2 *gbuf = nullptr;        // outer-block partial sums [B2][nrhs][3][plane] (three levels)
     double *S = nullptr, *Jr = nullptr;
     double *rhs = nullptr, *y = nullptr, *p = nullptr, *q = nullptr;
     double *u = nullptr, *uy = nullptr;
@@ -137,7 +139,8 @@ struct mj_solver {
     double *Lr = nullptr, *bq = nullptr;
     // statistics of the last run
     double t_gen_ms = 0, t_spec_ms = 0, t_probe_ms = 0;
-    double stat[18] = {};
+    double t_mac_tune_ms = 0;       // MAC time per step of the timed choice (time_block < 0)
+    double stat[19] = {};
     Events events;
 
     template <class T>
@@ -186,13 +189,34 @@ struct mj_solver {
         double *Pout = nullptr;         // forward: probe field of the step (else the internal buffer)
         bool skip_probes = false;
         double *Bout = nullptr;         // forward: gradient term B_n
-        char *far_kind = nullptr;       // 1 far launch, 2 near launch
+        char *far_kind = nullptr;       // 1 far (outer) launch, 2 near launch, 3 middle launch
         bool adjoint = false;           // transposed march
         const double *G = nullptr;      // adjoint: source g_j
         const double *Bj = nullptr;     // adjoint: B_j for the gradient (NULL: none)
         double *grad = nullptr;         // adjoint: gradient accumulator
     };
     mj::EpiArg epi_arg() const;
+    const double2 *mac(int n, int *kind);
+    void mac_autotune();
+    void default_time_division();
+    // arguments of a time-block MAC launch writing to `out`, first target step nb
+    mj::BlockMacArg block_arg(double2 *out, int nb) const
+    {
+        mj::BlockMacArg a{};
+        a.Khat = Khat;
+        a.ring_base = ring;
+        a.far = out;
+        a.Hx = Hx;
+        a.Hp = Hp;
+        a.Ny = Ny;
+        a.Nz = Nz;
+        a.nk = ell;
+        a.ring = ell;
+        a.nb = nb;
+        a.nrhs = nrhs;
+        a.jmin = 1;
+        return a;
+    }
     mj::AdjArg adj_arg() const;
     void step(const StepIO &io);
     void check_growth() const;
@@ -260,9 +284,15 @@ void mj_solver::create(const mj_config &c)
     Nz = mj::fft_pick_size(2 * W - 1);
     Hx = Nx / 2 + 1;
     Hp = mj::spectrum_pitch(Hx);
+    const bool tune_mac = c.time_block < 0;
     B = c.time_block > 0 ? c.time_block : 8;
-    if (B != 1 && B != 4 && B != 8 && B != 16 && B != 32)
-        throw ArgError("time_block must be 0 (auto), 1, 4, 8, 16 or 32");
+    if (!(B == 1 || B == 4 || B == 32 || (B >= 8 && B <= 16 && B % 2 == 0)))
+        throw ArgError("time_block must be -1 (timed), 0 (default), 1, 4, 8, 10, 12, 14, 16 or 32");
+    B2 = c.outer_block > 1 ? c.outer_block : 0;
+    if (c.time_block == 0 && c.outer_block == 0) default_time_division();
+    if (B2 && !(B == 4 || B == 8) ) throw ArgError("outer_block needs time_block 4 or 8");
+    if (B2 && !(B2 > B && B2 % B == 0 && B2 >= 8 && B2 <= 16 && B2 % 2 == 0))
+        throw ArgError("outer_block must be a multiple of time_block in 8 .. 16 (even), or 0");
     nloc = std::max(guess_deg + 1, (int)fir.size() - 1);   // the initial guess uses guess_deg + 1 steps
     rdepth = nloc + 1;
 
@@ -282,7 +312,10 @@ void mj_solver::create(const mj_config &c)
     const long sp = spec_plane();
     ring = dalloc<double2>((size_t)ell * nrhs * 3 * sp, "spectral history ring");
     Shat = dalloc<double2>((size_t)nrhs * 3 * sp, "spectral sum");
-    if (B > 1) farbuf = dalloc<double2>((size_t)B * nrhs * 3 * sp, "time-block partial sums");
+    // a timed choice of the time division tries blocks of up to 16 steps at both levels
+    const int fb_targets = tune_mac ? 16 : B, gb_targets = tune_mac ? 16 : B2;
+    if (fb_targets > 1) farbuf = dalloc<double2>((size_t)fb_targets * nrhs * 3 * sp, "time-block partial sums");
+    if (gb_targets) gbuf = dalloc<double2>((size_t)gb_targets * nrhs * 3 * sp, "outer-block partial sums");
     S = dalloc<double>((size_t)nrhs * 3 * M, "convolution");
     Jr = dalloc<double>((size_t)rdepth * nrhs * 3 * M, "current history");
     rhs = dalloc<double>((size_t)nrhs * 3 * M, "cg rhs");
@@ -308,6 +341,7 @@ void mj_solver::create(const mj_config &c)
     bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hp + (size_t)3 * nrhs * W * Ny * Hp);
     if (c.fft_pencils > 0) mj::fft3d_set_pencils(fft, c.fft_pencils);
     else mj::fft3d_autotune(fft, st);
+    if (tune_mac) mac_autotune();
     n = 0;
     MJ_CHECK(hipStreamSynchronize(st));
 }
@@ -519,6 +553,139 @@ mj::EpiArg mj_solver::epi_arg() const
     return e;
 }
 
+// The spectral history sum of step n >= 2 (sources J_1 .. J_{n-1} in the ring), launched as the
+// configured time division requires; returns where the step's sum is left.  *kind: 1 far (outer)
+// launch, 2 near, 3 middle, 0 none of these (no time blocking).
+const double2 *mj_solver::mac(int n, int *kind)
+{
+    const long sp = spec_plane();
+    const double2 *spec = Shat;
+    int far_kind = 0;
+    if (B == 1) {
+        mj::MacArg a{};
+        a.Khat = Khat;
+        a.ring_base = ring;
+        a.Shat = Shat;
+        a.Hx = Hx;
+        a.Hp = Hp;
+        a.Ny = Ny;
+        a.Nz = Nz;
+        a.nk = std::min(ell, n - 1);
+        a.ring = ell;
+        a.slot_nm1 = slotS(n - 1);
+        a.nrhs = nrhs;
+        mj::launch_mac(a, st);
+    } else if (B2 == 0) {
+        // blocks of B steps starting at n_b = 2, 2 + B, ...: the far part of every step of the
+        // block is formed at n_b, when all of its sources are in the ring
+        const int t = (n - 2) % B;
+        mj::BlockMacArg a = block_arg(farbuf, n - t);
+        a.ntarget = B;
+        a.t = t;
+        if (t == 0) mj::launch_mac_far(a, B, st);
+        else mj::launch_mac_near(a, st);
+        far_kind = t == 0 ? 1 : 2;
+        spec = farbuf + (size_t)t * nrhs * 3 * sp;
+    } else {
+        // three levels (the Toeplitz division of Sec. 4.1 applied twice): outer blocks of B2
+        // steps start at N_b = 2, 2 + B2, ...; each splits into inner blocks of B steps.
+        //   outer, at N_b:  G[tau] = sum_{k > tau} Khat_k Jhat_{N_b + tau - k} over sources before N_b
+        //   middle, at each inner start n_b > N_b:  F[t] = G[n_b - N_b + t] + the terms of the
+        //                   sources N_b .. n_b - 1 (inside the outer block, before the inner one)
+        //   near, every step:  + the terms of the sources n_b .. n - 1
+        // The first inner block needs no middle part: its sums stay in G.
+        const int tau = (n - 2) % B2, t = tau % B, q = tau / B;
+        double2 *fb = q == 0 ? gbuf : farbuf;
+        if (tau == 0) {
+            mj::BlockMacArg a = block_arg(gbuf, n);
+            a.ntarget = B2;
+            mj::launch_mac_win(a, B2, st);
+            far_kind = 1;
+        } else if (t == 0) {
+            mj::BlockMacArg a = block_arg(farbuf, n);
+            a.ntarget = B;
+            a.jmin = n - tau;
+            a.init = gbuf + (size_t)tau * nrhs * 3 * sp;
+            mj::launch_mac_win(a, B, st);
+            far_kind = 3;
+        } else {
+            mj::BlockMacArg a = block_arg(fb, n - t);
+            a.t = t;
+            mj::launch_mac_near(a, st);
+            far_kind = 2;
+        }
+        spec = fb + (size_t)t * nrhs * 3 * sp;
+    }
+    *kind = far_kind;
+    return spec;
+}
+
+// Default time division when the caller sets neither block: three levels, blocks of 4 in
+// outer blocks of 16, once the kernel reaches far enough back in time (ell >= 64) for the
+// outer level to pay; else two levels with blocks of 8.  At 104^3 (ell = 182) per step:
+// 2.85 ms against 3.39 ms for blocks of 8 alone.
+void mj_solver::default_time_division()
+{
+    if (ell >= 64) {
+        B = 4;
+        B2 = 16;
+    } else {
+        B = 8;
+        B2 = 0;
+    }
+}
+
+// Picks the time division (time block B, outer block B2) by timing the history sum of one
+// period of steps at steady state for each candidate: every lag live (the steps timed lie
+// beyond ell), on a cleared ring (the values do not change the time).  The candidates only
+// group the terms of eq:PnMOT differently, so results depend on the choice at rounding level.
+void mj_solver::mac_autotune()
+{
+    static const int cand[][2] = {{8, 0}, {12, 0}, {16, 0}, {4, 8}, {4, 12}, {4, 16}, {8, 16}};
+    MJ_CHECK(hipMemsetAsync(ring, 0, sizeof(double2) * (size_t)ell * nrhs * 3 * spec_plane(), st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MJ_CHECK(hipEventCreate(&e0));
+    MJ_CHECK(hipEventCreate(&e1));
+    double best = -1.0;
+    int bestB = 8, bestB2 = 0;
+    try {
+        for (const auto &cd : cand) {
+            B = cd[0];
+            B2 = cd[1];
+            const int period = B2 ? B2 : B;
+            const int n0 = 2 + period * ((ell + period - 1) / period);
+            double tmin = -1.0;
+            for (int rep = 0; rep < 3; rep++) {
+                MJ_CHECK(hipEventRecord(e0, st));
+                for (int i = 0; i < period; i++) {
+                    int kind = 0;
+                    (void)mac(n0 + i, &kind);
+                }
+                MJ_CHECK(hipEventRecord(e1, st));
+                MJ_CHECK(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                MJ_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0 && (tmin < 0.0 || ms < tmin)) tmin = ms;
+            }
+            const double per_step = tmin / period;
+            if (best < 0.0 || per_step < best) {
+                best = per_step;
+                bestB = cd[0];
+                bestB2 = cd[1];
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B = bestB;
+    B2 = bestB2;
+    t_mac_tune_ms = best;
+}
+
 // One step n -> n + 1 of the march on the current track: FFT of the newest source, spectral
 // history sum (plain or time-blocked), inverse FFT, right-hand side, Z_0 solve, and the
 // outputs asked for.  io.adjoint runs the transposed march instead (sources nu, local
@@ -536,45 +703,8 @@ void mj_solver::step(const StepIO &io)
                           3 * nrhs, st);
     }
     if (ev) MJ_CHECK(hipEventRecord(ev[1], st));
-    const double2 *spec = Shat;
     int far_kind = 0;
-    if (hist && B == 1) {
-        mj::MacArg a{};
-        a.Khat = Khat;
-        a.ring_base = ring;
-        a.Shat = Shat;
-        a.Hx = Hx;
-        a.Hp = Hp;
-        a.Ny = Ny;
-        a.Nz = Nz;
-        a.nk = std::min(ell, n - 1);
-        a.ring = ell;
-        a.slot_nm1 = slotS(n - 1);
-        a.nrhs = nrhs;
-        mj::launch_mac(a, st);
-    } else if (hist) {
-        // blocks of B steps starting at n_b = 2, 2 + B, ...: the far part of every step of the
-        // block is formed at n_b, when all of its sources are in the ring
-        const int t = (n - 2) % B;
-        mj::BlockMacArg a{};
-        a.Khat = Khat;
-        a.ring_base = ring;
-        a.far = farbuf;
-        a.Hx = Hx;
-        a.Hp = Hp;
-        a.Ny = Ny;
-        a.Nz = Nz;
-        a.nk = ell;
-        a.ring = ell;
-        a.nb = n - t;
-        a.ntarget = B;
-        a.t = t;
-        a.nrhs = nrhs;
-        if (t == 0) mj::launch_mac_far(a, B, st);
-        else mj::launch_mac_near(a, st);
-        far_kind = t == 0 ? 1 : 2;
-        spec = farbuf + (size_t)t * nrhs * 3 * sp;
-    }
+    const double2 *spec = hist ? mac(n, &far_kind) : Shat;
     if (io.far_kind) *io.far_kind = (char)far_kind;
     if (ev) MJ_CHECK(hipEventRecord(ev[2], st));
     if (hist) mj::fft3d_inverse(fft, spec, S, 3 * nrhs, st);
@@ -697,8 +827,8 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
     }
     MJ_CHECK(hipStreamSynchronize(st));
     double ph[6] = {0, 0, 0, 0, 0, 0}, probe_ms = 0;
-    double far_ms = 0, near_ms = 0;
-    int nfar = 0, nnear = 0;
+    double far_ms = 0, near_ms = 0, mid_ms = 0;
+    int nfar = 0, nnear = 0, nmid = 0;
     for (int s = 0; s < n_steps; s++) {
         hipEvent_t *ev = &events.ev[(size_t)7 * s];
         for (int k = 0; k < 5; k++) {
@@ -707,6 +837,7 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
             ph[k] += ms;
             if (k == 1 && step_far[s] == 1) { far_ms += ms; nfar++; }
             if (k == 1 && step_far[s] == 2) { near_ms += ms; nnear++; }
+            if (k == 1 && step_far[s] == 3) { mid_ms += ms; nmid++; }
         }
         float pms = 0, tot = 0;
         MJ_CHECK(hipEventElapsedTime(&pms, ev[5], ev[6]));
@@ -724,6 +855,7 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
     stat[11] = nfar;
     stat[12] = nnear ? near_ms / nnear : 0.0;
     stat[13] = probe_ms / ns;
+    stat[18] = nmid ? mid_ms / nmid : 0.0;
     if (noconv) throw std::range_error("Z_0 solve did not converge");
 }
 
@@ -991,17 +1123,18 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
 namespace {
 struct StateHeader {
     char magic[8];
-    int32_t version, U, V, W, nrhs, ell, B, rdepth, Nx, Ny, Nz, Hp;
-    int64_t n, ring_bytes, far_bytes, jr_bytes;
+    int32_t version, U, V, W, nrhs, ell, B, rdepth, Nx, Ny, Nz, Hp, B2, pad_;
+    int64_t n, ring_bytes, far_bytes, jr_bytes, outer_bytes;
 };
-constexpr char kStateMagic[8] = {'M', 'J', 'S', 'T', 'A', 'T', 'E', '1'};
+constexpr char kStateMagic[8] = {'M', 'J', 'S', 'T', 'A', 'T', 'E', '2'};
 }  // namespace
 
 size_t mj_solver::state_bytes() const
 {
     const size_t sp = (size_t)spec_plane(), v3 = (size_t)nrhs * 3;
     return sizeof(StateHeader) + sizeof(double2) * (size_t)ell * v3 * sp +
-           (farbuf ? sizeof(double2) * (size_t)B * v3 * sp : 0) + sizeof(double) * (size_t)rdepth * v3 * M;
+           (farbuf ? sizeof(double2) * (size_t)B * v3 * sp : 0) + (gbuf ? sizeof(double2) * (size_t)B2 * v3 * sp : 0) +
+           sizeof(double) * (size_t)rdepth * v3 * M;
 }
 
 void mj_solver::get_state(void *buf) const
@@ -1009,7 +1142,7 @@ void mj_solver::get_state(void *buf) const
     const size_t sp = (size_t)spec_plane(), v3 = (size_t)nrhs * 3;
     StateHeader h{};
     std::memcpy(h.magic, kStateMagic, 8);
-    h.version = 1;
+    h.version = 2;
     h.U = U;
     h.V = V;
     h.W = W;
@@ -1021,10 +1154,12 @@ void mj_solver::get_state(void *buf) const
     h.Ny = Ny;
     h.Nz = Nz;
     h.Hp = Hp;
+    h.B2 = B2;
     h.n = n;
     h.ring_bytes = (int64_t)(sizeof(double2) * (size_t)ell * v3 * sp);
     h.far_bytes = farbuf ? (int64_t)(sizeof(double2) * (size_t)B * v3 * sp) : 0;
     h.jr_bytes = (int64_t)(sizeof(double) * (size_t)rdepth * v3 * M);
+    h.outer_bytes = gbuf ? (int64_t)(sizeof(double2) * (size_t)B2 * v3 * sp) : 0;
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -1034,6 +1169,8 @@ void mj_solver::get_state(void *buf) const
     if (h.far_bytes) MJ_CHECK(hipMemcpy(p, farbuf, (size_t)h.far_bytes, hipMemcpyDeviceToHost));
     p += h.far_bytes;
     MJ_CHECK(hipMemcpy(p, Jr, (size_t)h.jr_bytes, hipMemcpyDeviceToHost));
+    p += h.jr_bytes;
+    if (h.outer_bytes) MJ_CHECK(hipMemcpy(p, gbuf, (size_t)h.outer_bytes, hipMemcpyDeviceToHost));
 }
 
 void mj_solver::set_state(const void *buf, size_t bytes)
@@ -1041,13 +1178,13 @@ void mj_solver::set_state(const void *buf, size_t bytes)
     StateHeader h;
     if (bytes < sizeof h) throw ArgError("state buffer too short");
     std::memcpy(&h, buf, sizeof h);
-    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1) throw ArgError("not a march state");
-    if (h.U != U || h.V != V || h.W != W || h.nrhs != nrhs || h.ell != ell || h.B != B || h.Nx != Nx ||
-        h.Ny != Ny || h.Nz != Nz || h.Hp != Hp)
-        throw ArgError("state of a solver with another grid, n_rhs, ell or time block");
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 2) throw ArgError("not a march state");
+    if (h.U != U || h.V != V || h.W != W || h.nrhs != nrhs || h.ell != ell || h.B != B || h.B2 != B2 ||
+        h.Nx != Nx || h.Ny != Ny || h.Nz != Nz || h.Hp != Hp)
+        throw ArgError("state of a solver with another grid, n_rhs, ell or time blocks");
     if (h.rdepth != rdepth) throw ArgError("state of a solver with another history depth (probes differ)");
-    if (bytes < state_bytes() || (size_t)h.ring_bytes + (size_t)h.far_bytes + (size_t)h.jr_bytes + sizeof h !=
-                                     state_bytes())
+    if (bytes < state_bytes() || (size_t)h.ring_bytes + (size_t)h.far_bytes + (size_t)h.jr_bytes +
+                                         (size_t)h.outer_bytes + sizeof h != state_bytes())
         throw ArgError("state buffer has the wrong size");
     if (h.n < 0 || h.n > INT32_MAX) throw ArgError("bad step count in the state");
     const char *p = (const char *)buf + sizeof h;
@@ -1057,6 +1194,8 @@ void mj_solver::set_state(const void *buf, size_t bytes)
     if (h.far_bytes) MJ_CHECK(hipMemcpy(farbuf, p, (size_t)h.far_bytes, hipMemcpyHostToDevice));
     p += h.far_bytes;
     MJ_CHECK(hipMemcpy(Jr, p, (size_t)h.jr_bytes, hipMemcpyHostToDevice));
+    p += h.jr_bytes;
+    if (h.outer_bytes) MJ_CHECK(hipMemcpy(gbuf, p, (size_t)h.outer_bytes, hipMemcpyHostToDevice));
     n = (int)h.n;
 }
 
@@ -1079,7 +1218,9 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
     if (rdepth < ell + 1) throw std::logic_error("probe history depth");
     // segment starts: 1, then block starts 2 + c L with L a multiple of the time block
     int L = ckpt_every > 0 ? ckpt_every : N;
-    if (B > 1) L = ((L + B - 1) / B) * B;
+    // restarts at (outer) time-block starts repeat the original arithmetic exactly
+    const int period = B2 ? B2 : B;
+    if (period > 1) L = ((L + period - 1) / period) * period;
     std::vector<int> starts{1};
     for (long s0 = 2 + (long)L; s0 <= N; s0 += L) starts.push_back((int)s0);
     const int C = (int)starts.size();
@@ -1116,10 +1257,11 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
     double *bqb = (double *)talloc(sizeof(double) * vec, "adjoint rhs");
     double2 *ring_a = (double2 *)talloc(sizeof(double2) * (size_t)ell * nrhs * 3 * sp, "adjoint ring");
     double2 *far_a = B > 1 ? (double2 *)talloc(sizeof(double2) * (size_t)B * nrhs * 3 * sp, "adjoint blocks") : nullptr;
+    double2 *g_a = B2 ? (double2 *)talloc(sizeof(double2) * (size_t)B2 * nrhs * 3 * sp, "adjoint outer blocks") : nullptr;
     double *nu_r = (double *)talloc(sizeof(double) * (size_t)rdepth * vec, "adjoint history");
     double *lam_r = (double *)talloc(sizeof(double) * (size_t)rdepth * vec, "adjoint local history");
     MJ_CHECK(hipMemsetAsync(grad_dev, 0, sizeof(double) * M, st));
-    double2 *const ring_f = ring, *const far_f = farbuf;
+    double2 *const ring_f = ring, *const far_f = farbuf, *const g_f = gbuf;
     double *const Jr_f = Jr;
     hipEvent_t tev[3];
     for (auto &tv : tev) MJ_CHECK(hipEventCreate(&tv));
@@ -1181,6 +1323,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             // transposed march over j = s1 .. s0 (reversed step n' = N + 1 - j)
             ring = ring_a;
             farbuf = far_a;
+            gbuf = g_a;
             Jr = nu_r;
             Lr = lam_r;
             bq = bqb;
@@ -1203,6 +1346,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             n_adj = n;
             ring = ring_f;
             farbuf = far_f;
+            gbuf = g_f;
             Jr = Jr_f;
             Lr = nullptr;
             bq = nullptr;
@@ -1213,6 +1357,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
         (void)hipStreamSynchronize(st);
         ring = ring_f;
         farbuf = far_f;
+        gbuf = g_f;
         Jr = Jr_f;
         Lr = nullptr;
         bq = nullptr;
@@ -1293,11 +1438,11 @@ const char *mj_last_error(const mj_solver *s) { return s ? s->err.c_str() : g_er
 int mj_info(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    double v[19] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
+    double v[20] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
                     (double)s->rdepth, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
                     s->t_spec_ms, (double)s->fir.size(), (double)s->np, (double)s->nw, (double)s->npairs,
-                    s->t_probe_ms, (double)s->fft.Px, (double)s->fft.Py, (double)s->fft.Pz};
-    for (int i = 0; i < n && i < 19; i++) out[i] = v[i];
+                    s->t_probe_ms, (double)s->fft.Px, (double)s->fft.Py, (double)s->fft.Pz, (double)s->B2};
+    for (int i = 0; i < n && i < 20; i++) out[i] = v[i];
     return MJ_OK;
 }
 
@@ -1483,7 +1628,7 @@ int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const 
 int mj_stats(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    for (int i = 0; i < n && i < 18; i++) out[i] = s->stat[i];
+    for (int i = 0; i < n && i < 19; i++) out[i] = s->stat[i];
     return MJ_OK;
 }
 

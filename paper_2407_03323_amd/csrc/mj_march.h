@@ -29,6 +29,8 @@ struct BlockMacArg {
     int ntarget;               // targets written by the far kernel (<= TB)
     int t;                     // near: position of the step in the block
     int nrhs;
+    int jmin;                  // far: sources before step jmin count as zero (<= 1: none dropped)
+    const double2 *init;       // far: partial sums the targets start from, laid out like far (NULL: zero)
 };
 
 struct WaveArg {
@@ -149,6 +151,8 @@ void launch_adj_epilogue(const EpiArg &e, hipStream_t st);
 void launch_adj_lambda(const AdjArg &a, hipStream_t st);
 void launch_grad_accum(const AdjArg &a, hipStream_t st);
 void launch_mac_near(const BlockMacArg &a, hipStream_t st);
+// far part with the rotation-free source window: tb = 4, 8, 10, 12, 14 or 16 targets
+void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st);
 void launch_epilogue(const EpiArg &e, hipStream_t st);
 void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,
                           const double *fir, int nfir, long M, double *P, hipStream_t st);

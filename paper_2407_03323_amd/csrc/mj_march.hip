@@ -5,6 +5,7 @@
 
 #include <climits>
 #include <cmath>
+#include <utility>
 
 namespace mj {
 
@@ -324,6 +325,134 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     }
 }
 
+// Far part with a rotation-free source window.  Targets t = 0 .. TG - 1 are steps n_b + t; each
+// sums F[t] = init[t] + sum_k Khat_k Jhat_{n_b + t - k} over the lags k >= t + 1 whose source
+// n_b + t - k is at least jmin (and at least 1).  One lane = one part (real or imaginary) of one
+// mirror point, as in k_mac_far with one target group.  The lane loads, at lag k, the source
+// s_k = n_b - k of target 0; target t at lag k takes s_{k - t}, loaded t lags earlier.  Sources
+// sit in W = TG + PD register slots, s_k in slot k mod W: the load of lag k + PD (issued before
+// lag k is accumulated) overwrites the slot of s_{k - TG}, which no target needs at lag k or
+// later, so no value ever moves between registers.  Kernel values of lag k sit in slot
+// k mod (PD + 1).  The lag loop is unrolled by UF, a multiple of both slot counts, so that every
+// slot index is a compile-time constant.
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+template <int TG, int PD, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_mac_win(BlockMacArg a)
+{
+    constexpr int W = TG + PD, KS = PD + 1;
+    constexpr int UF = W / gcd_c(W, KS) * KS;
+    const int Nyo = a.Ny / 2 + 1, Nzo = a.Nz / 2 + 1;
+    const long nocts = (long)a.Hp * Nyo * Nzo;
+    const int lane = threadIdx.x & 63;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int r = lb % a.nrhs;
+    const long o = (lb / a.nrhs) * 32L + (lane >> 1);
+    const int part = lane & 1;
+    const int m = threadIdx.x >> 6;
+    if (o >= nocts) return;
+    const int kx = (int)(o % a.Hp), qy = (int)((o / a.Hp) % Nyo), qz = (int)(o / ((long)a.Hp * Nyo));
+    const int fy = m & 1, fz = m >> 1;
+    if (kx >= a.Hx) return;   // row padding
+    if ((fy && (qy == 0 || 2 * qy == a.Ny)) || (fz && (qz == 0 || 2 * qz == a.Nz))) return;
+    const int ky = fy ? a.Ny - qy : qy, kz = fz ? a.Nz - qz : qz;
+    const double sy = fy ? -1.0 : 1.0, sz = fz ? -1.0 : 1.0;
+    const long plane2 = 2L * a.Nz * a.Ny * a.Hp;                           // one component, in doubles
+    const unsigned joff = (unsigned)(2 * (((long)kz * a.Ny + ky) * a.Hp + kx) + part) * 8u;
+    const unsigned koff = (unsigned)(o * 48);
+    const long slot_bytes = (long)a.nrhs * 3 * plane2 * 8, plane_bytes = plane2 * 8;
+    const char *Jbase = (const char *)a.ring_base + (long)r * 3 * plane_bytes;
+    const char *Kbase = (const char *)a.Khat;
+    const long klag_bytes = 6 * nocts * 8;
+    const int nb = a.nb, jlo = max(1, a.jmin);
+    // the largest lag with a term: target TG - 1 reaches source jlo at lag nb + TG - 1 - jlo
+    const int kmax = min(a.nk, nb - jlo + TG - 1);
+
+    // accumulators and source slots per component: arrays of at most TG + PD doubles each, which
+    // the compiler keeps in registers
+    double ax[TG], ay[TG], az[TG];
+#pragma unroll
+    for (int t = 0; t < TG; t++) ax[t] = ay[t] = az[t] = 0.0;
+    if (a.init) {
+        const double *I = (const double *)a.init + (long)r * 3 * plane2 + joff / 8;
+        [&]<int... T>(std::integer_sequence<int, T...>) __attribute__((always_inline)) {
+            ((T < a.ntarget ? (ax[T] = I[(long)T * a.nrhs * 3 * plane2],
+                               ay[T] = I[(long)T * a.nrhs * 3 * plane2 + plane2],
+                               az[T] = I[(long)T * a.nrhs * 3 * plane2 + 2 * plane2], 0)
+                            : 0),
+             ...);
+        }(std::make_integer_sequence<int, TG>{});
+    }
+    double jx[W], jy[W], jz[W];
+    double k0s[KS], k1s[KS], k2s[KS], k3s[KS], k4s[KS], k5s[KS];   // xx yy zz xy xz yz
+#pragma unroll
+    for (int s = 0; s < W; s++) jx[s] = jy[s] = jz[s] = 0.0;   // sources before the first lag are zero
+    // the loads of lag k into source slot js and kernel slot ks (lags beyond kmax load nothing)
+    auto load = [&](int k, double &vx, double &vy, double &vz, double &c0, double &c1, double &c2, double &c3,
+                    double &c4, double &c5) __attribute__((always_inline)) {
+        if (k > kmax) return;
+        const int j = nb - k;
+        if (j >= jlo) {
+            const char *J = Jbase + ring_slot(j, a.ring) * slot_bytes + joff;
+            vx = *(const double *)J;
+            vy = *(const double *)(J + plane_bytes);
+            vz = *(const double *)(J + 2 * plane_bytes);
+        } else {
+            vx = vy = vz = 0.0;
+        }
+        const double2 *K2 = (const double2 *)(Kbase + (long)(k - 1) * klag_bytes + koff);
+        const double2 v0 = K2[0], v1 = K2[1], v2 = K2[2];
+        c0 = v0.x;
+        c1 = v0.y;
+        c2 = v1.x;
+        c3 = v1.y;
+        c4 = v2.x;
+        c5 = v2.y;
+    };
+    // lag k = k0 + i, k0 = 1 mod UF: source slot of s_{k - t} is (1 + i - t) mod W.  The UF steps
+    // are expanded from a compile-time index sequence, so every slot index is a constant.
+    auto step = [&](auto ic, int k0, bool guard) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        const int k = k0 + i;
+        if (guard && k > kmax) return;
+        constexpr int ls = (1 + i + PD) % W, lk = (1 + i + PD) % KS, ck = (1 + i) % KS;
+        load(k + PD, jx[ls], jy[ls], jz[ls], k0s[lk], k1s[lk], k2s[lk], k3s[lk], k4s[lk], k5s[lk]);
+        __builtin_amdgcn_sched_barrier(0);
+        const double kxx = k0s[ck], kyy = k1s[ck], kzz = k2s[ck];
+        const double kxy = k3s[ck] * sy, kxz = k4s[ck] * sz, kyz = k5s[ck] * sy * sz;
+        [&]<int... T>(std::integer_sequence<int, T...>) __attribute__((always_inline)) {
+            ((ax[T] = fma(kxz, jz[(1 + i - T + 4 * W) % W],
+                          fma(kxy, jy[(1 + i - T + 4 * W) % W], fma(kxx, jx[(1 + i - T + 4 * W) % W], ax[T]))),
+              ay[T] = fma(kyz, jz[(1 + i - T + 4 * W) % W],
+                          fma(kyy, jy[(1 + i - T + 4 * W) % W], fma(kxy, jx[(1 + i - T + 4 * W) % W], ay[T]))),
+              az[T] = fma(kzz, jz[(1 + i - T + 4 * W) % W],
+                          fma(kyz, jy[(1 + i - T + 4 * W) % W], fma(kxz, jx[(1 + i - T + 4 * W) % W], az[T])))),
+             ...);
+        }(std::make_integer_sequence<int, TG>{});
+    };
+    auto body = [&](int k0, bool guard) __attribute__((always_inline)) {
+        [&]<int... I>(std::integer_sequence<int, I...>) __attribute__((always_inline)) {
+            (step(std::integral_constant<int, I>{}, k0, guard), ...);
+        }(std::make_integer_sequence<int, UF>{});
+    };
+    (void)body;
+#pragma unroll
+    for (int d = 0; d < PD; d++) {
+        const int ls = (1 + d) % W, lk = (1 + d) % KS;
+        load(1 + d, jx[ls], jy[ls], jz[ls], k0s[lk], k1s[lk], k2s[lk], k3s[lk], k4s[lk], k5s[lk]);
+    }
+    int k0 = 1;
+    for (; k0 <= kmax; k0 += UF) body(k0, true);
+    double *Fd = (double *)a.far + (long)r * 3 * plane2 + joff / 8;
+    [&]<int... T>(std::integer_sequence<int, T...>) __attribute__((always_inline)) {
+        ((T < a.ntarget ? (Fd[(long)T * a.nrhs * 3 * plane2] = ax[T],
+                           Fd[(long)T * a.nrhs * 3 * plane2 + plane2] = ay[T],
+                           Fd[(long)T * a.nrhs * 3 * plane2 + 2 * plane2] = az[T], 0)
+                        : 0),
+         ...);
+    }(std::make_integer_sequence<int, TG>{});
+}
+
 // near part of step n = n_b + t, accumulated in place into F[t]
 __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 {
@@ -360,8 +489,14 @@ __global__ void __launch_bounds__(256) k_mac_near(BlockMacArg a)
 
 void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
 {
+    // 10 to 16 targets: the windowed kernel; 4, 8 and 32: the grouped one (at 8 targets it ran
+    // 12.10 against 11.61 ms per launch at 104^3).  Neither takes jmin or init here.
+    if (tb >= 10 && tb <= 16 && tb % 2 == 0) {
+        launch_mac_win(a, tb, st);
+        return;
+    }
     const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
-    // TB = TG * G targets per launch; points per block = 32 / G
+    // the grouped kernel for 4 and 32 targets: TB = TG * G targets per launch; points per block = 32 / G
     auto grid = [&](int G) { return dim3((unsigned)((nocts + 32 / G - 1) / (32 / G) * a.nrhs)); };
     const dim3 blk(256);
     switch (tb) {
@@ -369,9 +504,26 @@ void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
     // (168 VGPRs, one lag in flight) measured slower than two waves with two lags in flight.
     case 4: hipLaunchKernelGGL((k_mac_far<4, 1, 2, 3>), grid(1), blk, 0, st, a); break;
     case 8: hipLaunchKernelGGL((k_mac_far<8, 1, 2, 2>), grid(1), blk, 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_mac_far<8, 2, 2, 2>), grid(2), blk, 0, st, a); break;
     case 32: hipLaunchKernelGGL((k_mac_far<8, 4, 2, 2>), grid(4), blk, 0, st, a); break;
-    default: throw ArgError("unsupported time block (4, 8, 16 or 32)");
+    default: throw ArgError("unsupported time block (4, 8, 10, 12, 14, 16 or 32)");
+    }
+    MJ_CHECK(hipGetLastError());
+}
+
+void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st)
+{
+    const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
+    const dim3 grid((unsigned)((nocts + 31) / 32 * a.nrhs)), blk(256);
+    // second argument: lags in flight; the register file holds two at 8 targets, one above
+    // (166 to 238 VGPRs, two waves per SIMD)
+    switch (tb) {
+    case 4: hipLaunchKernelGGL((k_mac_win<4, 2, 3>), grid, blk, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_mac_win<8, 2, 2>), grid, blk, 0, st, a); break;
+    case 10: hipLaunchKernelGGL((k_mac_win<10, 1, 2>), grid, blk, 0, st, a); break;
+    case 12: hipLaunchKernelGGL((k_mac_win<12, 1, 2>), grid, blk, 0, st, a); break;
+    case 14: hipLaunchKernelGGL((k_mac_win<14, 1, 2>), grid, blk, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_mac_win<16, 1, 2>), grid, blk, 0, st, a); break;
+    default: throw ArgError("unsupported target count of the windowed far kernel (4, 8, 10, 12, 14 or 16)");
     }
     MJ_CHECK(hipGetLastError());
 }

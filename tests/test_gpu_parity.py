@@ -154,7 +154,7 @@ def _rel(a, b):
     return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
 
 
-@pytest.mark.parametrize("with_fir,tb", [(False, 1), (True, 1), (False, 8), (True, 4), (True, 16)])
+@pytest.mark.parametrize("with_fir,tb", [(False, 1), (True, 1), (False, 8), (True, 4), (True, 16), (True, 10), (True, 32)])
 def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir, tb):
     """P_{n-1} through FFT -> spectral MAC -> inverse FFT (+ local and FIR terms) against the
     direct sum, random history over all ell lags, heterogeneous eps."""
@@ -183,14 +183,21 @@ def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir, tb):
 
 
 # ----------------------------------------------------------------------------- march
-@pytest.mark.parametrize("tb", [1, 4, 8, 16, 32])
-def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb):
-    """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8, with and without
-    time blocking of the history sum."""
+@pytest.mark.parametrize("tb,ob", [(1, 0), (4, 0), (8, 0), (10, 0), (12, 0), (14, 0), (16, 0), (32, 0),
+                                   (8, 16), (4, 12), (4, 8), (-1, 0)])
+def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb, ob):
+    """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8, without time
+    blocking of the history sum, with two levels (blocks of tb steps) and with three (outer
+    blocks of ob steps split into blocks of tb)."""
     torch = torch_cuda
-    say("march C1 time_block=%d" % tb)
+    say("march C1 time_block=%d outer_block=%d" % (tb, ob))
     prob, o, Jref = c1_oracle
-    s = make_solver(prob, time_block=tb)
+    s = make_solver(prob, time_block=tb, outer_block=ob)
+    if tb < 0:
+        info = s.info()
+        say("  timed choice: time block %d, outer block %d" % (info["time_block"], info["outer_block"]))
+        assert (info["time_block"], info["outer_block"]) in ((8, 0), (12, 0), (16, 0), (4, 8), (4, 12), (4, 16),
+                                                             (8, 16))
     Jt = torch.zeros((prob.n_steps, 1, 3, 8, 8, 8), dtype=torch.float64, device="cuda")
     s.run(prob.n_steps, Jt)
     torch.cuda.synchronize()
@@ -202,21 +209,21 @@ def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb):
     s.close()
 
 
-@pytest.mark.parametrize("tb", [1, 4, 8, 16])
-def test_march_short_support(torch_cuda, tb):
+@pytest.mark.parametrize("tb,ob", [(1, 0), (4, 0), (8, 0), (16, 0), (4, 8), (8, 16)])
+def test_march_short_support(torch_cuda, tb, ob):
     """4 x 3 x 3 heterogeneous block with a 3-tap FIR: the kernel support (ell = 6 lags) is
     shorter than the time block, so the near part must stop at the last lag."""
     from oracle import mot
     torch = torch_cuda
     U, V, W, n = 4, 3, 3, 60
-    say("march 4x3x3 time_block=%d" % tb)
+    say("march 4x3x3 time_block=%d outer_block=%d" % (tb, ob))
     eps = wl.random_eps(U, V, W, 17, 2.0, 10.0)
     k, p = wl.XPOL_PLUS_Z
     prob = wl.Problem("short", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 3.0)], n,
                       fir=wl.binomial_highpass(3, 0.1))
     K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
     ref = mot.Oracle(prob, K=K).run(n)
-    s = make_solver(prob, time_block=tb)
+    s = make_solver(prob, time_block=tb, outer_block=ob)
     assert s.ell < 8
     Jt = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
     s.run(n, Jt)
@@ -235,19 +242,19 @@ def _three_waves(U, V, W):
     return [wl.gaussian_wave(U, V, W, np.array(d), np.array(q), s_) for d, q, s_ in zip(dirs, pols, sig)]
 
 
-@pytest.mark.parametrize("tb", [1, 8, 16])
-def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb):
+@pytest.mark.parametrize("tb,ob", [(1, 0), (8, 0), (16, 0), (8, 16)])
+def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob):
     """Three right-hand sides marched together: each equals its own single-RHS march (the
     per-RHS arithmetic is the same, so to rounding) and the oracle's march."""
     from oracle import mot
     torch = torch_cuda
     U, V, W, n = 6, 5, 4, 60
-    say("batched rhs 6x5x4 time_block=%d" % tb)
+    say("batched rhs 6x5x4 time_block=%d outer_block=%d" % (tb, ob))
     eps = wl.random_eps(U, V, W, 5, 1.0, 8.0)
     waves = _three_waves(U, V, W)
     fir = wl.binomial_highpass(5, 0.1)
     prob = wl.Problem("batch", U, V, W, eps, waves, n, fir=fir)
-    s = make_solver(prob, time_block=tb)
+    s = make_solver(prob, time_block=tb, outer_block=ob)
     Jb = torch.zeros((n, 3, 3, W, V, U), dtype=torch.float64, device="cuda")
     s.run(n, Jb)
     torch.cuda.synchronize()
@@ -256,7 +263,7 @@ def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb):
     K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
     for i, w in enumerate(waves):
         p1 = wl.Problem("single", U, V, W, eps, [w], n, fir=fir)
-        s1 = make_solver(p1, time_block=tb)
+        s1 = make_solver(p1, time_block=tb, outer_block=ob)
         J1 = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
         s1.run(n, J1)
         torch.cuda.synchronize()
@@ -534,14 +541,14 @@ def adjoint_oracle():
     return prob, probes, phi, grad
 
 
-@pytest.mark.parametrize("tb,ckpt", [(1, 0), (1, 9), (8, 0), (8, 9), (16, 5)])
-def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt):
+@pytest.mark.parametrize("tb,ckpt,ob", [(1, 0, 0), (1, 9, 0), (8, 0, 0), (8, 9, 0), (16, 5, 0), (8, 9, 16), (4, 0, 8)])
+def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt, ob):
     """Phi and dPhi/deps_r of every voxel (one with eps_r = 1) from the transposed march,
     with and without checkpoint/recompute segments, against the oracle's direct adjoint."""
     torch = torch_cuda
     prob, probes, phi_ref, grad_ref = adjoint_oracle
-    say("adjoint 5x4x3 time_block=%d ckpt_every=%d" % (tb, ckpt))
-    s = make_solver(prob, time_block=tb)
+    say("adjoint 5x4x3 time_block=%d ckpt_every=%d outer_block=%d" % (tb, ckpt, ob))
+    s = make_solver(prob, time_block=tb, outer_block=ob)
     s.set_probes(probes)
     g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
     phi = s.adjoint_gradient(prob.n_steps, g, ckpt)
@@ -1074,15 +1081,15 @@ def test_prism_voxel_march_probes_and_gradient_match_oracle(torch_cuda):
 
 
 # ----------------------------------------------------------------------------- checkpoint / resume
-@pytest.mark.parametrize("tb,with_probes", [(8, True), (1, False), (16, False)])
-def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes):
+@pytest.mark.parametrize("tb,with_probes,ob", [(8, True, 0), (1, False, 0), (16, False, 0), (8, True, 16)])
+def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes, ob):
     """mj_get_state after 37 steps (inside a time block), mj_set_state on a fresh solver of the
     same configuration: the next 53 steps repeat the uninterrupted march bit for bit (currents
     and probe field).  A state from another time block or a cut buffer is refused."""
     from paper_2407_03323_amd.motjvie import MJ_EINVAL, MotJvieError
     torch = torch_cuda
     U, V, W, n1, N = 6, 5, 4, 37, 90
-    say("checkpoint/resume tb=%d probes=%s" % (tb, with_probes))
+    say("checkpoint/resume tb=%d probes=%s outer=%d" % (tb, with_probes, ob))
     eps = wl.random_eps(U, V, W, 41, 2.0, 9.0)
     k, p = wl.XPOL_PLUS_Z
     prob = wl.Problem("resume", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], N,
@@ -1090,8 +1097,8 @@ def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes):
     probes = wl.fibonacci_sphere(3, 5.0, (U / 2, V / 2, W / 2))
     npb = len(probes) if with_probes else 0
 
-    def solver(tb_=tb):
-        s_ = make_solver(prob, time_block=tb_)
+    def solver(tb_=tb, ob_=ob):
+        s_ = make_solver(prob, time_block=tb_, outer_block=ob_)
         if with_probes:
             s_.set_probes(probes)
         return s_
@@ -1118,7 +1125,7 @@ def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes):
         s.set_state(state[:-8])
     assert ei.value.code == MJ_EINVAL
     s.close()
-    other = solver(4 if tb != 4 else 8)
+    other = solver(4 if tb != 4 else 8, 0)
     with pytest.raises(MotJvieError) as ei:
         other.set_state(state)
     assert ei.value.code == MJ_EINVAL
@@ -1320,3 +1327,29 @@ def test_step_and_thinned_march_repeat_run(torch_cuda, tb):
     assert torch.equal(Jt, J[6::7][: n // 7]) and torch.equal(Pt, P)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("tb,ob", [(12, 0), (16, 0), (8, 16)])
+def test_time_levels_agree_at_full_size(torch_cuda, tb, ob):
+    """At 104^3 (ell = 182, the configuration bench.py times), marches with other time blocks
+    (two levels of 12 or 16 steps) and with three levels (outer blocks of 16 split into 8) give
+    the currents of the two-level march with blocks of 8 to rounding: the time division only
+    regroups the terms of eq:PnMOT.  60 steps after a prefill of 190."""
+    torch = torch_cuda
+    p = wl.config("C5")
+    out = []
+    for (b, o) in ((8, 0), (tb, ob)):
+        say("104^3 time_block=%d outer_block=%d" % (b, o))
+        s = make_solver(p, time_block=b, outer_block=o)
+        s.run(190)
+        J = torch.zeros((6, 1, 3, p.W, p.V, p.U), dtype=torch.float64, device="cuda")
+        s.run(60, J, j_every=10)
+        torch.cuda.synchronize()
+        out.append(J)
+        st = s.stats()
+        say("  far launch %.3f ms (%d), middle %.3f ms, near %.3f ms, MAC %.3f ms/step" % (
+            st["far_launch_ms"], st["far_launches"], st["mid_launch_ms"], st["near_launch_ms"], st["mac_ms"]))
+        s.close()
+    err = float((out[0] - out[1]).norm() / out[0].norm())
+    say("  rel L2 against blocks of 8: %.3e" % err)
+    assert err <= 1e-11
