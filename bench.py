@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched (C3) and adjoint (C4) ratios")
     ap.add_argument("--time-block", type=int, default=0, help="steps per time block (0 = library default)")
     ap.add_argument("--outer-block", type=int, default=0, help="steps per outer time block (three levels; 0 = two)")
+    ap.add_argument("--z0-solver", type=int, default=0, help="0 by size, 1 CG, 2 Chebyshev")
+    ap.add_argument("--z0-graphs", type=int, default=0, help="replay the Chebyshev batches from HIP graphs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -206,7 +208,8 @@ def main():
 
     prob = wl.config(args.workload)
     t_setup = time.perf_counter()
-    solver = motjvie.solver_for(prob, time_block=args.time_block, outer_block=args.outer_block)
+    solver = motjvie.solver_for(prob, time_block=args.time_block, outer_block=args.outer_block,
+                                z0_solver=args.z0_solver, z0_graphs=args.z0_graphs)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     info = solver.info()
@@ -313,6 +316,7 @@ def main():
                    "phase_ms": {k: round(st[k], 4) for k in ("fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms",
                                                               "z0_ms")},
                    "cg_iters": round(st["cg_iters"], 2), "time_block": B, "outer_block": B2,
+                   "z0_solver": "CG" if info["z0_solver"] == 1 else "Chebyshev",
                    "mid_launch_ms": round(st["mid_launch_ms"], 4),
                    "fft_pencils": [info["fft_pencils_x"], info["fft_pencils_y"], info["fft_pencils_z"]],
                    "far_launch_ms": round(st["far_launch_ms"], 4), "near_launch_ms": round(st["near_launch_ms"], 4)},

@@ -93,6 +93,15 @@ typedef struct {
     int32_t outer_block;      /* a third level of the time division (Sec. 4.1 applied twice): steps per
                                  outer block, a multiple of time_block (which must then be 4 or 8), even,
                                  in 8 .. 16.  0 or 1: two levels (or the default, see time_block) */
+    int32_t z0_solver;        /* the Z_0 solve (eq:MOTInversion) on the symmetrised Z_0 with the Jacobi
+                                 preconditioner: 1 CG; 2 Chebyshev iteration on its spectrum, estimated at
+                                 mj_create and mj_set_eps (one stencil pass per iteration and no inner
+                                 products: fewer launches, more iterations); 0 Chebyshev up to 2^19 voxels
+                                 x right-hand sides, CG above.  Both stop at cg_rtol; cg_maxit bounds
+                                 their iterations */
+    int32_t z0_graphs;        /* != 0: the Chebyshev passes of a solve (whose arguments depend only on the
+                                 pass index) are captured once per batch shape as HIP graphs and replayed
+                                 on `stream` in later steps; 0: launched one by one */
 } mj_config;
 
 /*
@@ -112,13 +121,15 @@ void mj_destroy(mj_solver *s);
 const char *mj_last_error(const mj_solver *s);
 
 /*
- * mj_info -- sizes of the solver.  out (host, n entries used, n <= 20):
+ * mj_info -- sizes of the solver.  out (host, n entries used, n <= 23):
  *   [0] ell  [1] Nx [2] Ny [3] Nz (padded FFT sizes)  [4] time block B
  *   [5] history depth kept in real space  [6] n_rhs  [7] current step n
  *   [8] device bytes allocated  [9] kernel generation time (ms)  [10] spectra time (ms)
  *   [11] number of FIR taps  [12] probes  [13] lag window per probe pair
  *   [14] probe pairs  [15] probe kernel generation time (ms)
  *   [16] [17] [18] pencils per block of the x, y and z FFT passes  [19] outer time block (0: none)
+ *   [20] Z_0 solver in use (0 Chebyshev, 1 CG)  [21] [22] the bounds of the eigenvalues of the
+ *   Jacobi-preconditioned symmetrised Z_0 that the Chebyshev solve uses (0: not estimated)
  */
 int mj_info(const mj_solver *s, double *out, int32_t n);
 

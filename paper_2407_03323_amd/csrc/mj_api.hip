@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -18,6 +19,9 @@ using mj::UnstableError;
 namespace {
 
 thread_local std::string g_err;
+
+// voxels x right-hand sides up to which z0_solver = 0 takes the Chebyshev solve
+constexpr long kChebMaxUnknowns = 1L << 19;
 
 // ---------------------------------------------------------------------------- static staging
 // mj_kernel_values_noalloc stages its requests and results through this file-scope array
@@ -114,6 +118,16 @@ struct mj_solver {
     double *parts = nullptr;
     mj::CgScalars *scal = nullptr;
     int cg_guess = 8;
+    // Z_0 solver: 0 Chebyshev iteration (needs spectral bounds of M^-1 A), 1 CG
+    int z0_method = 0;
+    double lam_lo = 0.0, lam_hi = 0.0;   // bounds of the eigenvalues of M^-1 A (0: not estimated)
+    double *e2 = nullptr;                // second buffer of s d for the Chebyshev passes (haloed)
+    int cheb_pred = 0;                   // passes predicted for the next solve (0: none yet)
+    std::vector<double> cheb_rho;        // Chebyshev recurrence scalars by pass index (for lam_lo, lam_hi)
+    bool use_graphs = false;             // replay the Chebyshev batches from captured HIP graphs
+    hipStream_t cap_st = nullptr;        // the library's own stream, for capturing (never the null stream)
+    std::map<long, hipGraphExec_t> cheb_graphs;   // captured batches by (with init, first pass, passes)
+    double cheb_rho2 = 0.0;              // observed reduction of |r|^2 per pass
     mj::CgStatus *cgstat = nullptr, *cgstat_h = nullptr;
     mj::WaveArg *waves_d = nullptr;
     bool waves_set = false;
@@ -157,6 +171,8 @@ struct mj_solver {
     ~mj_solver()
     {
         if (st) (void)hipStreamSynchronize(st);
+        clear_graphs();
+        if (cap_st) (void)hipStreamDestroy(cap_st);
         mj::fft3d_free(fft);
         da.put(gen.moments);
         for (void *a : allocs) da.put(a);
@@ -229,6 +245,14 @@ struct mj_solver {
     void set_probes(int n_probes, const double *pos);
     void offgrid_values(int n, const int *probe, const int *vox, const int *lag, double *out);
     void solve_z0();
+    mj::CgArg cg_arg() const;
+    void solve_z0_chebyshev();
+    void estimate_spectrum();
+    void clear_graphs()
+    {
+        for (auto &kv : cheb_graphs) (void)hipGraphExecDestroy(kv.second);
+        cheb_graphs.clear();
+    }
     void history_sum(const double *Jh, int depth, double *P);
 };
 
@@ -252,6 +276,8 @@ void mj_solver::create(const mj_config &c)
     if (c.n_rhs < 1 || c.n_rhs > 64) throw ArgError("n_rhs must be in [1, 64]");
     if (c.fft_pencils < 0) throw ArgError("fft_pencils must be >= 0 (0: autotune)");
     if ((c.alloc == nullptr) != (c.free_ == nullptr)) throw ArgError("alloc and free_ are given together or not at all");
+    if (c.z0_solver < 0 || c.z0_solver > 2) throw ArgError("z0_solver must be 0 (by size), 1 (CG) or 2 (Chebyshev)");
+    use_graphs = c.z0_graphs != 0;
     da.fn_alloc = c.alloc;
     da.fn_free = c.free_;
     da.ctx = c.alloc_ctx;
@@ -296,7 +322,12 @@ void mj_solver::create(const mj_config &c)
     nloc = std::max(guess_deg + 1, (int)fir.size() - 1);   // the initial guess uses guess_deg + 1 steps
     rdepth = nloc + 1;
 
+    // the Z_0 solve: Chebyshev passes cost one launch each against four per CG iteration, which
+    // decides on small grids; on large ones CG's fewer iterations win (104^3: 12.9 CG iterations,
+    // 1.02 ms, against 24 passes, 1.16 ms; 32^3: 0.48 against 0.20 ms)
+    z0_method = c.z0_solver == 1 ? 1 : c.z0_solver == 2 ? 0 : ((long)nrhs * M <= kChebMaxUnknowns ? 0 : 1);
     MJ_CHECK(hipGetDevice(&dev));
+    if (use_graphs) MJ_CHECK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
     (void)scratch_ptr(dev);   // this device's staging array (mj_kernel_values_noalloc)
     chi = dalloc<double>(M, "chi");
     schi = dalloc<double>(M, "sqrt chi");
@@ -328,9 +359,11 @@ void mj_solver::create(const mj_config &c)
     const size_t Mp = (size_t)(U + 2) * (V + 2) * (W + 2);
     u = dalloc<double>((size_t)nrhs * 3 * Mp, "cg u");
     uy = dalloc<double>((size_t)nrhs * 3 * Mp, "cg uy");
-    // the one-voxel halo of u and uy is never written and stays zero
+    e2 = dalloc<double>((size_t)nrhs * 3 * Mp, "chebyshev direction");
+    // the one-voxel halo of u, uy and e2 is never written and stays zero
     MJ_CHECK(hipMemset(u, 0, sizeof(double) * nrhs * 3 * Mp));
     MJ_CHECK(hipMemset(uy, 0, sizeof(double) * nrhs * 3 * Mp));
+    MJ_CHECK(hipMemset(e2, 0, sizeof(double) * nrhs * 3 * Mp));
     nblk = (int)((M + 255) / 256);
     parts = dalloc<double>((size_t)3 * nrhs * nblk, "cg partials");
     scal = dalloc<mj::CgScalars>(nrhs, "cg scalars");
@@ -342,6 +375,7 @@ void mj_solver::create(const mj_config &c)
     if (c.fft_pencils > 0) mj::fft3d_set_pencils(fft, c.fft_pencils);
     else mj::fft3d_autotune(fft, st);
     if (tune_mac) mac_autotune();
+    if (z0_method == 0) estimate_spectrum();
     n = 0;
     MJ_CHECK(hipStreamSynchronize(st));
 }
@@ -444,7 +478,7 @@ void mj_solver::build_spectra()
     t_spec_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
 }
 
-void mj_solver::solve_z0()
+mj::CgArg mj_solver::cg_arg() const
 {
     mj::CgArg a{};
     a.M = M;
@@ -467,6 +501,16 @@ void mj_solver::solve_z0()
     a.part = parts;
     a.scal = scal;
     a.stat = cgstat;
+    return a;
+}
+
+void mj_solver::solve_z0()
+{
+    if (z0_method == 0 && lam_hi > 0.0) {
+        solve_z0_chebyshev();
+        return;
+    }
+    mj::CgArg a = cg_arg();
     mj::launch_cg_init(a, st);   // also clears the status records
     // enqueue as many iterations as the last solve needed before the first look at the
     // convergence flags; kernels after convergence return at once
@@ -490,6 +534,220 @@ void mj_solver::solve_z0()
     int mx = 0;
     for (int i = 0; i < nrhs; i++) mx = std::max(mx, cgstat_h[i].iters);
     cg_guess = mx + 1;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix (diagonal a, off-diagonal
+// b, b[0] unused): the Sturm count of the LDL^T pivots.
+static int sturm_count(const std::vector<double> &a, const std::vector<double> &b, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t j = 0; j < a.size(); j++) {
+        const double off = j ? b[j] * b[j] / q : 0.0;
+        q = a[j] - x - off;
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) cnt++;
+    }
+    return cnt;
+}
+
+// Extreme eigenvalues of M^-1 A (M the Jacobi preconditioner) for the Chebyshev solve: a CG run
+// on a pseudo-random right-hand side is a Lanczos process, whose tridiagonal matrix
+// T (T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j) has extreme
+// eigenvalues that approach those of M^-1 A from inside; bisection on its Sturm counts gives
+// them.  The bounds used are widened by 10 % below and 5 % above.  A spectrum with nothing in
+// it (no voxel with eps != 1) leaves the bounds at 0, which selects the CG solve.
+void mj_solver::estimate_spectrum()
+{
+    lam_lo = lam_hi = 0.0;
+    cheb_rho.clear();   // the recurrence scalars and the captured batches hold the old bounds
+    clear_graphs();
+    mj::CgArg a = cg_arg();
+    a.nrhs = 1;
+    a.tol2 = 0.0;   // run every iteration
+    const size_t Mp = (size_t)(U + 2) * (V + 2) * (W + 2);
+    MJ_CHECK(hipMemsetAsync(uy, 0, sizeof(double) * Mp * 3, st));
+    mj::launch_fill_trial(schi, M, 1, rhs, y, st);
+    mj::launch_cg_init(a, st);
+    std::vector<double> alpha, beta;
+    mj::CgScalars sc{};
+    MJ_CHECK(hipMemcpyAsync(&sc, scal, sizeof sc, hipMemcpyDeviceToHost, st));
+    MJ_CHECK(hipStreamSynchronize(st));
+    const double rz0 = sc.rz[0];
+    if (!(rz0 > 0.0) || !std::isfinite(rz0)) {
+        restart();
+        return;
+    }
+    const int m = std::min(40, 3 * (int)std::min<long>(M, 1000));
+    for (int it = 0; it < m; it++) {
+        mj::launch_cg_a(a, it, st);
+        mj::launch_cg_b(a, it, st);
+        MJ_CHECK(hipMemcpyAsync(&sc, scal, sizeof sc, hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipStreamSynchronize(st));
+        const double rz = sc.rz[it & 1], rzn = sc.rz[(it + 1) & 1], pq = sc.pq;
+        if (!(pq > 0.0) || !std::isfinite(pq) || !(rz > 0.0)) break;
+        alpha.push_back(rz / pq);
+        beta.push_back(rzn / rz);
+        // the Krylov space is exhausted (tiny grids): the residual has vanished
+        if (!(rzn > 1e-28 * rz0)) break;
+    }
+    restart();
+    const size_t k = alpha.size();
+    if (k == 0) return;
+    std::vector<double> d(k), e(k, 0.0);
+    for (size_t j = 0; j < k; j++) {
+        d[j] = 1.0 / alpha[j] + (j ? beta[j - 1] / alpha[j - 1] : 0.0);
+        if (j) e[j] = std::sqrt(beta[j - 1]) / alpha[j - 1];
+    }
+    double lo = 1e300, hi = -1e300;
+    for (size_t j = 0; j < k; j++) {   // Gershgorin interval of T
+        const double rad = (j ? std::fabs(e[j]) : 0.0) + (j + 1 < k ? std::fabs(e[j + 1]) : 0.0);
+        lo = std::min(lo, d[j] - rad);
+        hi = std::max(hi, d[j] + rad);
+    }
+    auto kth = [&](int idx) {   // eigenvalue number idx (0-based, ascending) by bisection
+        double l = lo, h = hi;
+        for (int b = 0; b < 200 && h - l > 1e-14 * std::max(1.0, std::fabs(h)); b++) {
+            const double mid = 0.5 * (l + h);
+            if (sturm_count(d, e, mid) > idx) h = mid;
+            else l = mid;
+        }
+        return 0.5 * (l + h);
+    };
+    const double emin = kth(0), emax = kth((int)k - 1);
+    if (!(emin > 0.0) || !(emax >= emin)) return;
+    lam_lo = 0.9 * emin;
+    lam_hi = 1.05 * emax;
+}
+
+// The Z_0 solve by Chebyshev iteration (k_cheb_*): one stencil pass per iteration and no inner
+// products, so no reductions inside the iteration.  The passes of a solve are enqueued in
+// batches; only the last pass of a batch computes |r|^2, and the host reads the outcome once per
+// batch.  The first batch has as many passes as the last solve needed, from its observed
+// reduction per pass and its initial residual; without a last solve, the host first reads
+// |r_0| / |b| and uses the convergence factor of the Chebyshev polynomials for the estimated
+// spectrum.
+void mj_solver::solve_z0_chebyshev()
+{
+    mj::ChebArg a{};
+    a.cg = cg_arg();
+    a.r = q;
+    const double theta = 0.5 * (lam_hi + lam_lo), delta = 0.5 * (lam_hi - lam_lo);
+    a.inv_theta = 1.0 / theta;
+    double *ebuf[2] = {u, e2};
+    const double kappa = lam_hi / lam_lo;
+    const double rho_th = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
+    const double tol2 = cg_rtol * cg_rtol;
+    // the recurrence scalars by pass index: rho_0 = delta / theta, rho_{k+1} = 1 / (2 theta / delta - rho_k)
+    if ((int)cheb_rho.size() < cg_maxit + 1) {
+        cheb_rho.assign((size_t)cg_maxit + 1, 0.0);
+        cheb_rho[0] = delta / theta;
+        for (int k = 0; k < cg_maxit; k++) cheb_rho[(size_t)k + 1] = 1.0 / (2.0 * theta / delta - cheb_rho[(size_t)k]);
+    }
+    // the kernels of one batch: (the initial residual and) passes T .. T + K - 1, the last with the
+    // check; their arguments depend only on (T, K), so a captured batch replays unchanged
+    auto launch_batch = [&](bool with_init, int T, int K, hipStream_t s_) {
+        if (with_init) {
+            a.e_out = ebuf[0];
+            a.passes = 0;
+            mj::launch_cheb_init(a, s_);
+        }
+        for (int j = 0; j < K; j++) {
+            const int k = T + j;
+            a.c1 = cheb_rho[(size_t)k + 1] * cheb_rho[(size_t)k];
+            a.c2 = 2.0 * cheb_rho[(size_t)k + 1] / delta;
+            a.e_in = ebuf[k & 1];
+            a.e_out = ebuf[(k + 1) & 1];
+            a.want_norm = j == K - 1;
+            a.passes = k + 1;
+            mj::launch_cheb_pass(a, s_);
+        }
+    };
+    auto enqueue = [&](bool with_init, int T, int K) {
+        if (!use_graphs) {
+            launch_batch(with_init, T, K, st);
+            return;
+        }
+        const long key = ((long)with_init << 40) | ((long)T << 20) | K;
+        auto it = cheb_graphs.find(key);
+        if (it == cheb_graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
+            MJ_CHECK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
+            try {
+                launch_batch(with_init, T, K, cap_st);
+            } catch (...) {
+                (void)hipStreamEndCapture(cap_st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            MJ_CHECK(hipStreamEndCapture(cap_st, &g));
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            MJ_CHECK(e);
+            it = cheb_graphs.emplace(key, ex).first;
+        }
+        MJ_CHECK(hipGraphLaunch(it->second, st));
+    };
+    // passes to bring |r|^2 from rr to tol^2 bb at a reduction rho2 per pass
+    auto passes_for = [&](double rr, double bb, double rho2) {
+        if (!(rr > tol2 * bb) || !(bb > 0.0)) return 0;
+        const double k = std::log(tol2 * bb / rr) / std::log(rho2);
+        return (int)std::ceil(std::max(1.0, k));
+    };
+    auto read_status = [&] {
+        MJ_CHECK(hipMemcpyAsync(cgstat_h, cgstat, sizeof(mj::CgStatus) * nrhs, hipMemcpyDeviceToHost, st));
+        MJ_CHECK(hipStreamSynchronize(st));
+        bool done = true;
+        for (int i = 0; i < nrhs; i++) done = done && cgstat_h[i].done;
+        return done;
+    };
+    int K = std::min(cheb_pred, cg_maxit);
+    int total = 0;
+    bool done = false;
+    if (K <= 0) {
+        // no last solve: read |r_0| / |b| first, and use the Chebyshev polynomials' convergence factor
+        enqueue(true, 0, 0);
+        if (read_status()) return;
+        K = 0;
+        for (int i = 0; i < nrhs; i++)
+            K = std::max(K, passes_for(cgstat_h[i].rr0, cgstat_h[i].bb, rho_th * rho_th) + 1);
+        K = std::max(1, std::min(K, cg_maxit));
+        enqueue(false, 0, K);
+    } else {
+        enqueue(true, 0, K);
+    }
+    total = K;
+    done = read_status();
+    while (!done && total < cg_maxit) {
+        // more passes, from the residual reached and the reduction seen so far
+        K = 1;
+        for (int i = 0; i < nrhs; i++) {
+            const mj::CgStatus &c = cgstat_h[i];
+            if (c.done) continue;
+            const double rr = c.res * c.res * c.bb;
+            double rho2 = rho_th * rho_th;
+            if (c.rr0 > 0.0 && rr > 0.0 && rr < c.rr0) rho2 = std::max(rho2, std::pow(rr / c.rr0, 1.0 / total));
+            if (!(rho2 < 1.0)) rho2 = 0.9;
+            K = std::max(K, passes_for(rr, c.bb, rho2) + 1);
+        }
+        K = std::min(K, cg_maxit - total);
+        enqueue(false, total, K);
+        total += K;
+        done = read_status();
+    }
+    // the next solve starts with the passes this one would have needed: its observed reduction
+    // per pass applied to its initial residual
+    int pred = 1;
+    for (int i = 0; i < nrhs; i++) {
+        const mj::CgStatus &c = cgstat_h[i];
+        const double rr = c.res * c.res * c.bb;
+        double rho2 = rho_th * rho_th;
+        if (c.rr0 > 0.0 && rr > 0.0 && rr < c.rr0 && total > 0) rho2 = std::max(rho2 * 0.25, std::pow(rr / c.rr0, 1.0 / total));
+        if (!(rho2 < 1.0)) rho2 = 0.9;
+        pred = std::max(pred, passes_for(c.rr0, c.bb, rho2));
+    }
+    cheb_pred = pred;
 }
 
 // 8-point Gauss-Legendre on [-1/2, 1/2] (weights summing to 1), long double Newton
@@ -869,8 +1127,13 @@ void mj_solver::restart()
     MJ_CHECK(hipMemsetAsync(p, 0, v, st));
     MJ_CHECK(hipMemsetAsync(q, 0, v, st));
     MJ_CHECK(hipMemsetAsync(y, 0, v, st));
+    // the Chebyshev directions: voxels whose eps changed to 1 must read as zero in the stencil
+    const size_t vp = sizeof(double) * (size_t)nrhs * 3 * (U + 2) * (V + 2) * (W + 2);
+    MJ_CHECK(hipMemsetAsync(u, 0, vp, st));
+    MJ_CHECK(hipMemsetAsync(e2, 0, vp, st));
     MJ_CHECK(hipStreamSynchronize(st));
     cg_guess = 8;
+    cheb_pred = 0;
     n = 0;
 }
 
@@ -1123,7 +1386,7 @@ void mj_solver::offgrid_values(int cnt, const int *probe, const int *vox3, const
 namespace {
 struct StateHeader {
     char magic[8];
-    int32_t version, U, V, W, nrhs, ell, B, rdepth, Nx, Ny, Nz, Hp, B2, pad_;
+    int32_t version, U, V, W, nrhs, ell, B, rdepth, Nx, Ny, Nz, Hp, B2, cheb_pred;
     int64_t n, ring_bytes, far_bytes, jr_bytes, outer_bytes;
 };
 constexpr char kStateMagic[8] = {'M', 'J', 'S', 'T', 'A', 'T', 'E', '2'};
@@ -1155,6 +1418,7 @@ void mj_solver::get_state(void *buf) const
     h.Nz = Nz;
     h.Hp = Hp;
     h.B2 = B2;
+    h.cheb_pred = cheb_pred;   // the next Z_0 solve's first batch of passes (part of its arithmetic)
     h.n = n;
     h.ring_bytes = (int64_t)(sizeof(double2) * (size_t)ell * v3 * sp);
     h.far_bytes = farbuf ? (int64_t)(sizeof(double2) * (size_t)B * v3 * sp) : 0;
@@ -1197,6 +1461,7 @@ void mj_solver::set_state(const void *buf, size_t bytes)
     p += h.jr_bytes;
     if (h.outer_bytes) MJ_CHECK(hipMemcpy(gbuf, p, (size_t)h.outer_bytes, hipMemcpyHostToDevice));
     n = (int)h.n;
+    cheb_pred = std::max(0, (int)h.cheb_pred);
 }
 
 // Gradient of Phi = sum_{n=1}^{N} sum_r sum_p |E^s_{r,p}(n)|^2 with respect to eps_r of every
@@ -1261,6 +1526,8 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
     double *nu_r = (double *)talloc(sizeof(double) * (size_t)rdepth * vec, "adjoint history");
     double *lam_r = (double *)talloc(sizeof(double) * (size_t)rdepth * vec, "adjoint local history");
     MJ_CHECK(hipMemsetAsync(grad_dev, 0, sizeof(double) * M, st));
+    std::vector<int> pred_at((size_t)N + 2, 0);
+    int adj_pred = 0;
     double2 *const ring_f = ring, *const far_f = farbuf, *const g_f = gbuf;
     double *const Jr_f = Jr;
     hipEvent_t tev[3];
@@ -1272,9 +1539,11 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             if (!cgstat_h[i].done) noconv = true;
     };
     try {
-        // 1. forward
+        // 1. forward; the Chebyshev prediction each step starts from is kept, so that a
+        // recomputed segment takes the same passes as the original steps
         const int last0 = starts[C - 1];
         for (int t = 1; t <= N; t++) {
+            pred_at[(size_t)t] = cheb_pred;
             StepIO io;
             io.Pout = Ehist + (size_t)(t - 1) * nrhs * np * 3;
             io.Bout = t >= last0 ? Bbuf + (size_t)(t - last0) * vec : nullptr;
@@ -1312,6 +1581,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
                             mj::fft3d_forward(fft, src, ring + (size_t)slotS(j) * nrhs * 3 * sp, 3 * nrhs, st);
                     }
                 }
+                cheb_pred = pred_at[(size_t)s0];
                 for (int t = s0; t <= s1; t++) {
                     StepIO io;
                     io.skip_probes = true;
@@ -1328,6 +1598,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             Lr = lam_r;
             bq = bqb;
             n = n_adj;
+            cheb_pred = adj_pred;
             for (int j = s1; j >= s0; j--) {
                 mj::AdjArg a = adj_arg();
                 a.Ehist = Ehist;
@@ -1344,6 +1615,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
                 check_cg();
             }
             n_adj = n;
+            adj_pred = cheb_pred;
             ring = ring_f;
             farbuf = far_f;
             gbuf = g_f;
@@ -1438,11 +1710,12 @@ const char *mj_last_error(const mj_solver *s) { return s ? s->err.c_str() : g_er
 int mj_info(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    double v[20] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
+    double v[23] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
                     (double)s->rdepth, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
                     s->t_spec_ms, (double)s->fir.size(), (double)s->np, (double)s->nw, (double)s->npairs,
-                    s->t_probe_ms, (double)s->fft.Px, (double)s->fft.Py, (double)s->fft.Pz, (double)s->B2};
-    for (int i = 0; i < n && i < 20; i++) out[i] = v[i];
+                    s->t_probe_ms, (double)s->fft.Px, (double)s->fft.Py, (double)s->fft.Pz, (double)s->B2,
+                    (double)s->z0_method, s->lam_lo, s->lam_hi};
+    for (int i = 0; i < n && i < 23; i++) out[i] = v[i];
     return MJ_OK;
 }
 
@@ -1511,6 +1784,7 @@ int mj_set_eps(mj_solver *s, const double *eps_r)
         if (s->n != 0) throw std::logic_error("eps is changed at n = 0 (after mj_create or mj_reset)");
         s->set_material(eps_r);
         s->restart();
+        if (s->z0_method == 0) s->estimate_spectrum();
     });
 }
 

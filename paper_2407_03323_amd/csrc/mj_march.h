@@ -98,6 +98,7 @@ struct CgStatus {
     int iters;               // iterations taken
     double res;              // relative residual |r| / |b| at the last test
     double bb;               // |b|^2 of the solve's right-hand side (growth detector)
+    double rr0;              // |r_0|^2 of the initial guess (Chebyshev solve)
 };
 
 struct CgArg {
@@ -114,6 +115,25 @@ struct CgArg {
     CgScalars *scal;         // [nrhs]
     CgStatus *stat;          // [nrhs]
 };
+
+// Chebyshev iteration on the symmetrised Z_0 system with the Jacobi preconditioner M (see
+// mj_march.hip): no inner products, one stencil pass per iteration.
+struct ChebArg {
+    CgArg cg;                // geometry, sqrt(chi), rhs, uy = s y0, y, partial sums, status, tol2
+    double *r;               // residual [nrhs][3][M]
+    const double *e_in;      // s d_k in the zero-haloed layout [nrhs][3][Mp]
+    double *e_out;           // s d_{k+1}, same layout (the other of two buffers)
+    double c1, c2;           // d_{k+1} = c1 d_k + c2 M^-1 r_{k+1}
+    double inv_theta;        // d_0 = M^-1 r_0 / theta
+    int want_norm;           // the pass writes partial sums of |r|^2 and the check follows it
+    int passes;              // passes done when this one ends (recorded in the status)
+};
+// r_0 = rhs - A y0, e_0 = s M^-1 r_0 / theta; reduces |r_0|^2 and |b|^2 into the status
+void launch_cheb_init(const ChebArg &a, hipStream_t st);
+// one iteration; with want_norm also the convergence check |r|^2 <= tol^2 |b|^2
+void launch_cheb_pass(const ChebArg &a, hipStream_t st);
+// pseudo-random right-hand side (zero where sqrt(chi) = 0) and zero initial guess
+void launch_fill_trial(const double *schi, long M, int nrhs, double *rhs, double *y, hipStream_t st);
 
 // Scattered field at probe points: E^s_p(n) = sum_{k=0}^{ell} sum_s K_k(r_p - r_s) J_{n-k}(s)
 // over the source voxels s of the scatterer.  Pairs (p, s) are stored per probe sorted by the

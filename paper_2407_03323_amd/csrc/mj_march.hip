@@ -806,7 +806,7 @@ __global__ void __launch_bounds__(1024) k_cg_reduce(CgArg a, int it)
     const double rr = sc->rr, bb = sc->bb;
     const bool pass = rr <= a.tol2 * bb || bb == 0.0;
     sc->conv = pass ? iter : INT_MAX;
-    a.stat[r] = CgStatus{pass ? 1 : 0, iter, bb > 0.0 ? sqrt(rr / bb) : 0.0, bb};
+    a.stat[r] = CgStatus{pass ? 1 : 0, iter, bb > 0.0 ? sqrt(rr / bb) : 0.0, bb, 0.0};
 }
 
 // r = rhs - A y0 (uy = s y0), u = s M^-1 r; partials rz, rr, bb
@@ -971,6 +971,157 @@ void launch_cg_finish(const double *y, const double *schi, long M, int nrhs, dou
 {
     hipLaunchKernelGGL(k_cg_finish, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, y, schi, M, nrhs, J, Jout);
     MJ_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------- Chebyshev
+// Chebyshev iteration (the three-term recurrence of Saad, "Iterative Methods for Sparse Linear
+// Systems", Alg. 12.1, with the Jacobi preconditioner) on A y = rhs, for the eigenvalues of
+// M^-1 A in [theta - delta, theta + delta]:
+//   r_0 = rhs - A y_0,  d_0 = M^-1 r_0 / theta,
+//   y_{k+1} = y_k + d_k,  r_{k+1} = r_k - A d_k,  d_{k+1} = c1_k d_k + c2_k M^-1 r_{k+1},
+// with c1_k = rho_{k+1} rho_k, c2_k = 2 rho_{k+1} / delta, rho_0 = delta / theta,
+// rho_{k+1} = 1 / (2 theta / delta - rho_k): scalars that do not depend on the data, so the
+// iteration needs no inner products.  One pass per iteration: A d_k needs d_k at the 26
+// neighbours, so d is kept as e = s d in the zero-haloed stencil layout, in two buffers that
+// the passes alternate.  Voxels with s = 0 stay out (their e is zero and y is zero).
+
+// r_0, e_0 and the partial sums of |r_0|^2 and |b|^2
+__global__ void __launch_bounds__(256) k_cheb_init(ChebArg a)
+{
+    const CgArg &g = a.cg;
+    const CgBlock cb = cg_block();
+    const int r = cb.r;
+    const long M = g.M, base = (long)r * 3 * M;
+    const long i = cb.bx * (long)blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};   // rr, bb
+    if (i < M) {
+        const double s = g.schi[i];
+        const long ip = haloed(g, i), bp = (long)r * 3 * g.Mp;
+        if (s != 0.0) {
+            const double c0 = cg_c0(g, s), md = cg_md(g, s, c0);
+            double Ku[3], ctr[3];
+            stencil_apply(g, g.uy + bp, ip, Ku, ctr);
+            for (int c = 0; c < 3; c++) {
+                const long o = base + c * M + i;
+                const double b = g.rhs[o];
+                const double rv = b - (c0 * g.y[o] - s * Ku[c]);
+                a.r[o] = rv;
+                a.e_out[bp + c * g.Mp + ip] = s * md * rv * a.inv_theta;
+                v[0] += rv * rv;
+                v[1] += b * b;
+            }
+        } else {
+            for (int c = 0; c < 3; c++) {
+                a.r[base + c * M + i] = 0.0;
+                a.e_out[bp + c * g.Mp + ip] = 0.0;
+            }
+        }
+    }
+    block_partials<2>(v, g.part + (size_t)r * 3 * gridDim.x, gridDim.x, cb.bx);
+}
+
+// one iteration: y += d, r -= A d, d' = c1 d + c2 M^-1 r (partial |r|^2 when asked)
+__global__ void __launch_bounds__(256) k_cheb_pass(ChebArg a)
+{
+    const CgArg &g = a.cg;
+    const CgBlock cb = cg_block();
+    const int r = cb.r;
+    const long M = g.M, base = (long)r * 3 * M;
+    const long i = cb.bx * (long)blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < M) {
+        const double s = g.schi[i];
+        if (s != 0.0) {
+            const long ip = haloed(g, i), bp = (long)r * 3 * g.Mp;
+            double Ke[3], ectr[3];
+            stencil_apply(g, a.e_in + bp, ip, Ke, ectr);
+            const double c0 = cg_c0(g, s), md = cg_md(g, s, c0), inv_s = 1.0 / s;
+            for (int c = 0; c < 3; c++) {
+                const long o = base + c * M + i;
+                const double d = ectr[c] * inv_s;
+                g.y[o] += d;
+                const double rv = a.r[o] - (c0 * d - s * Ke[c]);
+                a.r[o] = rv;
+                a.e_out[bp + c * g.Mp + ip] = s * (a.c1 * d + a.c2 * md * rv);
+                v[0] += rv * rv;
+            }
+        }
+    }
+    if (a.want_norm) block_partials<1>(v, g.part + (size_t)r * 3 * gridDim.x, gridDim.x, cb.bx);
+}
+
+// One block per right-hand side adds the partials in block order.  NV = 2 after the init pass
+// (|r_0|^2, |b|^2), NV = 1 after a pass with want_norm (|r|^2): the status records the test.
+template <int NV>
+__global__ void __launch_bounds__(1024) k_cheb_reduce(ChebArg a)
+{
+    __shared__ double sm[16];
+    const CgArg &g = a.cg;
+    const int r = blockIdx.x, nb = g.nblk;
+    const double *pr = g.part + (size_t)r * 3 * nb;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) acc[q] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 1024)
+#pragma unroll
+        for (int q = 0; q < NV; q++) acc[q] += pr[(size_t)q * nb + b];
+#pragma unroll
+    for (int q = 0; q < NV; q++) acc[q] = block_sum(acc[q], sm);
+    if (threadIdx.x != 0) return;
+    CgScalars *sc = g.scal + r;
+    if constexpr (NV == 2) {
+        sc->rr = acc[0];
+        sc->bb = acc[1];
+        sc->rz[0] = acc[0];   // |r_0|^2, kept for the status of the check
+    } else {
+        sc->rr = acc[0];
+    }
+    const double rr = sc->rr, bb = sc->bb;
+    const bool pass = rr <= g.tol2 * bb || bb == 0.0;
+    g.stat[r] = CgStatus{pass ? 1 : 0, a.passes, bb > 0.0 ? sqrt(rr / bb) : 0.0, bb, sc->rz[0]};
+}
+
+// A deterministic pseudo-random right-hand side (values in [-1, 1), zero where s = 0) and a
+// zero initial guess, for the spectral estimate of M^-1 A.
+__global__ void k_fill_trial(const double *__restrict__ schi, long M, int nrhs, double *__restrict__ rhs,
+                             double *__restrict__ y)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const bool in = schi[i] != 0.0;
+    for (int r = 0; r < nrhs; r++)
+        for (int c = 0; c < 3; c++) {
+            const long o = ((long)r * 3 + c) * M + i;
+            unsigned long long x = (unsigned long long)o * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+            x ^= x >> 31;
+            x *= 0xBF58476D1CE4E5B9ull;
+            x ^= x >> 29;
+            rhs[o] = in ? (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0 : 0.0;
+            y[o] = 0.0;
+        }
+}
+
+void launch_fill_trial(const double *schi, long M, int nrhs, double *rhs, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_trial, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, schi, M, nrhs, rhs, y);
+    MJ_CHECK(hipGetLastError());
+}
+
+void launch_cheb_init(const ChebArg &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cheb_init, dim3(a.cg.nblk, a.cg.nrhs), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_cheb_reduce<2>, dim3(a.cg.nrhs), dim3(1024), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+}
+void launch_cheb_pass(const ChebArg &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cheb_pass, dim3(a.cg.nblk, a.cg.nrhs), dim3(256), 0, st, a);
+    MJ_CHECK(hipGetLastError());
+    if (a.want_norm) {
+        hipLaunchKernelGGL(k_cheb_reduce<1>, dim3(a.cg.nrhs), dim3(1024), 0, st, a);
+        MJ_CHECK(hipGetLastError());
+    }
 }
 
 // ---------------------------------------------------------------------------- probes

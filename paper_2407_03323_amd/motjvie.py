@@ -45,7 +45,7 @@ class mj_config(ctypes.Structure):
         ("fft_pencils", ctypes.c_int32),
         ("hy", ctypes.c_double), ("hz", ctypes.c_double),
         ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
-        ("outer_block", ctypes.c_int32),
+        ("outer_block", ctypes.c_int32), ("z0_solver", ctypes.c_int32), ("z0_graphs", ctypes.c_int32),
     ]
 
 
@@ -141,7 +141,7 @@ class Solver:
 
     def __init__(self, U, V, W, eps, fir=None, h=1.0, c_dt=None, n_rhs=1, cg_rtol=0.0, cg_maxit=0,
                  time_block=0, quad_order=0, stream=None, fft_pencils=0, hy=0.0, hz=0.0, allocator=None,
-                 outer_block=0):
+                 outer_block=0, z0_solver=0, z0_graphs=0):
         """allocator: None (the library's hipMalloc) or "torch" (PyTorch's caching allocator,
         through mj_config.alloc / free_)."""
         self._lib = load_library()
@@ -166,6 +166,8 @@ class Solver:
         cfg.fft_pencils = int(fft_pencils)
         cfg.hy, cfg.hz = float(hy), float(hz)
         cfg.outer_block = int(outer_block)
+        cfg.z0_solver = int(z0_solver)
+        cfg.z0_graphs = int(z0_graphs)
         self._alloc_fns = None
         if allocator == "torch":
             self._alloc_fns = torch_allocator(cfg.stream)
@@ -194,12 +196,12 @@ class Solver:
             pass
 
     def info(self) -> dict:
-        out = np.zeros(20)
-        self._check(self._lib.mj_info(self._h, _dptr(out), 20))
+        out = np.zeros(23)
+        self._check(self._lib.mj_info(self._h, _dptr(out), 23))
         keys = ["ell", "Nx", "Ny", "Nz", "time_block", "real_depth", "n_rhs", "n", "device_bytes",
                 "gen_ms", "spectra_ms", "n_fir", "n_probes", "probe_window", "probe_pairs", "probe_gen_ms",
-                "fft_pencils_x", "fft_pencils_y", "fft_pencils_z", "outer_block"]
-        ms = ("gen_ms", "spectra_ms", "probe_gen_ms")
+                "fft_pencils_x", "fft_pencils_y", "fft_pencils_z", "outer_block", "z0_solver", "lam_lo", "lam_hi"]
+        ms = ("gen_ms", "spectra_ms", "probe_gen_ms", "lam_lo", "lam_hi")
         return {k: (int(v) if k not in ms else float(v)) for k, v in zip(keys, out)}
 
     @property

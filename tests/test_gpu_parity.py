@@ -244,8 +244,10 @@ def _three_waves(U, V, W):
 
 @pytest.mark.parametrize("tb,ob", [(1, 0), (8, 0), (16, 0), (8, 16)])
 def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob):
-    """Three right-hand sides marched together: each equals its own single-RHS march (the
-    per-RHS arithmetic is the same, so to rounding) and the oracle's march."""
+    """Three right-hand sides marched together: each equals its own single-RHS march and the
+    oracle's march.  The batch shares every launch, and its Z_0 solve runs as many Chebyshev
+    passes as its slowest right-hand side needs, so a batched current differs from its single
+    march by what the solve tolerance allows (1e-13 in the residual), not more."""
     from oracle import mot
     torch = torch_cuda
     U, V, W, n = 6, 5, 4, 60
@@ -273,7 +275,7 @@ def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob):
         e_single = _rel(Jb[:, i], J1)
         e_oracle = _rel(Jb[:, i], ref)
         say("  rhs", i, "vs single", e_single, "vs oracle", e_oracle)
-        assert e_single <= 1e-13
+        assert e_single <= 1e-11
         assert e_oracle <= 1e-8
 
 
@@ -1353,3 +1355,76 @@ def test_time_levels_agree_at_full_size(torch_cuda, tb, ob):
     err = float((out[0] - out[1]).norm() / out[0].norm())
     say("  rel L2 against blocks of 8: %.3e" % err)
     assert err <= 1e-11
+
+
+def test_chebyshev_solve_matches_cg_and_oracle(torch_cuda):
+    """The Z_0 solve by Chebyshev iteration (the default) and by CG give the same march to the
+    solve tolerance, and both match the oracle's direct solve; the spectral bounds the
+    Chebyshev iteration uses enclose every eigenvalue of the Jacobi-preconditioned symmetrised
+    Z_0, computed densely from the oracle's K_0 (eq:Z) on the host."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n = 6, 5, 4, 80
+    eps = wl.random_eps(U, V, W, 61, 1.0, 14.0)
+    eps[0, :, :] = 1.0                                   # a vacuum layer
+    k = (0.48, -0.6, 0.64)
+    kk = np.asarray(k)
+    pol = np.cross(kk, (1.0, 0.0, 0.0))
+    pol = tuple(pol / np.linalg.norm(pol))
+    prob = wl.Problem("cheb", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, pol, 2.5)], n,
+                      fir=wl.binomial_highpass(5, 0.05))
+    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    o = mot.Oracle(prob, K=K)
+    ref = o.run(n)
+    out = {}
+    for solver in (2, 1):
+        s = make_solver(prob, time_block=8, z0_solver=solver)
+        assert s.info()["z0_solver"] == (0 if solver == 2 else 1)
+        info = s.info()
+        J = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+        s.run(n, J)
+        st = s.stats()
+        out[solver] = J.cpu().numpy()[:, 0]
+        say("  solver %d: iterations %.2f (max %d), residual %.2e, bounds [%.4f, %.4f], rel L2 vs oracle %.3e" % (
+            solver, st["cg_iters"], st["cg_iters_max"], st["cg_res_max"], info["lam_lo"], info["lam_hi"],
+            _rel(out[solver], ref)))
+        assert st["cg_res_max"] <= 1e-13
+        if solver == 2:
+            lo, hi = info["lam_lo"], info["lam_hi"]
+        s.close()
+    assert _rel(out[2], ref) <= 1e-8 and _rel(out[1], ref) <= 1e-8
+    assert _rel(out[2], out[1]) <= 1e-11
+    # dense spectrum of M^-1 A, A = D^-1 Z_0 D on the voxels with chi > 0 (D = diag sqrt chi)
+    chi = np.tile(mot.chi_of(eps).ravel(), 3)
+    m = chi > 0
+    Z0 = o.Z0.toarray()[np.ix_(m, m)]
+    d = np.sqrt(chi[m])
+    A = Z0 * d[None, :] / d[:, None]
+    Mh = 1.0 / np.sqrt(np.diag(A))
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T) * Mh[:, None] * Mh[None, :])
+    say("  M^-1 A spectrum [%.4f, %.4f]" % (ev[0], ev[-1]))
+    assert lo <= ev[0] and ev[-1] <= hi
+
+
+def test_chebyshev_graph_replays_match_eager_launches(torch_cuda):
+    """The Chebyshev batches replayed from captured HIP graphs (one capture per batch shape,
+    replayed in every later step, with the march's other kernels and the host's status reads in
+    between) give the same currents, bit for bit, as the same passes launched one by one."""
+    torch = torch_cuda
+    U, n = 12, 120
+    x, y, z = wl.voxel_centres(U, U, U)
+    eps = np.where((x - 6) ** 2 + (y - 6) ** 2 + (z - 6) ** 2 <= 5.0 ** 2, 9.0, 1.0)
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("graph", U, U, U, eps, [wl.gaussian_wave(U, U, U, k, p, 3.0)], n,
+                      fir=wl.binomial_highpass(17, 0.01))
+    out = []
+    for graphs in (0, 1):
+        s = make_solver(prob, z0_solver=2, z0_graphs=graphs)
+        J = torch.zeros((n, 1, 3, U, U, U), dtype=torch.float64, device="cuda")
+        s.run(n, J)
+        torch.cuda.synchronize()
+        st = s.stats()
+        say("  graphs %d: %.2f passes per solve, %.4f ms per step in the solve" % (graphs, st["cg_iters"], st["z0_ms"]))
+        out.append(J)
+        s.close()
+    assert torch.equal(out[0], out[1])
