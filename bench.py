@@ -55,15 +55,16 @@ def mac_source_digest() -> str:
     return hashlib.sha1(src[a:b].encode()).hexdigest()[:12]
 
 
-def mac_traffic(workload: str):
+def mac_traffic(workload: str, overlap: bool = False):
     """HBM bytes per MAC launch from the committed rocprofv3 counter summary, if it was taken
-    on the current MAC source; else None."""
+    on the current MAC source and of the same launch (in line, or on the second stream);
+    else None."""
     path = os.path.join(ROOT, "profiles", "mac_traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("mac_source_sha1_12") != mac_source_digest():
+    if d.get("mac_source_sha1_12") != mac_source_digest() or bool(d.get("overlap", False)) != overlap:
         return None
     return d.get("bytes_per_launch")
 
@@ -179,6 +180,8 @@ def main():
     ap.add_argument("--outer-block", type=int, default=0, help="steps per outer time block (three levels; 0 = two)")
     ap.add_argument("--z0-solver", type=int, default=0, help="0 by size, 1 CG, 2 Chebyshev")
     ap.add_argument("--z0-graphs", type=int, default=0, help="replay the Chebyshev batches from HIP graphs")
+    ap.add_argument("--outer-overlap", type=int, default=0,
+                    help="0 library default, 1 outer level in line, 2 on a second stream")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -209,7 +212,8 @@ def main():
     prob = wl.config(args.workload)
     t_setup = time.perf_counter()
     solver = motjvie.solver_for(prob, time_block=args.time_block, outer_block=args.outer_block,
-                                z0_solver=args.z0_solver, z0_graphs=args.z0_graphs)
+                                z0_solver=args.z0_solver, z0_graphs=args.z0_graphs,
+                                outer_overlap=args.outer_overlap)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     info = solver.info()
@@ -258,7 +262,15 @@ def main():
     SJ, SK = 48.0 * half * R, 48.0 * octant
     B2 = info["outer_block"]
     TB = B2 if B2 else B                      # targets of one far launch
-    if B > 1:
+    ov = bool(info["outer_overlap"])
+    if ov:
+        # the launch on the second stream: lags B2 + 1 .. ell of the next outer block's B2
+        # targets (sources before the current block), B2 partial sums written.  Its duration
+        # is measured on that stream while the march shares the device
+        bytes_launch = (ell - B2) * (SJ + SK) + B2 * SJ
+        launch_ms = st["side_launch_ms"]
+        kname = "k_mac_win<%d> (outer level of three, on the second stream, history MAC)" % TB
+    elif B > 1:
         # per launch: every one of the ell lags once (Jhat and Khat) and TB partial sums written
         bytes_launch = ell * (SJ + SK) + TB * SJ
         launch_ms = st["far_launch_ms"]
@@ -271,11 +283,12 @@ def main():
     achieved = bytes_launch / (launch_ms / 1e3) / 1e9
     # FP64 work of the same launch: a real symmetric 3x3 times a complex 3-vector is 36 FLOP per
     # (lag, half-spectrum point, target); target t of a block sums lags t + 1 .. ell
-    flop_launch = 36.0 * half * R * (sum(ell - t for t in range(TB)) if B > 1 else ell)
+    flop_launch = 36.0 * half * R * (sum(ell - B2 - t for t in range(TB)) if ov else
+                                     sum(ell - t for t in range(TB)) if B > 1 else ell)
     tflops = flop_launch / (launch_ms / 1e3) / 1e12
     fp64 = {"flop_per_launch": flop_launch, "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tflops / FP64_PEAK_TFLOPS}
-    traffic = mac_traffic(args.workload)
+    traffic = mac_traffic(args.workload, ov)
     # the whole FFT convolution of a step (forward FFT, MAC at every level, inverse FFT):
     # algorithmic bytes per step over the measured time of those three phases
     U, V, W = prob.U, prob.V, prob.W
@@ -283,7 +296,12 @@ def main():
     if B > 1:
         # near part of the step at position t of an inner block: read and write F[t], t lags
         near_bytes = sum(2 * SJ + t * (SJ + SK) for t in range(1, B)) / B
-        mac_step = bytes_launch / TB + near_bytes
+        if ov:
+            # on the caller's stream at each outer block start: the B2 sums from the second
+            # stream read, the B2 sources of the block before, lags 1 .. 2 B2 - 1, B2 sums written
+            mac_step = (3 * B2 * SJ + (2 * B2 - 1) * SK) / B2 + near_bytes
+        else:
+            mac_step = bytes_launch / TB + near_bytes
         if B2:
             # middle part at the start of inner block q > 0: its B sums start from the outer ones,
             # q B sources of the outer block, lags up to q B + B - 1, B sums written
@@ -319,7 +337,9 @@ def main():
                    "z0_solver": "CG" if info["z0_solver"] == 1 else "Chebyshev",
                    "mid_launch_ms": round(st["mid_launch_ms"], 4),
                    "fft_pencils": [info["fft_pencils_x"], info["fft_pencils_y"], info["fft_pencils_z"]],
-                   "far_launch_ms": round(st["far_launch_ms"], 4), "near_launch_ms": round(st["near_launch_ms"], 4)},
+                   "far_launch_ms": round(st["far_launch_ms"], 4), "near_launch_ms": round(st["near_launch_ms"], 4),
+                   "outer_overlap": ov, "side_launch_ms": round(st["side_launch_ms"], 4),
+                   "side_launches_timed": int(st["side_launches"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "bytes_per_launch": bytes_launch,

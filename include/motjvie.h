@@ -102,6 +102,14 @@ typedef struct {
     int32_t z0_graphs;        /* != 0: the Chebyshev passes of a solve (whose arguments depend only on the
                                  pass index) are captured once per batch shape as HIP graphs and replayed
                                  on `stream` in later steps; 0: launched one by one */
+    int32_t outer_overlap;    /* three levels only: 2 forms the outer sums of each outer block over the
+                                 sources before the previous block on a second stream of the library's
+                                 own (non-blocking, default priority), while the previous block marches,
+                                 and adds the previous block's sources at the block start on `stream`;
+                                 1 forms them in one launch on `stream` at the block start; 0 the
+                                 default (1).  The two group the terms of eq:PnMOT differently (results
+                                 differ at rounding level); 2 holds B2 more partial sums on the device.
+                                 Every entry point orders its own work after the second stream's */
 } mj_config;
 
 /*
@@ -121,7 +129,7 @@ void mj_destroy(mj_solver *s);
 const char *mj_last_error(const mj_solver *s);
 
 /*
- * mj_info -- sizes of the solver.  out (host, n entries used, n <= 23):
+ * mj_info -- sizes of the solver.  out (host, n entries used, n <= 24):
  *   [0] ell  [1] Nx [2] Ny [3] Nz (padded FFT sizes)  [4] time block B
  *   [5] history depth kept in real space  [6] n_rhs  [7] current step n
  *   [8] device bytes allocated  [9] kernel generation time (ms)  [10] spectra time (ms)
@@ -130,6 +138,7 @@ const char *mj_last_error(const mj_solver *s);
  *   [16] [17] [18] pencils per block of the x, y and z FFT passes  [19] outer time block (0: none)
  *   [20] Z_0 solver in use (0 Chebyshev, 1 CG)  [21] [22] the bounds of the eigenvalues of the
  *   Jacobi-preconditioned symmetrised Z_0 that the Chebyshev solve uses (0: not estimated)
+ *   [23] 1 if the outer level runs on the second stream (outer_overlap)
  */
 int mj_info(const mj_solver *s, double *out, int32_t n);
 
@@ -297,7 +306,7 @@ int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const 
 
 /*
  * mj_stats -- per-phase device times of the last mj_run (HIP events on the solver's stream),
- *   in ms per step, and CG statistics.  out (host, n <= 19): [0] forward FFT  [1] history
+ *   in ms per step, and CG statistics.  out (host, n <= 21): [0] forward FFT  [1] history
  *   MAC  [2] inverse FFT  [3] epilogue (excitation, FIR, RHS)  [4] Z_0 solve  [5] total
  *   [6] mean CG iterations  [7] max final relative residual  [8] steps timed
  *   [9] max CG iterations  [10] mean duration of one far-part MAC launch (time-blocked,
@@ -305,7 +314,10 @@ int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const 
  *   [13] probes.  [5] includes [13].  After mj_adjoint_gradient: [14] forward pass (ms,
  *   whole run)  [15] backward pass with recomputation (ms)  [16] segments  [17] checkpoint bytes.
  *   [18] mean duration of one middle-level MAC launch (three time levels).  With three levels,
- *   [10] and [11] describe the outer launches.
+ *   [10] and [11] describe the outer launches (overlapped: those on `stream`, which add the
+ *   previous block's sources).  [19] mean duration of one launch on the second stream
+ *   (outer_overlap = 2, events on that stream; it shares the device with the march)
+ *   [20] such launches timed, those that had finished when the run returned.
  */
 int mj_stats(const mj_solver *s, double *out, int32_t n);
 

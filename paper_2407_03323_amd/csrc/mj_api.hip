@@ -23,6 +23,9 @@ thread_local std::string g_err;
 // voxels x right-hand sides up to which z0_solver = 0 takes the Chebyshev solve
 constexpr long kChebMaxUnknowns = 1L << 19;
 
+// whether outer_overlap = 0 runs the outer level of three on the second stream
+constexpr bool kOverlapDefault = false;
+
 // ---------------------------------------------------------------------------- static staging
 // mj_kernel_values_noalloc stages its requests and results through this file-scope array
 // instead of allocating: kNoAllocMax requests, laid out as results [max][6] doubles, then
@@ -112,6 +115,20 @@ struct mj_solver {
     double *Khat = nullptr;
     double2 *ring = nullptr, *Shat = nullptr, *farbuf = nullptr;
     double2 *gbuf = nullptr;        // outer-block partial sums [B2][nrhs][3][plane] (three levels)
+    // Overlapped outer level (three levels): while an outer block marches, a second stream forms
+    // the next block's outer sums over the sources before the current block; at the next block
+    // start the sources of the block just marched are added on the caller's stream.
+    bool overlap = false;
+    double2 *hbuf = nullptr;        // those sums [B2][nrhs][3][plane], of the block starting at h_block
+    int h_block = 0;                // 0: hbuf holds no block's sums
+    hipStream_t side = nullptr;     // the library's second stream (non-blocking, default priority)
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    bool side_pending = false;      // work on `side` may still run: `st` waits for ev_side first
+    static constexpr int kSideTimers = 8;
+    hipEvent_t side_t[kSideTimers][2] = {};   // start and end of recent launches on `side`
+    bool side_busy[kSideTimers] = {};
+    int side_count = 0, side_done = 0;
+    double side_ms = 0.0;
     double *S = nullptr, *Jr = nullptr;
     double *rhs = nullptr, *y = nullptr, *p = nullptr, *q = nullptr;
     double *u = nullptr, *uy = nullptr;
@@ -135,6 +152,7 @@ struct mj_solver {
     mj::Fft3D fft{};
     mj::GenResult gen{};
     double K0_27[27 * 6] = {};
+    double *k0_d = nullptr;         // K0_27 on the device (the Z_0 stencil of this solver)
     int nblk = 1;
     int n = 0;
     int dev = 0;                    // device current at mj_create
@@ -154,7 +172,7 @@ struct mj_solver {
     // statistics of the last run
     double t_gen_ms = 0, t_spec_ms = 0, t_probe_ms = 0;
     double t_mac_tune_ms = 0;       // MAC time per step of the timed choice (time_block < 0)
-    double stat[19] = {};
+    double stat[21] = {};
     Events events;
 
     template <class T>
@@ -171,6 +189,15 @@ struct mj_solver {
     ~mj_solver()
     {
         if (st) (void)hipStreamSynchronize(st);
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        for (hipEvent_t e : {ev_main, ev_side})
+            if (e) (void)hipEventDestroy(e);
+        for (auto &pr : side_t)
+            for (hipEvent_t e : pr)
+                if (e) (void)hipEventDestroy(e);
         clear_graphs();
         if (cap_st) (void)hipStreamDestroy(cap_st);
         mj::fft3d_free(fft);
@@ -213,6 +240,22 @@ struct mj_solver {
     };
     mj::EpiArg epi_arg() const;
     const double2 *mac(int n, int *kind);
+    void outer_sums(int nb, hipStream_t stream);
+    void outer_overlapped(int nb);
+    // `st` waits for the work on the second stream
+    void join_side()
+    {
+        if (!side_pending) return;
+        MJ_CHECK(hipStreamWaitEvent(st, ev_side, 0));
+        side_pending = false;
+    }
+    // ... and forgets the sums it formed (the march, the ring or the time division changes)
+    void drop_side()
+    {
+        join_side();
+        h_block = 0;
+    }
+    void collect_side_timers(bool wait);
     void mac_autotune();
     void default_time_division();
     // arguments of a time-block MAC launch writing to `out`, first target step nb
@@ -277,6 +320,8 @@ void mj_solver::create(const mj_config &c)
     if (c.fft_pencils < 0) throw ArgError("fft_pencils must be >= 0 (0: autotune)");
     if ((c.alloc == nullptr) != (c.free_ == nullptr)) throw ArgError("alloc and free_ are given together or not at all");
     if (c.z0_solver < 0 || c.z0_solver > 2) throw ArgError("z0_solver must be 0 (by size), 1 (CG) or 2 (Chebyshev)");
+    if (c.outer_overlap < 0 || c.outer_overlap > 2)
+        throw ArgError("outer_overlap must be 0 (default), 1 (in line) or 2 (on a second stream)");
     use_graphs = c.z0_graphs != 0;
     da.fn_alloc = c.alloc;
     da.fn_free = c.free_;
@@ -347,6 +392,15 @@ void mj_solver::create(const mj_config &c)
     const int fb_targets = tune_mac ? 16 : B, gb_targets = tune_mac ? 16 : B2;
     if (fb_targets > 1) farbuf = dalloc<double2>((size_t)fb_targets * nrhs * 3 * sp, "time-block partial sums");
     if (gb_targets) gbuf = dalloc<double2>((size_t)gb_targets * nrhs * 3 * sp, "outer-block partial sums");
+    const bool want_overlap = c.outer_overlap == 2 || (c.outer_overlap == 0 && kOverlapDefault);
+    if (gb_targets && want_overlap) {
+        hbuf = dalloc<double2>((size_t)gb_targets * nrhs * 3 * sp, "next outer block's sums");
+        MJ_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        MJ_CHECK(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
+        MJ_CHECK(hipEventCreateWithFlags(&ev_side, hipEventDisableTiming));
+        for (auto &pr : side_t)
+            for (hipEvent_t &e : pr) MJ_CHECK(hipEventCreate(&e));
+    }
     S = dalloc<double>((size_t)nrhs * 3 * M, "convolution");
     Jr = dalloc<double>((size_t)rdepth * nrhs * 3 * M, "current history");
     rhs = dalloc<double>((size_t)nrhs * 3 * M, "cg rhs");
@@ -375,6 +429,7 @@ void mj_solver::create(const mj_config &c)
     if (c.fft_pencils > 0) mj::fft3d_set_pencils(fft, c.fft_pencils);
     else mj::fft3d_autotune(fft, st);
     if (tune_mac) mac_autotune();
+    overlap = hbuf != nullptr && B2 > 0;
     if (z0_method == 0) estimate_spectrum();
     n = 0;
     MJ_CHECK(hipStreamSynchronize(st));
@@ -442,7 +497,8 @@ void mj_solver::build_spectra()
                 for (int dx = -1; dx <= 1; dx++, o++)
                     if ((U == 1 && dx != 0) || (V == 1 && dy != 0) || (W == 1 && dz != 0))
                         for (int c = 0; c < 6; c++) K0_27[6 * o + c] = 0.0;
-        mj::upload_stencil(K0_27);
+        k0_d = dalloc<double>(27 * 6, "K_0 stencil");
+        MJ_CHECK(hipMemcpy(k0_d, K0_27, sizeof K0_27, hipMemcpyHostToDevice));
     }
 
     // spectra of lags 1..ell on the padded grid, octant only, with 1/(Nx Ny Nz) folded in
@@ -492,6 +548,7 @@ mj::CgArg mj_solver::cg_arg() const
     a.schi = schi;
     a.d0 = fir.empty() ? 0.0 : fir[0];
     a.k0c = K0_27[13 * 6 + 0];
+    a.k0 = k0_d;
     a.rhs = rhs;
     a.uy = uy;
     a.y = y;
@@ -777,6 +834,7 @@ static void gl8_half(double *x, double *w)
 mj::EpiArg mj_solver::epi_arg() const
 {
     mj::EpiArg e{};
+    e.k0 = k0_d;
     e.M = M;
     e.U = U;
     e.V = V;
@@ -855,9 +913,13 @@ const double2 *mj_solver::mac(int n, int *kind)
         const int tau = (n - 2) % B2, t = tau % B, q = tau / B;
         double2 *fb = q == 0 ? gbuf : farbuf;
         if (tau == 0) {
-            mj::BlockMacArg a = block_arg(gbuf, n);
-            a.ntarget = B2;
-            mj::launch_mac_win(a, B2, st);
+            if (overlap) {
+                outer_overlapped(n);
+            } else {
+                mj::BlockMacArg a = block_arg(gbuf, n);
+                a.ntarget = B2;
+                mj::launch_mac_win(a, B2, st);
+            }
             far_kind = 1;
         } else if (t == 0) {
             mj::BlockMacArg a = block_arg(farbuf, n);
@@ -876,6 +938,73 @@ const double2 *mj_solver::mac(int n, int *kind)
     }
     *kind = far_kind;
     return spec;
+}
+
+// The outer sums of the block starting at nb over the sources before nb - B2 (lags above B2),
+// into hbuf on `stream`: the work that can run while the block before nb marches.
+void mj_solver::outer_sums(int nb, hipStream_t stream)
+{
+    if (nb - B2 - 1 < 1) throw std::logic_error("outer sums without sources");
+    mj::BlockMacArg a = block_arg(hbuf, nb);
+    a.ntarget = B2;
+    a.jmax = nb - B2 - 1;
+    mj::launch_mac_win(a, B2, stream);
+}
+
+// The outer level at the start nb of an outer block, overlapped (Sec. 4.1's division with the
+// outer sums split at nb - B2):
+//   G[tau] = H[tau] + sum over the sources nb - B2 .. nb - 1 of Khat_k Jhat_{nb + tau - k},
+// H being the sums over the sources before nb - B2, formed on the second stream while the block
+// before marched (or here, in line, after a restart).  Then the second stream starts on the
+// next block's H, over the sources before nb.  It reads ring slots of sources nb + B2 - ell ..
+// nb - 1 while this block's steps write the slots of sources nb - ell .. nb + B2 - 1 - ell, and
+// writes hbuf, which only the next block start reads, after waiting for it.
+void mj_solver::outer_overlapped(int nb)
+{
+    join_side();
+    const bool have_h = nb - B2 - 1 >= 1;
+    if (have_h && h_block != nb) outer_sums(nb, st);
+    mj::BlockMacArg a = block_arg(gbuf, nb);
+    a.ntarget = B2;
+    a.jmin = nb - B2;
+    a.init = have_h ? hbuf : nullptr;
+    mj::launch_mac_win(a, B2, st);
+    MJ_CHECK(hipEventRecord(ev_main, st));
+    MJ_CHECK(hipStreamWaitEvent(side, ev_main, 0));
+    const int slot = side_count % kSideTimers;
+    if (side_busy[slot]) {
+        MJ_CHECK(hipEventSynchronize(side_t[slot][1]));
+        collect_side_timers(false);
+    }
+    MJ_CHECK(hipEventRecord(side_t[slot][0], side));
+    outer_sums(nb + B2, side);
+    MJ_CHECK(hipEventRecord(side_t[slot][1], side));
+    side_busy[slot] = true;
+    side_count++;
+    MJ_CHECK(hipEventRecord(ev_side, side));
+    side_pending = true;
+    h_block = nb + B2;
+}
+
+// Adds the durations of the finished launches on the second stream to side_ms (waiting for
+// all of them with wait).
+void mj_solver::collect_side_timers(bool wait)
+{
+    for (int i = 0; i < kSideTimers; i++) {
+        if (!side_busy[i]) continue;
+        if (wait) MJ_CHECK(hipEventSynchronize(side_t[i][1]));
+        const hipError_t q = hipEventQuery(side_t[i][1]);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();   // not an error: keep it from the next launch check
+            continue;
+        }
+        MJ_CHECK(q);
+        float ms = 0.0f;
+        MJ_CHECK(hipEventElapsedTime(&ms, side_t[i][0], side_t[i][1]));
+        side_ms += ms;
+        side_done++;
+        side_busy[i] = false;
+    }
 }
 
 // Default time division when the caller sets neither block: three levels, blocks of 4 in
@@ -1040,6 +1169,7 @@ void mj_solver::check_growth() const
 mj::AdjArg mj_solver::adj_arg() const
 {
     mj::AdjArg a{};
+    a.k0 = k0_d;
     a.M = M;
     a.U = U;
     a.V = V;
@@ -1068,6 +1198,8 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
     double cg_iter_sum = 0, cg_res_max = 0, cg_iter_max = 0;
     bool noconv = false;
     std::vector<char> step_far(n_steps, 0);
+    side_ms = 0.0;
+    side_done = 0;
     for (int s = 0; s < n_steps; s++) {
         StepIO io;
         io.ev = &events.ev[(size_t)7 * s];
@@ -1114,6 +1246,9 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
     stat[12] = nnear ? near_ms / nnear : 0.0;
     stat[13] = probe_ms / ns;
     stat[18] = nmid ? mid_ms / nmid : 0.0;
+    if (side) collect_side_timers(false);
+    stat[19] = side_done ? side_ms / side_done : 0.0;
+    stat[20] = side_done;
     if (noconv) throw std::range_error("Z_0 solve did not converge");
 }
 
@@ -1123,6 +1258,7 @@ void mj_solver::run(int n_steps, double *Jout, double *Pout, int j_every)
 // 0 * Inf.  They are cleared here, as at mj_create.
 void mj_solver::restart()
 {
+    drop_side();
     const size_t v = sizeof(double) * (size_t)nrhs * 3 * M;
     MJ_CHECK(hipMemsetAsync(p, 0, v, st));
     MJ_CHECK(hipMemsetAsync(q, 0, v, st));
@@ -1139,6 +1275,7 @@ void mj_solver::restart()
 
 void mj_solver::history_sum(const double *Jh, int depth, double *P)
 {
+    drop_side();
     const long sp = spec_plane();
     const int nfake = ell + 1;
     for (int k = 1; k <= ell; k++) {
@@ -1452,6 +1589,7 @@ void mj_solver::set_state(const void *buf, size_t bytes)
         throw ArgError("state buffer has the wrong size");
     if (h.n < 0 || h.n > INT32_MAX) throw ArgError("bad step count in the state");
     const char *p = (const char *)buf + sizeof h;
+    drop_side();
     MJ_CHECK(hipStreamSynchronize(st));
     MJ_CHECK(hipMemcpy(ring, p, (size_t)h.ring_bytes, hipMemcpyHostToDevice));
     p += h.ring_bytes;
@@ -1570,6 +1708,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             const int s0 = starts[c], s1 = seg_end(c);
             if (c < C - 1) {
                 // restart the forward march at s0 from its checkpoint and recompute the segment
+                drop_side();
                 n = s0 - 1;
                 if (c > 0) {
                     const int j0 = s0 - 1 - ell;   // first stored step
@@ -1591,6 +1730,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
                 }
             }
             // transposed march over j = s1 .. s0 (reversed step n' = N + 1 - j)
+            drop_side();
             ring = ring_a;
             farbuf = far_a;
             gbuf = g_a;
@@ -1616,6 +1756,7 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
             }
             n_adj = n;
             adj_pred = cheb_pred;
+            drop_side();
             ring = ring_f;
             farbuf = far_f;
             gbuf = g_f;
@@ -1627,6 +1768,9 @@ void mj_solver::adjoint_gradient(int N, int ckpt_every, double *phi, double *gra
         MJ_CHECK(hipStreamSynchronize(st));
     } catch (...) {
         (void)hipStreamSynchronize(st);
+        if (side) (void)hipStreamSynchronize(side);
+        side_pending = false;
+        h_block = 0;
         ring = ring_f;
         farbuf = far_f;
         gbuf = g_f;
@@ -1710,12 +1854,12 @@ const char *mj_last_error(const mj_solver *s) { return s ? s->err.c_str() : g_er
 int mj_info(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    double v[23] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
+    double v[24] = {(double)s->ell, (double)s->Nx, (double)s->Ny, (double)s->Nz, (double)s->B,
                     (double)s->rdepth, (double)s->nrhs, (double)s->n, (double)s->bytes, s->t_gen_ms,
                     s->t_spec_ms, (double)s->fir.size(), (double)s->np, (double)s->nw, (double)s->npairs,
                     s->t_probe_ms, (double)s->fft.Px, (double)s->fft.Py, (double)s->fft.Pz, (double)s->B2,
-                    (double)s->z0_method, s->lam_lo, s->lam_hi};
-    for (int i = 0; i < n && i < 23; i++) out[i] = v[i];
+                    (double)s->z0_method, s->lam_lo, s->lam_hi, s->overlap ? 1.0 : 0.0};
+    for (int i = 0; i < n && i < 24; i++) out[i] = v[i];
     return MJ_OK;
 }
 
@@ -1902,7 +2046,7 @@ int mj_kernel_values_noalloc(mj_solver *s, int32_t n, const int32_t *lag, const 
 int mj_stats(const mj_solver *s, double *out, int32_t n)
 {
     if (!s || !out) return MJ_EINVAL;
-    for (int i = 0; i < n && i < 19; i++) out[i] = s->stat[i];
+    for (int i = 0; i < n && i < 21; i++) out[i] = s->stat[i];
     return MJ_OK;
 }
 

@@ -31,6 +31,8 @@ struct BlockMacArg {
     int nrhs;
     int jmin;                  // far: sources before step jmin count as zero (<= 1: none dropped)
     const double2 *init;       // far: partial sums the targets start from, laid out like far (NULL: zero)
+    int jmax;                  // windowed far kernel: sources after step jmax count as zero (<= 0: none
+                               // dropped); its lag loop then starts at nb - jmax
 };
 
 struct WaveArg {
@@ -61,6 +63,7 @@ struct EpiArg {
     const double *Lring;     // lambda history [depth][nrhs][3][M] (the local terms act on lambda)
     const double *G;         // adjoint source g_j [nrhs][3][M]
     double *bq;              // b'_j, kept for the voxels with chi = 0 [nrhs][3][M]
+    const double *k0;        // the solver's K_0 stencil (the gradient term B_n)
 };
 
 // Adjoint of the probe objective and the eps-gradient (see mj_march.hip).
@@ -84,6 +87,7 @@ struct AdjArg {
     const double *Bj;        // B_j [nrhs][3][M]
     const double *inv_eps;
     double *grad;            // [M], accumulated
+    const double *k0;        // the solver's K_0 stencil (the adjoint's local term)
 };
 
 struct CgScalars {
@@ -114,6 +118,9 @@ struct CgArg {
     double *part;            // [nrhs][3][nblk]
     CgScalars *scal;         // [nrhs]
     CgStatus *stat;          // [nrhs]
+    // the solver's K_0(D) on its 27-point support [27][6] in device memory: entry
+    // 13 + dx + 3 dy + 9 dz, components xx yy zz xy xz yz; read through the scalar cache
+    const double *k0;
 };
 
 // Chebyshev iteration on the symmetrised Z_0 system with the Jacobi preconditioner M (see
@@ -176,7 +183,6 @@ void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st);
 void launch_epilogue(const EpiArg &e, hipStream_t st);
 void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,
                           const double *fir, int nfir, long M, double *P, hipStream_t st);
-void upload_stencil(const double *K0_27x6);
 void launch_cg_init(const CgArg &a, hipStream_t st);
 void launch_cg_a(const CgArg &a, int it, hipStream_t st);
 void launch_cg_b(const CgArg &a, int it, hipStream_t st);

@@ -327,14 +327,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 
 // Far part with a rotation-free source window.  Targets t = 0 .. TG - 1 are steps n_b + t; each
 // sums F[t] = init[t] + sum_k Khat_k Jhat_{n_b + t - k} over the lags k >= t + 1 whose source
-// n_b + t - k is at least jmin (and at least 1).  One lane = one part (real or imaginary) of one
-// mirror point, as in k_mac_far with one target group.  The lane loads, at lag k, the source
-// s_k = n_b - k of target 0; target t at lag k takes s_{k - t}, loaded t lags earlier.  Sources
-// sit in W = TG + PD register slots, s_k in slot k mod W: the load of lag k + PD (issued before
-// lag k is accumulated) overwrites the slot of s_{k - TG}, which no target needs at lag k or
-// later, so no value ever moves between registers.  Kernel values of lag k sit in slot
-// k mod (PD + 1).  The lag loop is unrolled by UF, a multiple of both slot counts, so that every
-// slot index is a compile-time constant.
+// n_b + t - k is at least jmin (and at least 1) and, if jmax > 0, at most jmax.  One lane = one
+// part (real or imaginary) of one mirror point, as in k_mac_far with one target group.  The lane
+// loads, at lag k, the source s_k = n_b - k of target 0; target t at lag k takes s_{k - t},
+// loaded t lags earlier.  Sources sit in W = TG + PD register slots, s_k in slot
+// (k - klo + 1) mod W, klo being the first lag: the load of lag k + PD (issued before lag k is
+// accumulated) overwrites the slot of s_{k - TG}, which no target needs at lag k or later, so no
+// value ever moves between registers.  Kernel values of lag k sit in slot (k - klo + 1) mod
+// (PD + 1).  The lag loop is unrolled by UF, a multiple of both slot counts, so that every slot
+// index is a compile-time constant.
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 template <int TG, int PD, int WPE>
@@ -367,6 +368,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int nb = a.nb, jlo = max(1, a.jmin);
     // the largest lag with a term: target TG - 1 reaches source jlo at lag nb + TG - 1 - jlo
     const int kmax = min(a.nk, nb - jlo + TG - 1);
+    // the smallest: target 0 reaches source jmax at lag nb - jmax, and no target has a source
+    // after jmax below that lag
+    const int klo = a.jmax > 0 ? max(1, nb - a.jmax) : 1;
 
     // accumulators and source slots per component: arrays of at most TG + PD doubles each, which
     // the compiler keeps in registers
@@ -409,8 +413,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         c4 = v2.x;
         c5 = v2.y;
     };
-    // lag k = k0 + i, k0 = 1 mod UF: source slot of s_{k - t} is (1 + i - t) mod W.  The UF steps
-    // are expanded from a compile-time index sequence, so every slot index is a constant.
+    // lag k = k0 + i, k0 = klo mod UF: source slot of s_{k - t} is (1 + i - t) mod W.  Slots of
+    // sources before lag klo are never loaded and stay zero, which is their value: they lie
+    // after jmax.  The UF steps are expanded from a compile-time index sequence, so every slot
+    // index is a constant.
     auto step = [&](auto ic, int k0, bool guard) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
         const int k = k0 + i;
@@ -439,9 +445,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
     for (int d = 0; d < PD; d++) {
         const int ls = (1 + d) % W, lk = (1 + d) % KS;
-        load(1 + d, jx[ls], jy[ls], jz[ls], k0s[lk], k1s[lk], k2s[lk], k3s[lk], k4s[lk], k5s[lk]);
+        load(klo + d, jx[ls], jy[ls], jz[ls], k0s[lk], k1s[lk], k2s[lk], k3s[lk], k4s[lk], k5s[lk]);
     }
-    int k0 = 1;
+    int k0 = klo;
     for (; k0 <= kmax; k0 += UF) body(k0, true);
     double *Fd = (double *)a.far + (long)r * 3 * plane2 + joff / 8;
     [&]<int... T>(std::integer_sequence<int, T...>) __attribute__((always_inline)) {
@@ -658,12 +664,10 @@ void launch_history_local(const double *Jh, int depth, const double *S, const do
 // them in block order and stores the scalars, so the results do not depend on scheduling.  The
 // same kernel takes the convergence test and keeps the status record, and the iteration kernels
 // read its outcome (CgScalars::conv) from the previous launch.
-__constant__ double c_K0[27 * 6];
-
-void upload_stencil(const double *K0_27x6)
-{
-    MJ_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_K0), K0_27x6, sizeof(double) * 27 * 6));
-}
+// The K_0 stencil through the scalar cache: every lane reads the same entries, and a pointer
+// into the constant address space makes them scalar loads
+typedef __attribute__((address_space(4))) const double kconst_t;
+__device__ inline kconst_t *kconst(const double *p) { return (kconst_t *)p; }
 
 // sum_{D} K_0(D) u(m - D) at haloed index ip (the halo of u is zero, so no bounds tests);
 // ctr receives u(m) itself
@@ -674,7 +678,7 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
     const long sy = a.U + 2, sz = (long)(a.U + 2) * (a.V + 2);
     double acc0, acc1, acc2;
     {
-        const double *k = &c_K0[13 * 6];
+        kconst_t *k = kconst(a.k0) + 13 * 6;
         const double u0 = u[ip], u1 = u[Mp + ip], u2 = u[2 * Mp + ip];
         ctr[0] = u0;
         ctr[1] = u1;
@@ -691,7 +695,7 @@ __device__ inline void stencil_apply(const CgArg &a, const double *__restrict__ 
         const double s0 = u[ip - off] + u[ip + off];
         const double s1 = u[Mp + ip - off] + u[Mp + ip + off];
         const double s2 = u[2 * Mp + ip - off] + u[2 * Mp + ip + off];
-        const double *k = &c_K0[o * 6];
+        kconst_t *k = kconst(a.k0) + o * 6;
         acc0 += k[0] * s0 + k[3] * s1 + k[4] * s2;
         acc1 += k[3] * s0 + k[1] * s1 + k[5] * s2;
         acc2 += k[4] * s0 + k[5] * s1 + k[2] * s2;
@@ -1211,8 +1215,8 @@ void launch_probes(const ProbeStepArg &a, hipStream_t st)
 //   B_n = <E^i>(n) + sum_{k=0}^{ell} (T(k dt) J_{n-k} + K_k (*) J_{n-k}).
 
 // (K_0 (*) x)(m) on the plain (non-haloed) layout, with bounds tests
-__device__ inline void stencil_plain(const double *__restrict__ x, long M, int U, int V, int W, int u, int v, int w,
-                                     double out[3])
+__device__ inline void stencil_plain(const double *K0, const double *__restrict__ x, long M, int U, int V, int W,
+                                     int u, int v, int w, double out[3])
 {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int o = 0; o < 27; o++) {
@@ -1221,7 +1225,7 @@ __device__ inline void stencil_plain(const double *__restrict__ x, long M, int U
         if (su < 0 || su >= U || sv < 0 || sv >= V || sw < 0 || sw >= W) continue;
         const long j = ((long)sw * V + sv) * U + su;
         const double x0 = x[j], x1 = x[M + j], x2 = x[2 * M + j];
-        const double *k = &c_K0[o * 6];
+        kconst_t *k = kconst(K0) + o * 6;
         a0 += k[0] * x0 + k[3] * x1 + k[4] * x2;
         a1 += k[3] * x0 + k[1] * x1 + k[5] * x2;
         a2 += k[4] * x0 + k[5] * x1 + k[2] * x2;
@@ -1244,7 +1248,7 @@ __global__ void __launch_bounds__(256) k_grad_term(EpiArg e, const double *__res
     const WaveArg wa = e.waves[r];
     const double avg = wave_average(wa, e, u, v, w, e.n * e.c_dt);
     double k0[3];
-    stencil_plain(Jn + (long)r * 3 * M, M, e.U, e.V, e.W, u, v, w, k0);
+    stencil_plain(e.k0, Jn + (long)r * 3 * M, M, e.U, e.V, e.W, u, v, w, k0);
     for (int c = 0; c < 3; c++) {
         const long o = ((long)r * 3 + c) * M + i;
         double b = avg * wa.pol[c] + 0.5 * Jn[o] + k0[c];   // T(0) = T(dt) = 1/2, T(k dt) = 0 for k >= 2
@@ -1353,7 +1357,7 @@ __global__ void __launch_bounds__(256) k_adj_lambda(AdjArg a)
     }
     const int u = (int)(i % a.U), v = (int)((i / a.U) % a.V), w = (int)(i / ((long)a.U * a.V));
     double kn[3];
-    stencil_plain(a.nu + (long)r * 3 * M, M, a.U, a.V, a.W, u, v, w, kn);
+    stencil_plain(a.k0, a.nu + (long)r * 3 * M, M, a.U, a.V, a.W, u, v, w, kn);
     for (int c = 0; c < 3; c++) {
         const long o = ((long)r * 3 + c) * M + i;
         a.lam[o] = (a.bq[o] + kn[c]) / a.c0[i];

@@ -46,6 +46,7 @@ class mj_config(ctypes.Structure):
         ("hy", ctypes.c_double), ("hz", ctypes.c_double),
         ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
         ("outer_block", ctypes.c_int32), ("z0_solver", ctypes.c_int32), ("z0_graphs", ctypes.c_int32),
+        ("outer_overlap", ctypes.c_int32),
     ]
 
 
@@ -141,7 +142,7 @@ class Solver:
 
     def __init__(self, U, V, W, eps, fir=None, h=1.0, c_dt=None, n_rhs=1, cg_rtol=0.0, cg_maxit=0,
                  time_block=0, quad_order=0, stream=None, fft_pencils=0, hy=0.0, hz=0.0, allocator=None,
-                 outer_block=0, z0_solver=0, z0_graphs=0):
+                 outer_block=0, z0_solver=0, z0_graphs=0, outer_overlap=0):
         """allocator: None (the library's hipMalloc) or "torch" (PyTorch's caching allocator,
         through mj_config.alloc / free_)."""
         self._lib = load_library()
@@ -168,6 +169,7 @@ class Solver:
         cfg.outer_block = int(outer_block)
         cfg.z0_solver = int(z0_solver)
         cfg.z0_graphs = int(z0_graphs)
+        cfg.outer_overlap = int(outer_overlap)
         self._alloc_fns = None
         if allocator == "torch":
             self._alloc_fns = torch_allocator(cfg.stream)
@@ -196,11 +198,12 @@ class Solver:
             pass
 
     def info(self) -> dict:
-        out = np.zeros(23)
-        self._check(self._lib.mj_info(self._h, _dptr(out), 23))
+        out = np.zeros(24)
+        self._check(self._lib.mj_info(self._h, _dptr(out), 24))
         keys = ["ell", "Nx", "Ny", "Nz", "time_block", "real_depth", "n_rhs", "n", "device_bytes",
                 "gen_ms", "spectra_ms", "n_fir", "n_probes", "probe_window", "probe_pairs", "probe_gen_ms",
-                "fft_pencils_x", "fft_pencils_y", "fft_pencils_z", "outer_block", "z0_solver", "lam_lo", "lam_hi"]
+                "fft_pencils_x", "fft_pencils_y", "fft_pencils_z", "outer_block", "z0_solver", "lam_lo", "lam_hi",
+                "outer_overlap"]
         ms = ("gen_ms", "spectra_ms", "probe_gen_ms", "lam_lo", "lam_hi")
         return {k: (int(v) if k not in ms else float(v)) for k, v in zip(keys, out)}
 
@@ -320,12 +323,12 @@ class Solver:
         return phi.value
 
     def stats(self) -> dict:
-        out = np.zeros(19)
-        self._check(self._lib.mj_stats(self._h, _dptr(out), 19))
+        out = np.zeros(21)
+        self._check(self._lib.mj_stats(self._h, _dptr(out), 21))
         keys = ["fft_fwd_ms", "mac_ms", "fft_inv_ms", "epilogue_ms", "z0_ms", "step_ms", "cg_iters",
                 "cg_res_max", "steps", "cg_iters_max", "far_launch_ms", "far_launches", "near_launch_ms",
                 "probe_ms", "adjoint_forward_ms", "adjoint_backward_ms", "adjoint_segments",
-                "adjoint_checkpoint_bytes", "mid_launch_ms"]
+                "adjoint_checkpoint_bytes", "mid_launch_ms", "side_launch_ms", "side_launches"]
         return dict(zip(keys, out.tolist()))
 
     def fft_roundtrip(self, x, X=None, y=None):

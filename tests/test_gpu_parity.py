@@ -183,16 +183,19 @@ def test_history_sum_matches_oracle_8cube(torch_cuda, with_fir, tb):
 
 
 # ----------------------------------------------------------------------------- march
-@pytest.mark.parametrize("tb,ob", [(1, 0), (4, 0), (8, 0), (10, 0), (12, 0), (14, 0), (16, 0), (32, 0),
-                                   (8, 16), (4, 12), (4, 8), (-1, 0)])
-def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb, ob):
+@pytest.mark.parametrize("tb,ob,ov", [(1, 0, 0), (4, 0, 0), (8, 0, 0), (10, 0, 0), (12, 0, 0), (14, 0, 0),
+                                      (16, 0, 0), (32, 0, 0), (8, 16, 0), (4, 12, 0), (4, 8, 0), (-1, 0, 0),
+                                      (4, 8, 2), (4, 12, 2)])
+def test_march_matches_oracle_C1(torch_cuda, c1_oracle, tb, ob, ov):
     """J(t) over all 200 steps of the 8^3 eps_r = 4 cube: relative L2 <= 1e-8, without time
     blocking of the history sum, with two levels (blocks of tb steps) and with three (outer
-    blocks of ob steps split into blocks of tb)."""
+    blocks of ob steps split into blocks of tb), the outer level in line or (ov = 2) on the
+    second stream."""
     torch = torch_cuda
-    say("march C1 time_block=%d outer_block=%d" % (tb, ob))
+    say("march C1 time_block=%d outer_block=%d outer_overlap=%d" % (tb, ob, ov))
     prob, o, Jref = c1_oracle
-    s = make_solver(prob, time_block=tb, outer_block=ob)
+    s = make_solver(prob, time_block=tb, outer_block=ob, outer_overlap=ov)
+    assert s.info()["outer_overlap"] == (1 if ov == 2 else 0)
     if tb < 0:
         info = s.info()
         say("  timed choice: time block %d, outer block %d" % (info["time_block"], info["outer_block"]))
@@ -232,6 +235,47 @@ def test_march_short_support(torch_cuda, tb, ob):
     say("  ell", s.ell, "rel L2", err)
     assert err <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("tb,ob", [(4, 8), (4, 16), (8, 16)])
+def test_overlapped_outer_level_matches_oracle(torch_cuda, tb, ob):
+    """The outer level on the second stream, on a 20 x 3 x 3 bar (ell = 22, so the sums formed
+    there reach lags 9 .. 22 with outer blocks of 8 and 17 .. 22 with 16) over 120 steps:
+    J(t) against the oracle (<= 1e-8) and against the in-line outer level (the same terms
+    grouped differently: <= 1e-11), and a second march after mj_reset repeats the first bit
+    for bit (the reset forgets the sums formed for the next block)."""
+    from oracle import mot
+    torch = torch_cuda
+    U, V, W, n = 20, 3, 3, 120
+    say("overlapped outer level 20x3x3 time_block=%d outer_block=%d" % (tb, ob))
+    eps = wl.random_eps(U, V, W, 23, 2.0, 9.0)
+    k, p = wl.XPOL_PLUS_Z
+    prob = wl.Problem("bar", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 3.0)], n,
+                      fir=wl.binomial_highpass(5, 0.05))
+    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    ref = mot.Oracle(prob, K=K).run(n)
+    out = {}
+    for ov in (1, 2):
+        s = make_solver(prob, time_block=tb, outer_block=ob, outer_overlap=ov)
+        assert s.ell == 22 and s.info()["outer_overlap"] == (ov == 2)
+        J = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+        s.run(n, J)
+        if ov == 2:
+            st = s.stats()
+            say("  launches on the second stream timed", st["side_launches"], "mean ms", st["side_launch_ms"])
+            s.reset()
+            J2 = torch.zeros_like(J)
+            s.run(n, J2)
+            torch.cuda.synchronize()
+            assert torch.equal(J, J2)
+        torch.cuda.synchronize()
+        out[ov] = J.cpu().numpy()[:, 0]
+        s.close()
+    e_or = _rel(out[2], ref)
+    e_in = _rel(out[2], out[1])
+    say("  vs oracle", e_or, "vs in line", e_in)
+    assert e_or <= 1e-8
+    assert e_in <= 1e-11
 
 
 def _three_waves(U, V, W):
@@ -578,14 +622,16 @@ def adjoint_oracle():
     return prob, probes, phi, grad
 
 
-@pytest.mark.parametrize("tb,ckpt,ob", [(1, 0, 0), (1, 9, 0), (8, 0, 0), (8, 9, 0), (16, 5, 0), (8, 9, 16), (4, 0, 8)])
-def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt, ob):
+@pytest.mark.parametrize("tb,ckpt,ob,ov", [(1, 0, 0, 0), (1, 9, 0, 0), (8, 0, 0, 0), (8, 9, 0, 0), (16, 5, 0, 0),
+                                          (8, 9, 16, 0), (4, 0, 8, 0), (4, 9, 8, 2)])
+def test_adjoint_gradient_matches_oracle(torch_cuda, adjoint_oracle, tb, ckpt, ob, ov):
     """Phi and dPhi/deps_r of every voxel (one with eps_r = 1) from the transposed march,
-    with and without checkpoint/recompute segments, against the oracle's direct adjoint."""
+    with and without checkpoint/recompute segments, against the oracle's direct adjoint
+    (ov = 2: the outer level on the second stream, forward and transposed)."""
     torch = torch_cuda
     prob, probes, phi_ref, grad_ref = adjoint_oracle
-    say("adjoint 5x4x3 time_block=%d ckpt_every=%d outer_block=%d" % (tb, ckpt, ob))
-    s = make_solver(prob, time_block=tb, outer_block=ob)
+    say("adjoint 5x4x3 time_block=%d ckpt_every=%d outer_block=%d outer_overlap=%d" % (tb, ckpt, ob, ov))
+    s = make_solver(prob, time_block=tb, outer_block=ob, outer_overlap=ov)
     s.set_probes(probes)
     g = torch.zeros((prob.W, prob.V, prob.U), dtype=torch.float64, device="cuda")
     phi = s.adjoint_gradient(prob.n_steps, g, ckpt)
@@ -922,12 +968,13 @@ def test_C2_steps_satisfy_the_march_equation(torch_cuda):
 _RESTRICTED_104 = {}
 
 
-@pytest.mark.parametrize("time_block", [0, 8])
-def test_full_size_104_march_matches_oracle(torch_cuda, time_block):
+@pytest.mark.parametrize("time_block,ov", [(0, 0), (8, 0), (0, 2)])
+def test_full_size_104_march_matches_oracle(torch_cuda, time_block, ov):
     """The march at full size: the 104^3 grid (208^3 pads, ell = 182, the 17-tap FIR with
     delta = 0.01, the 104^3 workload's plane wave), with eps_r = 1 except four 2^3 blocks
     (eps_r 12, 6, 9, 4) 95 to 162 voxels apart, in the default time division that bench.py times
-    (blocks of 4 inside outer blocks of 16) and in blocks of 8.  400 steps: the ring of 182
+    (blocks of 4 inside outer blocks of 16; ov = 2 with the outer level on the second stream)
+    and in blocks of 8.  400 steps: the ring of 182
     spectra wraps twice, every position in a block of 16 recurs 25 times, and the blocks couple
     through lags 93 to 165, which only the far parts of the history sum carry.  J(t) of the 32
     block voxels over all steps against the oracle's dense march restricted to them (exact,
@@ -948,11 +995,12 @@ def test_full_size_104_march_matches_oracle(torch_cuda, time_block):
     vox = np.array(vox)
     p.eps = eps
     n, chunk = 400, 50
-    say("104^3 march parity, time_block %d: create" % time_block)
-    s = make_solver(p, time_block=time_block)
+    say("104^3 march parity, time_block %d, outer_overlap %d: create" % (time_block, ov))
+    s = make_solver(p, time_block=time_block, outer_overlap=ov)
     info = s.info()
     assert s.ell == 182 and info["Nx"] == 208
     assert (info["time_block"], info["outer_block"]) == ((4, 16) if time_block == 0 else (8, 0))
+    assert info["outer_overlap"] == (ov == 2)
     J = torch.zeros((chunk, 1, 3, U, U, U), dtype=torch.float64, device="cuda")
     iu, iv, iw = (torch.tensor(vox[:, i], device="cuda") for i in range(3))
     got, outside = [], 0
@@ -1001,6 +1049,47 @@ def test_short_step_generator_matches_oracle(torch_cuda, UVW, r):
     say("  ell", ell, "worst / max|K|", worst)
     assert worst <= 1e-12
     s.close()
+
+
+def test_two_solvers_keep_their_own_stencil(torch_cuda):
+    """Two solvers alive together whose K_0 differ (c dt = h and c dt = h/2, both with the CG
+    solve and with the gradient term that applies K_0): marching them in turn gives each the
+    currents and the gradient it gives alone, bit for bit."""
+    torch = torch_cuda
+    U, V, W, n = 5, 4, 4, 30
+    say("two solvers with different K_0")
+    eps = wl.random_eps(U, V, W, 3, 2.0, 6.0)
+    k, p = wl.XPOL_PLUS_Z
+    probs = []
+    for r in (1.0, 0.5):
+        pr = wl.Problem("stencil", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 3.0)], n,
+                        fir=wl.binomial_highpass(5, 0.05), c_dt=r)
+        probs.append(pr)
+    probes = wl.fibonacci_sphere(2, 4.0, (U / 2, V / 2, W / 2))
+
+    def march(s):
+        J = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
+        s.run(n, J)
+        s.reset()
+        g = torch.zeros((W, V, U), dtype=torch.float64, device="cuda")
+        s.adjoint_gradient(n, g, 0)
+        torch.cuda.synchronize()
+        return J, g
+    alone = []
+    for pr in probs:
+        s = make_solver(pr, z0_solver=1)
+        s.set_probes(probes)
+        alone.append(march(s))
+        s.close()
+    both = [make_solver(pr, z0_solver=1) for pr in probs]
+    for s in both:
+        s.set_probes(probes)
+    got = [march(both[0]), march(both[1])]
+    got[0] = march(both[0])      # again, after the other solver ran
+    for (Ja, ga), (Jb, gb) in zip(alone, got):
+        assert torch.equal(Ja, Jb) and torch.equal(ga, gb)
+    for s in both:
+        s.close()
 
 
 def test_short_step_march_and_probes_match_oracle(torch_cuda):
@@ -1127,15 +1216,18 @@ def test_prism_voxel_march_probes_and_gradient_match_oracle(torch_cuda):
 
 
 # ----------------------------------------------------------------------------- checkpoint / resume
-@pytest.mark.parametrize("tb,with_probes,ob", [(8, True, 0), (1, False, 0), (16, False, 0), (8, True, 16)])
-def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes, ob):
+@pytest.mark.parametrize("tb,with_probes,ob,ov", [(8, True, 0, 0), (1, False, 0, 0), (16, False, 0, 0),
+                                                 (8, True, 16, 0), (4, True, 8, 2)])
+def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes, ob, ov):
     """mj_get_state after 37 steps (inside a time block), mj_set_state on a fresh solver of the
     same configuration: the next 53 steps repeat the uninterrupted march bit for bit (currents
-    and probe field).  A state from another time block or a cut buffer is refused."""
+    and probe field; with ov = 2 the restored solver forms the outer sums of the next block
+    in line, as the second stream would have).  A state from another time block or a cut
+    buffer is refused."""
     from paper_2407_03323_amd.motjvie import MJ_EINVAL, MotJvieError
     torch = torch_cuda
     U, V, W, n1, N = 6, 5, 4, 37, 90
-    say("checkpoint/resume tb=%d probes=%s outer=%d" % (tb, with_probes, ob))
+    say("checkpoint/resume tb=%d probes=%s outer=%d overlap=%d" % (tb, with_probes, ob, ov))
     eps = wl.random_eps(U, V, W, 41, 2.0, 9.0)
     k, p = wl.XPOL_PLUS_Z
     prob = wl.Problem("resume", U, V, W, eps, [wl.gaussian_wave(U, V, W, k, p, 2.0)], N,
@@ -1144,7 +1236,7 @@ def test_state_checkpoint_resumes_bit_for_bit(torch_cuda, tb, with_probes, ob):
     npb = len(probes) if with_probes else 0
 
     def solver(tb_=tb, ob_=ob):
-        s_ = make_solver(prob, time_block=tb_, outer_block=ob_)
+        s_ = make_solver(prob, time_block=tb_, outer_block=ob_, outer_overlap=ov)
         if with_probes:
             s_.set_probes(probes)
         return s_
