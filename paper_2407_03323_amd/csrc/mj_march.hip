@@ -521,7 +521,8 @@ void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st)
     const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     const dim3 grid((unsigned)((nocts + 31) / 32 * a.nrhs)), blk(256);
     // second argument: lags in flight; the register file holds two at 8 targets, one above
-    // (166 to 238 VGPRs, two waves per SIMD)
+    // (166 to 238 VGPRs, two waves per SIMD).  At 16 targets two lags in flight also fit (256
+    // VGPRs) but ran 16.3 against 15.5 ms per launch at 104^3
     switch (tb) {
     case 4: hipLaunchKernelGGL((k_mac_win<4, 2, 3>), grid, blk, 0, st, a); break;
     case 8: hipLaunchKernelGGL((k_mac_win<8, 2, 2>), grid, blk, 0, st, a); break;
