@@ -391,12 +391,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     double k0s[KS], k1s[KS], k2s[KS], k3s[KS], k4s[KS], k5s[KS];   // xx yy zz xy xz yz
 #pragma unroll
     for (int s = 0; s < W; s++) jx[s] = jy[s] = jz[s] = 0.0;   // sources before the first lag are zero
-    // the loads of lag k into source slot js and kernel slot ks (lags beyond kmax load nothing)
+    // the loads of lag k into a source slot and a kernel slot.  With many lags (UL: 10 targets or
+    // more) every call issues the same six loads, so that the wait before each lag's arithmetic
+    // counts only the loads issued after its own (a load skipped on some path makes the compiler
+    // wait for all of them): lags beyond kmax reload lag kmax, whose values no target uses, and a
+    // source before jlo reads a valid slot and is replaced by zero.  The middle level's short
+    // launches (4 targets, at most 15 lags, 3 of them without a source) skip those loads instead.
+    constexpr bool UL = TG >= 10;
     auto load = [&](int k, double &vx, double &vy, double &vz, double &c0, double &c1, double &c2, double &c3,
                     double &c4, double &c5) __attribute__((always_inline)) {
-        if (k > kmax) return;
-        const int j = nb - k;
-        if (j >= jlo) {
+        if (!UL && k > kmax) return;
+        const int kk = UL ? min(k, kmax) : k;
+        const int j = nb - kk;
+        const bool ok = j >= jlo;
+        if (UL) {
+            const char *J = Jbase + ring_slot(ok ? j : jlo, a.ring) * slot_bytes + joff;
+            const double x = *(const double *)J;
+            const double y = *(const double *)(J + plane_bytes);
+            const double z = *(const double *)(J + 2 * plane_bytes);
+            vx = ok ? x : 0.0;
+            vy = ok ? y : 0.0;
+            vz = ok ? z : 0.0;
+        } else if (ok) {
             const char *J = Jbase + ring_slot(j, a.ring) * slot_bytes + joff;
             vx = *(const double *)J;
             vy = *(const double *)(J + plane_bytes);
@@ -404,7 +420,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         } else {
             vx = vy = vz = 0.0;
         }
-        const double2 *K2 = (const double2 *)(Kbase + (long)(k - 1) * klag_bytes + koff);
+        const double2 *K2 = (const double2 *)(Kbase + (long)(kk - 1) * klag_bytes + koff);
         const double2 v0 = K2[0], v1 = K2[1], v2 = K2[2];
         c0 = v0.x;
         c1 = v0.y;
@@ -420,10 +436,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     auto step = [&](auto ic, int k0, bool guard) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
         const int k = k0 + i;
-        if (guard && k > kmax) return;
         constexpr int ls = (1 + i + PD) % W, lk = (1 + i + PD) % KS, ck = (1 + i) % KS;
+        if (!UL && guard && k > kmax) return;
         load(k + PD, jx[ls], jy[ls], jz[ls], k0s[lk], k1s[lk], k2s[lk], k3s[lk], k4s[lk], k5s[lk]);
         __builtin_amdgcn_sched_barrier(0);
+        if (UL && guard && k > kmax) return;
         const double kxx = k0s[ck], kyy = k1s[ck], kzz = k2s[ck];
         const double kxy = k3s[ck] * sy, kxz = k4s[ck] * sz, kyz = k5s[ck] * sy * sz;
         [&]<int... T>(std::integer_sequence<int, T...>) __attribute__((always_inline)) {
