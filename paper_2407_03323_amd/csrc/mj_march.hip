@@ -587,10 +587,15 @@ __device__ inline double wave_average(const WaveArg &w, const EpiArg &e, int u, 
     return w.amp * sum;
 }
 
+// Coefficients every lane reads alike (the K_0 stencil, the FIR taps) through the scalar cache:
+// a pointer into the constant address space makes them scalar loads
+typedef __attribute__((address_space(4))) const double kconst_t;
+__device__ inline kconst_t *kconst(const double *p) { return (kconst_t *)p; }
+
 // b = E_n - P_{n-1} with P_{n-1} = sum_k c_k J_{n-k} - chi (K (*) J)  (eq:MOTInversion, eq:PnMOT);
 // c_1 = T(dt)/eps + delta_1, c_k = delta_k (k >= 2).  Writes the right-hand side of the
 // symmetrised system (b / sqrt(chi)) and the extrapolated initial guess
-// y0 = 3 y_{n-1} - 3 y_{n-2} + y_{n-3}, y = J / sqrt(chi).
+// y0 = sum_{k=1}^{nguess} gx_k y_{n-k}, y = J / sqrt(chi).
 __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
 {
     const long M = e.M;
@@ -616,20 +621,36 @@ __global__ void __launch_bounds__(256) k_epilogue(EpiArg e)
     const double c1 = 0.5 * e.inv_eps[i] + (e.nfir > 1 ? e.fir[1] : 0.0);
     const int kmax = min(e.nloc, e.n - 1);   // lags with a past current
     // initial guess of the Z_0 solve: the polynomial through the last nguess solutions,
-    // evaluated at step n (the current is smooth in time, so this lands close to y_n)
+    // evaluated at step n (the current is smooth in time, so this lands close to y_n).  The
+    // three components of a past current are read together, eight lags at a time, and the
+    // taps come through the scalar cache; each component still sums its lags in order.
+    double b[3], g[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int c = 0; c < 3; c++) {
         const long o = ((long)r * 3 + c) * M + i;
-        double b = chi * (avg * w.pol[c] + (e.S ? e.S[o] : 0.0));
-        double g = 0.0;
-#pragma unroll 4
-        for (int k = 1; k <= kmax; k++) {
-            const double jv = e.Jring[(((long)e.slot_of[k] * e.nrhs + r) * 3 + c) * M + i];
-            const double ck = (k == 1) ? c1 : (k < e.nfir ? e.fir[k] : 0.0);
-            b -= ck * jv;
-            if (k <= e.nguess) g += e.gx[k - 1] * jv;
+        b[c] = chi * (avg * w.pol[c] + (e.S ? e.S[o] : 0.0));
+    }
+    kconst_t *fir = kconst(e.fir);
+#pragma unroll 8
+    for (int k = 1; k <= kmax; k++) {
+        const double *J = e.Jring + ((long)e.slot_of[k] * e.nrhs + r) * 3 * M + i;
+        const double j0 = J[0], j1 = J[M], j2 = J[2 * M];
+        const double ck = (k == 1) ? c1 : (k < e.nfir ? fir[k] : 0.0);
+        b[0] -= ck * j0;
+        b[1] -= ck * j1;
+        b[2] -= ck * j2;
+        if (k <= e.nguess) {
+            const double gk = e.gx[k - 1];
+            g[0] += gk * j0;
+            g[1] += gk * j1;
+            g[2] += gk * j2;
         }
-        const double y0 = g / sc;
-        e.rhs[o] = b / sc;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const long o = ((long)r * 3 + c) * M + i;
+        const double y0 = g[c] / sc;
+        e.rhs[o] = b[c] / sc;
         e.y[o] = y0;
         e.uy[((long)r * 3 + c) * Mp + ip] = sc * y0;
     }
@@ -682,10 +703,6 @@ void launch_history_local(const double *Jh, int depth, const double *S, const do
 // them in block order and stores the scalars, so the results do not depend on scheduling.  The
 // same kernel takes the convergence test and keeps the status record, and the iteration kernels
 // read its outcome (CgScalars::conv) from the previous launch.
-// The K_0 stencil through the scalar cache: every lane reads the same entries, and a pointer
-// into the constant address space makes them scalar loads
-typedef __attribute__((address_space(4))) const double kconst_t;
-__device__ inline kconst_t *kconst(const double *p) { return (kconst_t *)p; }
 
 // sum_{D} K_0(D) u(m - D) at haloed index ip (the halo of u is zero, so no bounds tests);
 // ctr receives u(m) itself
