@@ -31,6 +31,20 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Division by a divisor that is the same in every lane (a tile or plan size), by one multiply:
+// for x < 2^16 and 1 <= d <= 2^16, floor(x / d) = floor(x m / 2^32) with m = floor(2^32 / d) + 1,
+// since x m / 2^32 exceeds x / d by less than 2^-16 and the fraction of x / d is at most
+// 1 - 1/d.  Building m is scalar work (d is uniform); the per-element quotient replaces the
+// reciprocal-and-correct sequence of a division by a run-time divisor, which dominated the
+// integer work of the index arithmetic.  Every index divided here is below 2^16.
+struct FastDiv {
+    unsigned d;
+    unsigned long long m;
+    __device__ explicit FastDiv(unsigned dv) : d(dv), m((1ull << 32) / dv + 1) {}
+    __device__ unsigned div(unsigned x) const { return (unsigned)(((unsigned long long)x * m) >> 32); }
+    __device__ unsigned mod(unsigned x) const { return x - div(x) * d; }
+};
+
 __device__ inline double2 tw_at(const double2 *tw, int m, bool inv)
 {
     double2 w = tw[m];
@@ -122,12 +136,13 @@ __device__ void stage(double2 *buf, int N, int Ns, int P, int ld, const double2 
     const int nb = N / R;
     const int step = N / (Ns * R);
     const int total = P * nb;
+    const FastDiv fnb(nb), fns(Ns);
     double2 v[BF][R];
 #pragma unroll
     for (int f = 0; f < BF; f++) {
         const int b = (int)threadIdx.x + f * kThreads;
         if (b < total) {
-            const int p = b / nb, j = b - p * nb, jm = j % Ns;
+            const int p = fnb.div(b), j = b - p * nb, jm = fns.mod(j);
             const double2 *s = buf + p * ld;
 #pragma unroll
             for (int r = 0; r < R; r++) v[f][r] = s[j + r * nb];
@@ -141,8 +156,8 @@ __device__ void stage(double2 *buf, int N, int Ns, int P, int ld, const double2 
     for (int f = 0; f < BF; f++) {
         const int b = (int)threadIdx.x + f * kThreads;
         if (b < total) {
-            const int p = b / nb, j = b - p * nb, jm = j % Ns;
-            const int base = (j / Ns) * Ns * R + jm;
+            const int p = fnb.div(b), j = b - p * nb, jq = fns.div(j), jm = j - jq * Ns;
+            const int base = jq * Ns * R + jm;
             double2 *d = buf + p * ld;
 #pragma unroll
             for (int r = 0; r < R; r++) d[base + r * Ns] = v[f][r];
@@ -232,20 +247,21 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
     double2 *a = sm + N;
     load_twiddles(tw_s, tw, N);
     const int row0 = (int)xcd_block(blockIdx.x, gridDim.x) * (2 * P);
+    const FastDiv fN(N), fU(U), fH(Hx);
     // load: pencil p takes rows row0 + 2p (real part) and row0 + 2p + 1 (imaginary part)
     for (int i = threadIdx.x; i < P * N; i += blockDim.x) {
-        int p = i / N, n = i - p * N;
+        int p = fN.div(i), n = i - p * N;
         a[p * ld + n] = make_double2(0.0, 0.0);
     }
     __syncthreads();
     gather_tile<double>(
         2 * P * U,
         [&](int i) {
-            const int rr = i / U, u = i - rr * U, row = row0 + rr;
+            const int rr = fU.div(i), u = i - rr * U, row = row0 + rr;
             return row < nrows ? x[(size_t)row * U + u] : 0.0;
         },
         [&](int i, double v) {
-            const int rr = i / U, u = i - rr * U;
+            const int rr = fU.div(i), u = i - rr * U;
             double2 *slot = &a[(rr >> 1) * ld + u];
             if (rr & 1) slot->y = v; else slot->x = v;
         });
@@ -254,11 +270,11 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_fwd(const double *__restrict
     const double2 *res = a;
     // separate: Xa[k] = (Z[k] + conj Z[N-k]) / 2, Xb[k] = (Z[k] - conj Z[N-k]) / (2i)
     for (int i = threadIdx.x; i < 2 * P * Hx; i += blockDim.x) {
-        int rr = i / Hx, k = i - rr * Hx;
+        int rr = fH.div(i), k = i - rr * Hx;
         int row = row0 + rr;
         if (row >= nrows) continue;
         const double2 *Z = res + (rr >> 1) * ld;
-        double2 z1 = Z[k], z2 = Z[(N - k) % N];
+        double2 z1 = Z[k], z2 = Z[k == 0 ? 0 : N - k];
         double2 o;
         if (rr & 1) o = make_double2(0.5 * (z1.y + z2.y), -0.5 * (z1.x - z2.x));
         else o = make_double2(0.5 * (z1.x + z2.x), 0.5 * (z1.y - z2.y));
@@ -278,11 +294,12 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
     double2 *a = sm + N;
     load_twiddles(tw_s, tw, N);
     const int row0 = (int)xcd_block(blockIdx.x, gridDim.x) * (2 * P);
+    const FastDiv fN(N), fU(U);
     // Z[k] = Xa[k] + i Xb[k] for k <= N/2, Z[N-k] = conj(Xa[k]) + i conj(Xb[k]) for 0 < k < N/2
     gather_tile<double4>(
         P * N,
         [&](int i) {
-            const int p = i / N, n = i - p * N;
+            const int p = fN.div(i), n = i - p * N;
             const int ra = row0 + 2 * p, rb = ra + 1;
             const int k = n <= N / 2 ? n : N - n;
             double2 xa = make_double2(0, 0), xb = make_double2(0, 0);
@@ -291,7 +308,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
             return make_double4(xa.x, xa.y, xb.x, xb.y);
         },
         [&](int i, double4 v) {
-            const int p = i / N, n = i - p * N;
+            const int p = fN.div(i), n = i - p * N;
             double2 xa = make_double2(v.x, v.y), xb = make_double2(v.z, v.w);
             if (n > N / 2) {
                 xa.y = -xa.y;
@@ -303,7 +320,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_inv(const double2 *__restric
     lds_fft<MASK>(a, P, ld, pl, tw_s, true);
     const double2 *res = a;
     for (int i = threadIdx.x; i < 2 * P * U; i += blockDim.x) {
-        int rr = i / U, u = i - rr * U;
+        int rr = fU.div(i), u = i - rr * U;
         int row = row0 + rr;
         if (row >= nrows) continue;
         double2 z = res[(rr >> 1) * ld + u];
@@ -338,15 +355,16 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restr
     const int c = grp / g.nq, q = grp - c * g.nq;
     const int kx0 = tile * P;
     const int np = min(P, g.Hx - kx0);
+    const FastDiv fP(P);
     const double2 *src = in + c * g.cs_in + q * g.qs_in + kx0;
     gather_tile<double2>(
         P * N,
         [&](int i) {
-            const int n = i / P, p = i - n * P;
+            const int n = fP.div(i), p = i - n * P;
             return (n < g.n_in && p < np) ? src[(long)n * g.es_in + p] : make_double2(0.0, 0.0);
         },
         [&](int i, double2 v) {
-            const int n = i / P, p = i - n * P;
+            const int n = fP.div(i), p = i - n * P;
             a[p * ld + n] = v;
         });
     __syncthreads();
@@ -354,7 +372,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(const double2 *__restr
     const double2 *res = a;
     double2 *dst = out + c * g.cs_out + q * g.qs_out + kx0;
     for (int i = threadIdx.x; i < P * g.n_out; i += blockDim.x) {
-        int n = i / P, p = i - n * P;
+        int n = fP.div(i), p = i - n * P;
         if (p < np) dst[(long)n * g.es_out + p] = res[p * ld + n];
     }
 }
@@ -372,15 +390,18 @@ int pencils_per_block(int N) { return std::max(1, std::min(16, kTileElems / N));
 
 size_t lds_bytes(int N, int P) { return sizeof(double2) * (size_t)(N + P * (N + 1)); }
 
+// Radices of the stages, in order.  The first stage (Ns = 1) writes its R outputs with a stride
+// of R complex values in LDS, so an odd radix goes first: a stride of 13 x 16 bytes spreads the
+// lanes over every bank, where a stride of 4 x 16 bytes puts four lanes on each bank group.
+// Later stages write runs of Ns consecutive values.  Then radix 4 as often as possible, and 2.
 bool factor(int N, std::vector<int> &out)
 {
     out.clear();
     int n = N;
-    // prefer radix 4 (then 8 for leftovers of 2s), then the odd radices
+    for (int r : {13, 11, 7, 5, 3})
+        while (n % r == 0) { out.push_back(r); n /= r; }
     while (n % 4 == 0) { out.push_back(4); n /= 4; }
     while (n % 2 == 0) { out.push_back(2); n /= 2; }
-    for (int r : {3, 5, 7, 11, 13})
-        while (n % r == 0) { out.push_back(r); n /= r; }
     return n == 1 && (int)out.size() <= kMaxStages;
 }
 
