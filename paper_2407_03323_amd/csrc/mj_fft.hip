@@ -481,7 +481,7 @@ void fft3d_free(Fft3D &f)
 }
 
 // Radix set of a plan, and the kernel instance that serves it: the sets of the usual padded
-// sizes (208 = 4 4 13; powers of two; 2^k 3) have their own instances, any other plan the
+// sizes (208 = 13 4 4; powers of two; 3 2^k) have their own instances, any other plan the
 // generic one.
 static int plan_mask(const FftPlan1D &p)
 {
