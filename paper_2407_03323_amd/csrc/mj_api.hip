@@ -835,6 +835,8 @@ mj::EpiArg mj_solver::epi_arg() const
 {
     mj::EpiArg e{};
     e.k0 = k0_d;
+    for (const mj::WaveArg &w : waves)
+        if ((w.k[0] != 0.0) + (w.k[1] != 0.0) + (w.k[2] != 0.0) >= 2) e.oblique = 1;
     e.M = M;
     e.U = U;
     e.V = V;

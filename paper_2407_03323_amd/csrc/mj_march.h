@@ -64,6 +64,7 @@ struct EpiArg {
     const double *G;         // adjoint source g_j [nrhs][3][M]
     double *bq;              // b'_j, kept for the voxels with chi = 0 [nrhs][3][M]
     const double *k0;        // the solver's K_0 stencil (the gradient term B_n)
+    int oblique;             // some wave has two or more non-zero direction components
 };
 
 // Adjoint of the probe objective and the eps-gradient (see mj_march.hip).
