@@ -88,7 +88,7 @@ def test_binding_config_matches_header():
 
 
 @pytest.mark.parametrize("case", ["grid", "cdt", "cdt_small", "edge_short", "edge_long", "eps", "rhs", "pencils",
-                                  "alloc_only", "null"])
+                                  "alloc_only", "z0_solver", "outer_overlap", "outer_block", "null"])
 def test_create_rejects_invalid_arguments(lib, case):
     from paper_2407_03323_amd.motjvie import MJ_EINVAL
     h = ctypes.c_void_p()
@@ -118,6 +118,15 @@ def test_create_rejects_invalid_arguments(lib, case):
         fn = ALLOC_FN(lambda nbytes, ctx: None)     # an allocator without its free_
         c.alloc = fn
         keep = (keep, fn)
+    elif case == "z0_solver":
+        c, keep = _cfg()
+        c.z0_solver = 3
+    elif case == "outer_overlap":
+        c, keep = _cfg()
+        c.outer_overlap = 3
+    elif case == "outer_block":
+        c, keep = _cfg()
+        c.time_block, c.outer_block = 4, 10       # not a multiple of the time block
     else:
         c, keep = _cfg(n_rhs=0)
     assert lib.mj_create(ctypes.byref(c), ctypes.byref(h)) == MJ_EINVAL
