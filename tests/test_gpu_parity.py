@@ -286,21 +286,22 @@ def _three_waves(U, V, W):
     return [wl.gaussian_wave(U, V, W, np.array(d), np.array(q), s_) for d, q, s_ in zip(dirs, pols, sig)]
 
 
-@pytest.mark.parametrize("tb,ob", [(1, 0), (8, 0), (16, 0), (8, 16)])
-def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob):
+@pytest.mark.parametrize("tb,ob,ov", [(1, 0, 0), (8, 0, 0), (16, 0, 0), (8, 16, 0), (4, 8, 2)])
+def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob, ov):
     """Three right-hand sides marched together: each equals its own single-RHS march and the
     oracle's march.  The batch shares every launch, and its Z_0 solve runs as many Chebyshev
     passes as its slowest right-hand side needs, so a batched current differs from its single
-    march by what the solve tolerance allows (1e-13 in the residual), not more."""
+    march by what the solve tolerance allows (1e-13 in the residual), not more.  ov = 2 runs
+    the outer level on the second stream, whose sums are laid out per right-hand side too."""
     from oracle import mot
     torch = torch_cuda
     U, V, W, n = 6, 5, 4, 60
-    say("batched rhs 6x5x4 time_block=%d outer_block=%d" % (tb, ob))
+    say("batched rhs 6x5x4 time_block=%d outer_block=%d outer_overlap=%d" % (tb, ob, ov))
     eps = wl.random_eps(U, V, W, 5, 1.0, 8.0)
     waves = _three_waves(U, V, W)
     fir = wl.binomial_highpass(5, 0.1)
     prob = wl.Problem("batch", U, V, W, eps, waves, n, fir=fir)
-    s = make_solver(prob, time_block=tb, outer_block=ob)
+    s = make_solver(prob, time_block=tb, outer_block=ob, outer_overlap=ov)
     Jb = torch.zeros((n, 3, 3, W, V, U), dtype=torch.float64, device="cuda")
     s.run(n, Jb)
     torch.cuda.synchronize()
@@ -309,7 +310,7 @@ def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob):
     K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
     for i, w in enumerate(waves):
         p1 = wl.Problem("single", U, V, W, eps, [w], n, fir=fir)
-        s1 = make_solver(p1, time_block=tb, outer_block=ob)
+        s1 = make_solver(p1, time_block=tb, outer_block=ob, outer_overlap=ov)
         J1 = torch.zeros((n, 1, 3, W, V, U), dtype=torch.float64, device="cuda")
         s1.run(n, J1)
         torch.cuda.synchronize()
