@@ -25,6 +25,9 @@ constexpr long kChebMaxUnknowns = 1L << 19;
 
 // whether outer_overlap = 0 runs the outer level of three on the second stream
 constexpr bool kOverlapDefault = false;
+// LDS each block of the second stream's launch claims: above half of a CU's 160 KB, so that a
+// CU holds one such block (one wave per SIMD) and keeps room for the march's kernels
+constexpr size_t kSideLdsReserve = 96 * 1024;
 
 // ---------------------------------------------------------------------------- static staging
 // mj_kernel_values_noalloc stages its requests and results through this file-scope array
@@ -950,7 +953,7 @@ void mj_solver::outer_sums(int nb, hipStream_t stream)
     mj::BlockMacArg a = block_arg(hbuf, nb);
     a.ntarget = B2;
     a.jmax = nb - B2 - 1;
-    mj::launch_mac_win(a, B2, stream);
+    mj::launch_mac_win(a, B2, stream, stream == side ? kSideLdsReserve : 0);
 }
 
 // The outer level at the start nb of an outer block, overlapped (Sec. 4.1's division with the

@@ -180,7 +180,7 @@ void launch_adj_lambda(const AdjArg &a, hipStream_t st);
 void launch_grad_accum(const AdjArg &a, hipStream_t st);
 void launch_mac_near(const BlockMacArg &a, hipStream_t st);
 // far part with the rotation-free source window: tb = 4, 8, 10, 12, 14 or 16 targets
-void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st);
+void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st, size_t lds_reserve = 0);
 void launch_epilogue(const EpiArg &e, hipStream_t st);
 void launch_history_local(const double *Jh, int depth, const double *S, const double *chi, const double *inv_eps,
                           const double *fir, int nfir, long M, double *P, hipStream_t st);

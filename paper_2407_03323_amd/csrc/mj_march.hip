@@ -533,10 +533,19 @@ void launch_mac_far(const BlockMacArg &a, int tb, hipStream_t st)
     MJ_CHECK(hipGetLastError());
 }
 
-void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st)
+// lds_reserve: LDS bytes each block claims without using them, which caps the blocks a CU
+// holds at once (and so leaves room on every CU for other kernels running beside this one)
+void launch_mac_win(const BlockMacArg &a, int tb, hipStream_t st, size_t lds_reserve)
 {
     const long nocts = (long)a.Hp * (a.Ny / 2 + 1) * (a.Nz / 2 + 1);
     const dim3 grid((unsigned)((nocts + 31) / 32 * a.nrhs)), blk(256);
+    if (lds_reserve > 0 && tb == 16) {
+        MJ_CHECK(hipFuncSetAttribute((const void *)k_mac_win<16, 1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_reserve));
+        hipLaunchKernelGGL((k_mac_win<16, 1, 2>), grid, blk, lds_reserve, st, a);
+        MJ_CHECK(hipGetLastError());
+        return;
+    }
     // second argument: lags in flight; the register file holds two at 8 targets, one above
     // (166 to 238 VGPRs, two waves per SIMD).  At 16 targets two lags in flight also fit (256
     // VGPRs) but ran 16.3 against 15.5 ms per launch at 104^3
