@@ -90,6 +90,65 @@ struct Events {
 
 }  // namespace
 
+// n-point Gauss-Legendre rule on [-1/2, 1/2] (Newton on P_n from the Chebyshev-like start),
+// weights summing to 1
+static void gl_half(int n, double *x, double *w)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; i++) {
+        long double zz = cosl(pi * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int itn = 0; itn < 50; itn++) {
+            long double p0 = 1, p1 = zz;
+            for (int j = 2; j <= n; j++) {
+                long double p2 = ((2 * j - 1) * zz * p1 - (j - 1) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (zz * p1 - p0) / (zz * zz - 1);
+            long double d = p1 / dp;
+            zz -= d;
+            if (fabsl(d) < 1e-19L) break;
+        }
+        x[i] = n == 1 ? 0.0 : (double)(0.5L * zz);
+        w[i] = n == 1 ? 1.0 : (double)(1.0L / ((1 - zz * zz) * dp * dp));
+    }
+}
+
+// Gauss-Legendre order for averaging exp(-((T - k h x) / w)^2) over x in [-1/2, 1/2] with spread
+// s = |k| h / w: the least n <= 8 (the most the device tables hold) whose remainder bound
+// (n!)^4 / ((2n + 1) ((2n)!)^3) s^2n max|H_2n(x) exp(-x^2)|, with Cramer's bound
+// |H_m(x)| exp(-x^2 / 2) <= 1.0865 sqrt(2^m m!), stays below 2^-53, or 9 when none does.  0 spread takes the 1-point rule, which is then exact.
+static int gl_order(double s)
+{
+    if (s == 0.0) return 1;
+    for (int n = 1; n <= 8; n++) {
+        double f = 1.0, f2 = 1.0;
+        for (int i = 2; i <= n; i++) f *= i;
+        for (int i = 2; i <= 2 * n; i++) f2 *= i;
+        const double c = std::pow(f, 4) / ((2 * n + 1) * f2 * f2 * f2) * 1.0865 * std::sqrt(std::ldexp(f2, 2 * n));
+        if (c * std::pow(s, 2 * n) <= std::ldexp(1.0, -53)) return n;
+    }
+    return 9;
+}
+
+// The averaging plan of a wave with two or more non-zero direction components on voxels of
+// edges (h, hy, hz); see the fields of WaveArg.
+static void plan_wave(mj::WaveArg &w, double h, double hy, double hz)
+{
+    const double kh[3] = {w.k[0] * h, w.k[1] * hy, w.k[2] * hz};
+    int ax[3] = {0, 1, 2};
+    std::stable_sort(ax, ax + 3, [&](int a, int b) { return std::fabs(kh[a]) > std::fabs(kh[b]); });
+    int order[3];
+    for (int i = 0; i < 3; i++) {
+        w.kh[i] = kh[ax[i]];
+        order[i] = gl_order(std::fabs(kh[ax[i]]) / w.width);
+        w.nq[i] = std::min(order[i], 8);
+    }
+    // an erf pair costs about what 5 exponentials do
+    w.form = order[1] > 8 ? 2 : order[0] >= 6 ? 1 : 0;
+}
+
 struct mj_solver {
     // geometry and configuration
     int U = 0, V = 0, W = 0;
@@ -156,6 +215,7 @@ struct mj_solver {
     mj::GenResult gen{};
     double K0_27[27 * 6] = {};
     double *k0_d = nullptr;         // K0_27 on the device (the Z_0 stencil of this solver)
+    double *gl_d = nullptr;         // Gauss-Legendre rules of 1..8 points for the excitation
     int nblk = 1;
     int n = 0;
     int dev = 0;                    // device current at mj_create
@@ -426,6 +486,12 @@ void mj_solver::create(const mj_config &c)
     scal = dalloc<mj::CgScalars>(nrhs, "cg scalars");
     cgstat = dalloc<mj::CgStatus>(nrhs, "cg status");
     waves_d = dalloc<mj::WaveArg>(nrhs, "waves");
+    {
+        double rules[9 * 16] = {};
+        for (int n = 1; n <= 8; n++) gl_half(n, rules + 16 * n, rules + 16 * n + 8);
+        gl_d = dalloc<double>(9 * 16, "quadrature rules");
+        MJ_CHECK(hipMemcpy(gl_d, rules, sizeof rules, hipMemcpyHostToDevice));
+    }
     MJ_CHECK(hipHostMalloc((void **)&cgstat_h, sizeof(mj::CgStatus) * nrhs, hipHostMallocDefault));
     mj::fft3d_init(fft, U, V, W, 3 * nrhs, Nx, Ny, Nz, da);
     bytes += sizeof(double2) * ((size_t)3 * nrhs * W * V * Hp + (size_t)3 * nrhs * W * Ny * Hp);
@@ -811,29 +877,6 @@ void mj_solver::solve_z0_chebyshev()
 }
 
 // 8-point Gauss-Legendre on [-1/2, 1/2] (weights summing to 1), long double Newton
-static void gl8_half(double *x, double *w)
-{
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int i = 0; i < 8; i++) {
-        long double zz = cosl(pi * (i + 0.75L) / 8.5L);
-        long double dp = 0;
-        for (int itn = 0; itn < 50; itn++) {
-            long double p0 = 1, p1 = zz;
-            for (int j = 2; j <= 8; j++) {
-                long double p2 = ((2 * j - 1) * zz * p1 - (j - 1) * p0) / j;
-                p0 = p1;
-                p1 = p2;
-            }
-            dp = 8 * (zz * p1 - p0) / (zz * zz - 1);
-            long double d = p1 / dp;
-            zz -= d;
-            if (fabsl(d) < 1e-19L) break;
-        }
-        x[i] = (double)(0.5L * zz);
-        w[i] = (double)(1.0L / ((1 - zz * zz) * dp * dp));
-    }
-}
-
 mj::EpiArg mj_solver::epi_arg() const
 {
     mj::EpiArg e{};
@@ -867,7 +910,8 @@ mj::EpiArg mj_solver::epi_arg() const
     }
     e.Jring = Jr;
     e.waves = waves_d;
-    gl8_half(e.glx8, e.glw8);
+    gl_half(8, e.glx8, e.glw8);
+    e.gl = gl_d;
     e.rhs = rhs;
     e.y = y;
     e.uy = uy;
@@ -1891,6 +1935,7 @@ int mj_set_plane_waves(mj_solver *s, const double *khat, const double *pol, cons
             w[i].width = width[i];
             w[i].ct0 = ct0[i];
             w[i].amp = amp[i];
+            plan_wave(w[i], s->h, s->hy, s->hz);
         }
         MJ_CHECK(hipMemcpy(s->waves_d, w.data(), sizeof(mj::WaveArg) * s->nrhs, hipMemcpyHostToDevice));
         s->waves = w;

@@ -38,6 +38,14 @@ struct BlockMacArg {
 struct WaveArg {
     double k[3], pol[3], rref[3];
     double width, ct0, amp;
+    // How the voxel average of a wave with two or more non-zero direction components is taken
+    // (set by the host from the spreads |k_i| h_i / width): the axes by decreasing spread enter
+    // as their products k_i h_i, each with the Gauss-Legendre order that bounds its error by 2^-53
+    // of the amplitude, and form 0 takes the rule on all three, 1 erf on the widest and the rule
+    // on the other two, 2 the two widest in closed form and the rule on the third.
+    double kh[3];
+    int nq[3];
+    int form;
 };
 
 struct EpiArg {
@@ -57,6 +65,7 @@ struct EpiArg {
     const double *S;         // [nrhs][3][M] convolution (normalised) or NULL at n = 1
     const WaveArg *waves;    // [nrhs]
     double glx8[8], glw8[8]; // 8-point rule on [-1/2, 1/2], weights summing to 1
+    const double *gl;        // n-point rules on [-1/2, 1/2], n = 1..8: row n holds 8 nodes then 8 weights
     double *rhs, *y;         // [nrhs][3][M]
     double *uy;              // sqrt(chi) y0 in the zero-haloed layout [nrhs][3][(W+2)(V+2)(U+2)]
     // transposed march only

@@ -570,52 +570,93 @@ void launch_mac_near(const BlockMacArg &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------- excitation
-// chi_m times the voxel average of a Gaussian plane wave at c t = n c dt (eq:E), with an
-// 8-point Gauss-Legendre rule along every axis on which the wave varies (the average over an
-// axis the wave does not depend on is the identity).
+// Coefficients every lane reads alike (the K_0 stencil, the FIR taps, the quadrature rules)
+// through the scalar cache: a pointer into the constant address space makes them scalar loads
+typedef __attribute__((address_space(4))) const double kconst_t;
+__device__ inline kconst_t *kconst(const double *p) { return (kconst_t *)p; }
+
+// chi_m times the voxel average of a Gaussian plane wave at c t = n c dt (eq:E).  The average
+// over an axis the wave does not depend on is the identity.  A wave along one axis takes the
+// 8-point Gauss-Legendre rule on it.  A wave with two or three non-zero components follows the
+// plan the host made from its spreads s_i = |k_i| h_i / w (w the pulse width):
+//  * form 0: on each axis the n-point rule with the least n whose remainder bound
+//    (n!)^4 / ((2n + 1) ((2n)!)^3) s^2n max|d^2n/dx^2n exp(-x^2)| (the Gauss-Legendre remainder,
+//    the derivative bounded by Cramer's inequality) stays below 2^-53; at 64^3 with a width of
+//    8.5 voxels that is 4 or 5 points an axis where the oracle's rule takes 8;
+//  * form 1, once the widest axis would need 6 points or more: that axis in closed form,
+//    (w sqrt(pi) / (2 k_a h_a)) (erf((T + k_a h_a / 2) / w) - erf((T - k_a h_a / 2) / w)), through
+//    erfc where both arguments lie in one tail, and the rule on the other two;
+//  * form 2, once the second widest spread is beyond what the 8-point rule integrates to 2^-53
+//    (pulses narrower than about 1.4 voxels): the two widest axes in closed form.  With
+//    c_a = k_a h_a / (2w), c_b likewise and t = T / w, their average is (sqrt(pi) / (8 c_a c_b))
+//    times the second difference G(t + c_b + c_a) - G(t + c_b - c_a) - G(t - c_b + c_a)
+//    + G(t - c_b - c_a) of G(z) = z erf(z) + exp(-z^2) / sqrt(pi) = |z| + ierfc(|z|), the
+//    antiderivative of erf, where ierfc(x) = exp(-x^2) / sqrt(pi) - x erfc(x).
+// Each form is within a few units in the last place of the exact average wherever the oracle's
+// 8-point rule is too, and more exact where the rule is not.  CF = false leaves the plan out of
+// the kernel (its registers slow the right-hand side when every wave runs along an axis); a
+// launch takes CF = true whenever one of its waves does not, and a wave along an axis takes the
+// same 8-point rule either way.
 template <bool CF>
 __device__ inline double wave_average(const WaveArg &w, const EpiArg &e, int u, int v, int z, double ct)
 {
     const double tc = ct - w.ct0 - ((u + 0.5) * e.h - w.rref[0]) * w.k[0] - ((v + 0.5) * e.hy - w.rref[1]) * w.k[1] -
                       ((z + 0.5) * e.hz - w.rref[2]) * w.k[2];
     const double iw = 1.0 / w.width;
-    // The axis along which the retarded time spreads most takes its average in closed form,
-    // (w sqrt(pi) / (2 k_a h_a)) (erf((T + k_a h_a / 2) / w) - erf((T - k_a h_a / 2) / w)), the
-    // other two the 8-point rule.  Against the rule on all three axes (the oracle's) this
-    // differs by that rule's error on one axis, below 1e-13 of the peak for widths down to h/2,
-    // and takes 64 evaluations of erf pairs where the rule takes 512 of exp.  A wave along an
-    // axis keeps the rule (8 of exp cost less than one erf pair), and so does a spread below
-    // 1e-3 widths on every axis.  CF = false leaves this path out of the kernel (its registers
-    // slow the right-hand side when every wave runs along an axis); a launch takes CF = true
-    // whenever one of its waves does not, so both forms give the same values.
     if (CF && (w.k[0] != 0.0) + (w.k[1] != 0.0) + (w.k[2] != 0.0) >= 2) {
-        // spread per axis, and the axes picked by selects (no indexed local arrays)
-        const double s0 = fabs(w.k[0]) * e.h, s1 = fabs(w.k[1]) * e.hy, s2 = fabs(w.k[2]) * e.hz;
-        const bool a0 = s0 >= s1 && s0 >= s2, a1 = !a0 && s1 >= s2;
-        const double sa = a0 ? s0 : a1 ? s1 : s2;
-        if (sa * iw >= 1e-3) {
-            const double kah = a0 ? w.k[0] * e.h : a1 ? w.k[1] * e.hy : w.k[2] * e.hz, half = 0.5 * kah;
-            const double d1 = a0 ? w.k[1] * e.hy : w.k[0] * e.h;                 // the other two axes
-            const double d2 = a0 || a1 ? w.k[2] * e.hz : w.k[1] * e.hy;
-            const int n1 = d1 != 0.0 ? 8 : 1, n2 = d2 != 0.0 ? 8 : 1;
+        kconst_t *ga = kconst(e.gl) + 16 * w.nq[0], *gb = kconst(e.gl) + 16 * w.nq[1];
+        kconst_t *gc = kconst(e.gl) + 16 * w.nq[2];
+        const int na = w.nq[0], nb = w.nq[1], nc = w.nq[2];
+        if (w.form == 2) {
+            const double ca = 0.5 * w.kh[0] * iw, cb = 0.5 * w.kh[1] * iw;
             double sum = 0.0;
-            for (int i = 0; i < n1; i++) {
-                const double o1 = n1 > 1 ? e.glx8[i] * d1 : 0.0, w1 = n1 > 1 ? e.glw8[i] : 1.0;
+            for (int l = 0; l < nc; l++) {
+                const double t = (tc - gc[l] * w.kh[2]) * iw;
+                const double z[4] = {fabs(t + cb + ca), fabs(t + cb - ca), fabs(t - cb + ca), fabs(t - cb - ca)};
+                // the |z| terms cancel exactly once all four arguments share a sign
+                double g = fabs(t) >= fabs(ca) + fabs(cb) ? 0.0 : (z[0] - z[1]) - (z[2] - z[3]);
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const double ie = 0.5641895835477563 * exp(-z[q] * z[q]) - z[q] * erfc(z[q]);
+                    g += (q == 0 || q == 3) ? ie : -ie;
+                }
+                sum += gc[8 + l] * g;
+            }
+            return w.amp * sum * (0.2215567313631895 / (ca * cb));   // sqrt(pi) / 8
+        }
+        if (w.form == 1) {
+            const double half = 0.5 * w.kh[0];
+            double sum = 0.0;
+            for (int i = 0; i < nb; i++) {
+                const double o1 = gb[i] * w.kh[1];
                 double sl = 0.0;
-                for (int j = 0; j < n2; j++) {
-                    const double o2 = n2 > 1 ? e.glx8[j] * d2 : 0.0, w2 = n2 > 1 ? e.glw8[j] : 1.0;
-                    const double T = tc - o1 - o2;
+                for (int j = 0; j < nc; j++) {
+                    const double T = tc - o1 - gc[j] * w.kh[2];
                     const double u1 = (T + half) * iw, u2 = (T - half) * iw;
                     // erf(u1) - erf(u2), through erfc where both lie in one tail
                     const double d = (u1 > 0.0 && u2 > 0.0)   ? erfc(u2) - erfc(u1)
                                      : (u1 < 0.0 && u2 < 0.0) ? erfc(-u1) - erfc(-u2)
                                                               : erf(u1) - erf(u2);
-                    sl += w2 * d;
+                    sl += gc[8 + j] * d;
                 }
-                sum += w1 * sl;
+                sum += gb[8 + i] * sl;
             }
-            return w.amp * sum * (0.8862269254527580 * w.width / kah);   // sqrt(pi) / 2
+            return w.amp * sum * (0.8862269254527580 * w.width / w.kh[0]);   // sqrt(pi) / 2
         }
+        double sum = 0.0;
+        for (int i = 0; i < na; i++) {
+            const double o0 = ga[i] * w.kh[0];
+            for (int j = 0; j < nb; j++) {
+                const double o1 = o0 + gb[j] * w.kh[1];
+                double sl = 0.0;
+                for (int l = 0; l < nc; l++) {
+                    const double x = (tc - o1 - gc[l] * w.kh[2]) * iw;
+                    sl += gc[8 + l] * exp(-x * x);
+                }
+                sum += ga[8 + i] * gb[8 + j] * sl;
+            }
+        }
+        return w.amp * sum;
     }
     const int nx = w.k[0] != 0.0 ? 8 : 1, ny = w.k[1] != 0.0 ? 8 : 1, nz = w.k[2] != 0.0 ? 8 : 1;
     double sum = 0.0;
@@ -634,11 +675,6 @@ __device__ inline double wave_average(const WaveArg &w, const EpiArg &e, int u, 
     }
     return w.amp * sum;
 }
-
-// Coefficients every lane reads alike (the K_0 stencil, the FIR taps) through the scalar cache:
-// a pointer into the constant address space makes them scalar loads
-typedef __attribute__((address_space(4))) const double kconst_t;
-__device__ inline kconst_t *kconst(const double *p) { return (kconst_t *)p; }
 
 // b = E_n - P_{n-1} with P_{n-1} = sum_k c_k J_{n-k} - chi (K (*) J)  (eq:MOTInversion, eq:PnMOT);
 // c_1 = T(dt)/eps + delta_1, c_k = delta_k (k >= 2).  Writes the right-hand side of the
