@@ -876,7 +876,6 @@ void mj_solver::solve_z0_chebyshev()
     cheb_pred = pred;
 }
 
-// 8-point Gauss-Legendre on [-1/2, 1/2] (weights summing to 1), long double Newton
 mj::EpiArg mj_solver::epi_arg() const
 {
     mj::EpiArg e{};
