@@ -324,18 +324,22 @@ def test_batched_rhs_matches_single_and_oracle(torch_cuda, tb, ob, ov):
         assert e_oracle <= 1e-8
 
 
-def test_excitation_forms_match_oracle(torch_cuda):
+@pytest.mark.parametrize("prism", [False, True])
+def test_excitation_forms_match_oracle(torch_cuda, prism):
     """The voxel average of eq:E for oblique waves takes one of three forms on the device,
     chosen per wave from its spreads |k_i| h_i / w: the Gauss-Legendre rule with a per-axis
     order (a wide pulse, 8.5 voxels), erf on the widest axis (3 voxels), or the two widest
     axes in closed form (a pulse of 0.6 voxels, where the oracle's own 8-point rule is off by
     about 3e-13 of the peak).  The four waves, one of them along an axis, run as one batch, and
     each matches the oracle's march, and the step where the current first reaches a tenth
-    of its peak to 1e-11."""
+    of its peak to 1e-11.  On 1 x 0.7 x 1.3 voxels (c dt = 0.6) the z axis has the widest spread
+    of the oblique waves, so the axes enter the forms in another order; the narrow pulse then
+    spans 1.6 widths along z, and the oracle's 8-point rule is off by about 5e-12 of the peak."""
     from oracle import mot
     torch = torch_cuda
     U, V, W, n = 6, 5, 4, 50
-    say("excitation forms 6x5x4, 4 waves")
+    geo = dict(c_dt=0.6, hy=PRISM[1], hz=PRISM[2]) if prism else {}
+    say("excitation forms 6x5x4, 4 waves, prism voxels" if prism else "excitation forms 6x5x4, 4 waves")
     eps = wl.random_eps(U, V, W, 8, 1.0, 6.0)
     d3 = np.array([-1.0, -1.0, -np.sqrt(2.0)]) / 2
     waves = [wl.gaussian_wave(U, V, W, d3, np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0), 6.0, delay_in_sigmas=3.0),
@@ -343,16 +347,19 @@ def test_excitation_forms_match_oracle(torch_cuda):
              wl.gaussian_wave(U, V, W, d3, np.array([0.0, np.sqrt(2.0), -1.0]) / np.sqrt(3.0), 0.4, delay_in_sigmas=20.0),
              wl.gaussian_wave(U, V, W, np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0]), 2.0)]
     fir = wl.binomial_highpass(5, 0.1)
-    prob = wl.Problem("forms", U, V, W, eps, waves, n, fir=fir)
+    prob = wl.Problem("forms", U, V, W, eps, waves, n, fir=fir, **geo)
     s = make_solver(prob, time_block=8)
     J = torch.zeros((n, 4, 3, W, V, U), dtype=torch.float64, device="cuda")
     s.run(n, J)
     torch.cuda.synchronize()
     J = J.cpu().numpy()
     s.close()
-    K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
+    if prism:
+        K = oracle_kernel_table(U, V, W, mot.ell(U, V, W, 1.0, 0.6, PRISM[1], PRISM[2]), r=0.6, hv=PRISM)
+    else:
+        K = oracle_kernel_table(U, V, W, mot.ell(U, V, W))
     for i, w in enumerate(waves):
-        ref = mot.Oracle(wl.Problem("one", U, V, W, eps, [w], n, fir=fir), K=K).run(n)
+        ref = mot.Oracle(wl.Problem("one", U, V, W, eps, [w], n, fir=fir, **geo), K=K).run(n)
         peak = np.abs(ref).reshape(n, -1).max(axis=1)
         first = int(np.argmax(peak >= 0.1 * peak.max()))   # the first step at a tenth of the peak
         e_all, e_first = _rel(J[:, i], ref), _rel(J[first, i], ref[first])
