@@ -97,8 +97,8 @@ typedef struct {
                                  preconditioner: 1 CG; 2 Chebyshev iteration on its spectrum, estimated at
                                  mj_create and mj_set_eps (one stencil pass per iteration and no inner
                                  products: fewer launches, more iterations); 0 Chebyshev up to 2^19 voxels
-                                 x right-hand sides, CG above.  Both stop at cg_rtol; cg_maxit bounds
-                                 their iterations */
+                                 (whatever the number of right-hand sides, which share every launch), CG
+                                 above.  Both stop at cg_rtol; cg_maxit bounds their iterations */
     int32_t z0_graphs;        /* != 0: the Chebyshev passes of a solve (whose arguments depend only on the
                                  pass index) are captured once per batch shape as HIP graphs and replayed
                                  on `stream` in later steps; 0: launched one by one */

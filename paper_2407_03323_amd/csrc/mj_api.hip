@@ -432,8 +432,10 @@ void mj_solver::create(const mj_config &c)
 
     // the Z_0 solve: Chebyshev passes cost one launch each against four per CG iteration, which
     // decides on small grids; on large ones CG's fewer iterations win (104^3: 12.9 CG iterations,
-    // 1.02 ms, against 24 passes, 1.16 ms; 32^3: 0.48 against 0.20 ms)
-    z0_method = c.z0_solver == 1 ? 1 : c.z0_solver == 2 ? 0 : ((long)nrhs * M <= kChebMaxUnknowns ? 0 : 1);
+    // 1.02 ms, against 24 passes, 1.12 ms; 32^3: 0.48 against 0.19 ms).  A batch shares its
+    // launches, so the size that decides is the grid's (16 right-hand sides at 64^3: 26 passes,
+    // 5.98-6.07 ms, against 20 CG iterations, 6.23 ms)
+    z0_method = c.z0_solver == 1 ? 1 : c.z0_solver == 2 ? 0 : (M <= kChebMaxUnknowns ? 0 : 1);
     MJ_CHECK(hipGetDevice(&dev));
     if (use_graphs) MJ_CHECK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
     (void)scratch_ptr(dev);   // this device's staging array (mj_kernel_values_noalloc)
