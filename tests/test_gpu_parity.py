@@ -369,6 +369,33 @@ def test_excitation_forms_match_oracle(torch_cuda, prism):
         assert e_all <= 1e-8
 
 
+def test_batched_full_size_matches_single_marches(torch_cuda):
+    """The 16-wave 64^3 workload as bench.py times it (ell = 112, three time levels, Chebyshev
+    solve in its build for launches that fill the chip, the planned oblique excitation), marched
+    130 steps so that the ring wraps: waves 0, 7 and 15 of the batch against their own
+    single-wave marches, every 26th step, to the solve tolerance."""
+    torch = torch_cuda
+    p = wl.config("C3")
+    n, every = 130, 26
+    say("batched 64^3, 16 waves, %d steps" % n)
+    s = make_solver(p)
+    assert s.ell == 112 and s.info()["z0_solver"] == 0
+    J = torch.zeros((n // every, 16, 3, p.W, p.V, p.U), dtype=torch.float64, device="cuda")
+    s.run(n, J, j_every=every)
+    torch.cuda.synchronize()
+    s.close()
+    for i in (0, 7, 15):
+        p1 = wl.Problem("single", p.U, p.V, p.W, p.eps, [p.waves[i]], n, fir=p.fir)
+        s1 = make_solver(p1)
+        J1 = torch.zeros((n // every, 1, 3, p.W, p.V, p.U), dtype=torch.float64, device="cuda")
+        s1.run(n, J1, j_every=every)
+        torch.cuda.synchronize()
+        s1.close()
+        err = float((J[:, i] - J1[:, 0]).norm() / J1[:, 0].norm())
+        say("  wave %d: rel L2 against its single march %.3e" % (i, err))
+        assert float(J1.norm()) > 0 and err <= 1e-11
+
+
 def test_batched_rhs_with_a_zero_column(torch_cuda):
     """A batch whose first right-hand side is identically zero: its Z_0 solve ends at the
     initial test in every step while the second one iterates, so the batched iterations run
