@@ -144,6 +144,7 @@ struct ChebArg {
     double inv_theta;        // d_0 = M^-1 r_0 / theta
     int want_norm;           // the pass writes partial sums of |r|^2 and the check follows it
     int passes;              // passes done when this one ends (recorded in the status)
+    int rhs0, nr;            // the right-hand sides rhs0 .. rhs0 + nr - 1 only (nr = 0: all of them)
 };
 // r_0 = rhs - A y0, e_0 = s M^-1 r_0 / theta; reduces |r_0|^2 and |b|^2 into the status
 void launch_cheb_init(const ChebArg &a, hipStream_t st);

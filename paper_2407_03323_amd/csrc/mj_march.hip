@@ -1124,7 +1124,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? 
 {
     const CgArg &g = a.cg;
     const CgBlock cb = cg_block();
-    const int r = cb.r;
+    const int r = cb.r + a.rhs0;
     const long M = g.M, base = (long)r * 3 * M;
     const long i = cb.bx * (long)blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};   // rr, bb
@@ -1160,7 +1160,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? 
 {
     const CgArg &g = a.cg;
     const CgBlock cb = cg_block();
-    const int r = cb.r;
+    const int r = cb.r + a.rhs0;
     const long M = g.M, base = (long)r * 3 * M;
     const long i = cb.bx * (long)blockDim.x + threadIdx.x;
     double v[1] = {0.0};
@@ -1192,7 +1192,7 @@ __global__ void __launch_bounds__(1024) k_cheb_reduce(ChebArg a)
 {
     __shared__ double sm[16];
     const CgArg &g = a.cg;
-    const int r = blockIdx.x, nb = g.nblk;
+    const int r = blockIdx.x + a.rhs0, nb = g.nblk;
     const double *pr = g.part + (size_t)r * 3 * nb;
     double acc[NV];
 #pragma unroll
@@ -1244,23 +1244,27 @@ void launch_fill_trial(const double *schi, long M, int nrhs, double *rhs, double
 
 void launch_cheb_init(const ChebArg &a, hipStream_t st)
 {
-    if ((long)a.cg.nblk * a.cg.nrhs >= kChebOccBlocks)
-        hipLaunchKernelGGL(k_cheb_init<true>, dim3(a.cg.nblk, a.cg.nrhs), dim3(256), 0, st, a);
+    const int nr = a.nr > 0 ? a.nr : a.cg.nrhs;
+    if (a.rhs0 < 0 || a.rhs0 + nr > a.cg.nrhs) throw ArgError("Chebyshev launch: right-hand sides out of range");
+    if ((long)a.cg.nblk * nr >= kChebOccBlocks)
+        hipLaunchKernelGGL(k_cheb_init<true>, dim3(a.cg.nblk, nr), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_cheb_init<false>, dim3(a.cg.nblk, a.cg.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_cheb_init<false>, dim3(a.cg.nblk, nr), dim3(256), 0, st, a);
     MJ_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_cheb_reduce<2>, dim3(a.cg.nrhs), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_cheb_reduce<2>, dim3(nr), dim3(1024), 0, st, a);
     MJ_CHECK(hipGetLastError());
 }
 void launch_cheb_pass(const ChebArg &a, hipStream_t st)
 {
-    if ((long)a.cg.nblk * a.cg.nrhs >= kChebOccBlocks)
-        hipLaunchKernelGGL(k_cheb_pass<true>, dim3(a.cg.nblk, a.cg.nrhs), dim3(256), 0, st, a);
+    const int nr = a.nr > 0 ? a.nr : a.cg.nrhs;
+    if (a.rhs0 < 0 || a.rhs0 + nr > a.cg.nrhs) throw ArgError("Chebyshev launch: right-hand sides out of range");
+    if ((long)a.cg.nblk * nr >= kChebOccBlocks)
+        hipLaunchKernelGGL(k_cheb_pass<true>, dim3(a.cg.nblk, nr), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_cheb_pass<false>, dim3(a.cg.nblk, a.cg.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_cheb_pass<false>, dim3(a.cg.nblk, nr), dim3(256), 0, st, a);
     MJ_CHECK(hipGetLastError());
     if (a.want_norm) {
-        hipLaunchKernelGGL(k_cheb_reduce<1>, dim3(a.cg.nrhs), dim3(1024), 0, st, a);
+        hipLaunchKernelGGL(k_cheb_reduce<1>, dim3(nr), dim3(1024), 0, st, a);
         MJ_CHECK(hipGetLastError());
     }
 }
