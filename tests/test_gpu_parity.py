@@ -396,6 +396,41 @@ def test_batched_full_size_matches_single_marches(torch_cuda):
         assert float(J1.norm()) > 0 and err <= 1e-11
 
 
+def test_chebyshev_batch_in_groups(torch_cuda):
+    """A batch whose Chebyshev solve runs in two groups (22 waves at 48^3: the solve vectors of
+    21 fit the group budget), on the 48^3 workload's eps: launched one by one and replayed from
+    captured graphs (one capture per group and batch shape), bit for bit; and the first wave
+    of each group against its own single-wave march, to the solve tolerance."""
+    torch = torch_cuda
+    p = wl.config("C4")
+    U, n = p.U, 30
+    waves = [wl.gaussian_wave(U, U, U, k, q, 4.0) for k, q in wl.random_directions(22, 7)]
+    prob = wl.Problem("groups", U, U, U, p.eps, waves, n, fir=p.fir)
+    say("Chebyshev in groups, 48^3, 22 waves")
+    out = []
+    for graphs in (0, 1):
+        s = make_solver(prob, z0_graphs=graphs)
+        assert s.info()["z0_solver"] == 0
+        J = torch.zeros((n // 10, 22, 3, U, U, U), dtype=torch.float64, device="cuda")
+        s.run(n, J, j_every=10)
+        torch.cuda.synchronize()
+        st = s.stats()
+        say("  graphs %d: %.2f passes per solve, residual %.2e" % (graphs, st["cg_iters"], st["cg_res_max"]))
+        assert st["cg_res_max"] <= 1e-13
+        out.append(J)
+        s.close()
+    assert torch.equal(out[0], out[1])
+    for i in (0, 21):
+        s1 = make_solver(wl.Problem("single", U, U, U, p.eps, [waves[i]], n, fir=p.fir))
+        J1 = torch.zeros((n // 10, 1, 3, U, U, U), dtype=torch.float64, device="cuda")
+        s1.run(n, J1, j_every=10)
+        torch.cuda.synchronize()
+        s1.close()
+        err = float((out[0][:, i] - J1[:, 0]).norm() / J1[:, 0].norm())
+        say("  wave %d: rel L2 against its single march %.3e" % (i, err))
+        assert float(J1.norm()) > 0 and err <= 1e-11
+
+
 def test_batched_rhs_with_a_zero_column(torch_cuda):
     """A batch whose first right-hand side is identically zero: its Z_0 solve ends at the
     initial test in every step while the second one iterates, so the batched iterations run
